@@ -1,0 +1,543 @@
+"""FP64 CPU oracle of the entropic Fourier method (EFM) collision operator.
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU-baseline
+leg of bench.py may import this module.  It shares no code with the HIP
+library: every table here is computed from the defining integrals by
+quadrature (the library uses closed forms), every transform is a library FFT
+or an explicit exponential sum, and the collision term is the plain double
+sum of the paper.
+
+What it computes (citations are to the paper, arXiv 1704.07369):
+
+* grid X and mode set K (section 1.1, eq. X; section 1.2, eq. K), the DFT pair
+  (section 2, eq. DFT) and the trigonometric basis E_k(v) = exp(i pi k.v / T);
+* the modified Jackson filter (section 3.2.2, eq. JacksonFilter2) and its
+  tensor product;
+* the low-rank kernel modes of the fast algorithm (section 4.1, eq. fastAlg,
+  eq. spherical_hatB, eq. fast_hatB, eq. discrete_hatB) -- in 2D literally,
+  in 3D by the same polar decomposition carried one dimension up;
+* the entropic collision term in Fourier space (section 3.2.2, eq. Qsk), by
+  the O(T n^2) double sum (C code in csrc/efm_direct.c), and back on the grid
+  (eq. Qsr);
+* the same quantity evaluated point by point through the factorised fast
+  algorithm with explicit exponential sums (section 3.1.1, eq. fastFGM, with
+  the collocation evaluation of eq. FGM_Qcv) -- for large grids;
+* the DVM coefficients A^sigma (section 3.2, eq. A_simplified with the
+  filtered kernel, eq. tildetildeA) and the DVM form of Q (eq. Qsr), brute
+  force on tiny grids;
+* diagnostics: mass, entropy (section 4.2, eta), positivity error epsilon,
+  the discrete H-functional of Theorem 1;
+* forward Euler and the SSP-RK3 step (section 4.1), BKW closed forms.
+
+Readings of the paper (all fixed by reproducing Table 2 to every printed digit,
+or stated where the paper is silent) are documented in the design doc; in short:
+the even-N filter is eq. JacksonFilter2 evaluated with n = N/2; the 2D nodes
+are theta_t = t*pi/(2M), t = 0..2M-1; the 3D nodes are a hemisphere product
+rule (Gauss-Legendre in cos(theta) folded onto [0,1], uniform azimuth).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_efm_direct.so")
+_lib = None
+
+KIND_MAXWELL = "maxwell"          # B = C_d |g|^0
+KIND_HARD_SPHERE = "hard_sphere"  # B = C_d |g|^1
+
+# Section 4.2: B(g, w) = 1/(2 pi) in 2D and 1/(4 pi) in 3D for Maxwell
+# molecules; the hard-sphere kernel keeps the same constant times |g|.
+C_D = {2: 1.0 / (2.0 * math.pi), 3: 1.0 / (4.0 * math.pi)}
+
+
+def default_box(R: float) -> float:
+    """Smallest half-width with T >= (3 sqrt 2 + 1) R / 4 (section 1.2)."""
+    return (3.0 * math.sqrt(2.0) + 1.0) * R / 4.0
+
+
+# ----------------------------------------------------------------------------
+# Grid, modes, DFT
+# ----------------------------------------------------------------------------
+
+def modes_1d(N: int) -> np.ndarray:
+    """Mode values in FFT index order: 0..ceil(N/2)-1, -floor(N/2)..-1."""
+    return np.fft.fftfreq(N, d=1.0 / N).round().astype(np.int64)
+
+
+def mode_grid(N: int, d: int):
+    k = modes_1d(N)
+    return [x.ravel() for x in np.meshgrid(*([k] * d), indexing="ij")]
+
+
+def grid_points(N: int, d: int, L: float):
+    v = -L + (2.0 * L / N) * np.arange(N)
+    return [x.ravel() for x in np.meshgrid(*([v] * d), indexing="ij")]
+
+
+def E(k_list, v_list, L):
+    """E_k(v) = exp(i pi k.v / L) for all pairs (rows: points v, cols: modes k)."""
+    ph = np.zeros((len(v_list[0]), len(k_list[0])))
+    for kd, vd in zip(k_list, v_list):
+        ph += np.outer(vd, kd)
+    return np.exp(1j * math.pi / L * ph)
+
+
+def dft(F: np.ndarray, L: float) -> np.ndarray:
+    """Fh_k = N^-d sum_p F_p E_{-k}(p) (section 2, eq. DFT) on the grid
+    v_j = -L + j h.  Uses a library FFT as the summation step; the left-edge
+    offset of the grid contributes the explicit phase exp(i pi sum k)."""
+    d = F.ndim
+    N = F.shape[0]
+    ks = np.meshgrid(*([modes_1d(N)] * d), indexing="ij")
+    phase = np.exp(1j * math.pi * sum(ks))
+    return phase * np.fft.fftn(F) / N ** d
+
+
+def idft(Fh: np.ndarray, L: float) -> np.ndarray:
+    """F_p = sum_k Fh_k E_k(p) (section 2, eq. DFT)."""
+    d = Fh.ndim
+    N = Fh.shape[0]
+    ks = np.meshgrid(*([modes_1d(N)] * d), indexing="ij")
+    phase = np.exp(-1j * math.pi * sum(ks))
+    return np.fft.ifftn(phase * Fh) * N ** d
+
+
+# ----------------------------------------------------------------------------
+# Modified Jackson filter (section 3.2.2, eq. JacksonFilter2)
+# ----------------------------------------------------------------------------
+
+def jackson_n(N: int) -> int:
+    """The n of eq. JacksonFilter2: (N-1)/2 for odd N (the paper's N = 2n+1);
+    for even N the reading that reproduces Table 2 is n = N/2, so that the
+    mode -N/2 gets sigma = 0 (section 4.1, even-N remark)."""
+    return (N - 1) // 2 if N % 2 else N // 2
+
+
+def jackson_sigma(beta, n: int):
+    b = np.abs(np.asarray(beta, dtype=np.float64))
+    a = math.pi / (n + 1)
+    s = ((n + 1 - b) * np.cos(a * b) + np.sin(a * b) / math.tan(a)) / (n + 1)
+    return np.where(b <= n, s, 0.0)
+
+
+def sigma_1d(N: int) -> np.ndarray:
+    return jackson_sigma(modes_1d(N), jackson_n(N))
+
+
+def sigma_nd(N: int, d: int) -> np.ndarray:
+    s = sigma_1d(N)
+    out = s
+    for _ in range(d - 1):
+        out = np.multiply.outer(out, s)
+    return out.ravel()
+
+
+# ----------------------------------------------------------------------------
+# Quadrature rules (library primitives: numpy's Gauss-Legendre nodes)
+# ----------------------------------------------------------------------------
+
+def gauss_legendre(n: int, a: float, b: float):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (b - a) * x + 0.5 * (b + a), 0.5 * (b - a) * w
+
+
+def directions_2d(M: int):
+    """2M samples theta_t = t pi/(2M), t = 0..2M-1 on [0, pi): M samples in
+    [0, pi/2) (section 4.2, Table 2 convention) plus their partners shifted by
+    pi/2.  Returns (e_t, e_t^perp, weights pi/(2M)) -- eq. discrete_hatB."""
+    th = np.arange(2 * M) * math.pi / (2 * M)
+    e = np.stack([np.cos(th), np.sin(th)], axis=1)
+    ep = np.stack([np.cos(th + math.pi / 2), np.sin(th + math.pi / 2)], axis=1)
+    w = np.full(2 * M, math.pi / (2 * M))
+    return e, ep, w
+
+
+def hemisphere_split(M: int):
+    """M = M_mu * M_phi with M_mu the largest divisor of M not above sqrt(M/2)."""
+    best = 1
+    for a in range(1, M + 1):
+        if M % a == 0 and a * a <= M / 2.0:
+            best = a
+    return best, M // best
+
+
+def directions_3d(M: int):
+    """Hemisphere rule with positive weights summing to 2 pi: Gauss-Legendre
+    in mu = cos(theta) on [-1,1] with 2 M_mu nodes, the positive half kept
+    (integrands are even in e), times the uniform rule in azimuth."""
+    mm, mp = hemisphere_split(M)
+    x, w = np.polynomial.legendre.leggauss(2 * mm)
+    keep = x > 0
+    mu, wm = x[keep], w[keep]
+    dirs, wts = [], []
+    for i in range(mm):
+        st = math.sqrt(max(0.0, 1.0 - mu[i] ** 2))
+        for j in range(mp):
+            ph = 2.0 * math.pi * j / mp
+            dirs.append((st * math.cos(ph), st * math.sin(ph), mu[i]))
+            wts.append(wm[i] * 2.0 * math.pi / mp)
+    return np.array(dirs), np.array(wts)
+
+
+# ----------------------------------------------------------------------------
+# Kernel-mode factors by quadrature of their defining integrals
+# ----------------------------------------------------------------------------
+
+def _gl_nodes_for(omega_max: float, R: float):
+    n = int(math.ceil(0.75 * omega_max * R)) + 48
+    return gauss_legendre(n, -R, R)
+
+
+def psi_line(s: np.ndarray, R: float, power: int) -> np.ndarray:
+    """int_{-R}^{R} |rho|^power cos(rho s) d rho for each s (the imaginary part
+    of int E_l(rho e) d rho vanishes by symmetry).  power=0 is psi_R of
+    section 4.1 (2D); power=1 is its 3D analogue (Jacobian rho^{d-1} over
+    the delta-function factor rho)."""
+    smax = float(np.max(np.abs(s))) if s.size else 0.0
+    # the integrand is even in rho (and has a kink at 0 when power = 1), so
+    # integrate over [0, R] and double
+    rho, w = _gl_nodes_for(smax, R)
+    rho, w = 0.5 * (rho + R), 0.5 * w
+    wt = 2.0 * w * rho ** power
+    out = np.empty(s.shape)
+    flat_s, flat_o = s.ravel(), out.ravel()
+    for c0 in range(0, flat_s.size, 4096):
+        blk = flat_s[c0:c0 + 4096]
+        flat_o[c0:c0 + 4096] = np.cos(np.outer(blk, rho)) @ wt
+    return out
+
+
+def disk_integral(q: np.ndarray, R: float) -> np.ndarray:
+    """Phi = 2 int_{|x|<=R, x in a plane} cos(q x_1) dx, the circle integral of
+    psi_3 over the great circle orthogonal to e (the double cover of the disk
+    gives the factor 2).  With x_1 = R cos(theta):
+    Phi = 4 R^2 int_0^pi cos(q R cos theta) sin^2 theta d theta, evaluated by
+    the periodic trapezoid rule (the integrand is smooth, even, 2pi-periodic)."""
+    qmax = float(np.max(np.abs(q))) if q.size else 0.0
+    K = 2 * int(math.ceil(qmax * R)) + 96
+    th = 2.0 * math.pi * np.arange(K) / K
+    ct, s2 = np.cos(th), np.sin(th) ** 2
+    out = np.empty(q.shape)
+    flat_q, flat_o = q.ravel(), out.ravel()
+    for c0 in range(0, flat_q.size, 2048):
+        blk = flat_q[c0:c0 + 2048]
+        g = np.cos(np.outer(blk * R, ct)) @ s2
+        flat_o[c0:c0 + 2048] = 4.0 * R * R * 0.5 * (2.0 * math.pi / K) * g
+    return out
+
+
+@dataclass
+class LowRank:
+    """B_fast(l, m) = sum_t c[t] U[t, l] V[t, m] over the modes of one grid."""
+    c: np.ndarray       # (T,)
+    U: np.ndarray       # (T, n)
+    V: np.ndarray       # (T, n)
+
+    def matrix(self) -> np.ndarray:
+        return np.einsum("t,tl,tm->lm", self.c, self.U, self.V)
+
+    def diagonal(self) -> np.ndarray:
+        return np.einsum("t,tm,tm->m", self.c, self.U, self.V)
+
+
+def lowrank_2d_maxwell(N: int, L: float, R: float, M: int) -> LowRank:
+    """Section 4.1, eq. discrete_hatB with 2M samples on [0, pi), times the
+    Maxwell constant Btilde = 2^{d-1} C_2 = 1/pi (section 1, eq. Carleman)."""
+    kx, ky = mode_grid(N, 2)
+    e, ep, w = directions_2d(M)
+    bt = 2.0 * C_D[2]
+    T = len(w)
+    U = np.empty((T, kx.size)); V = np.empty((T, kx.size))
+    for t in range(T):
+        U[t] = psi_line(math.pi / L * (kx * e[t, 0] + ky * e[t, 1]), R, 0)
+        V[t] = psi_line(math.pi / L * (kx * ep[t, 0] + ky * ep[t, 1]), R, 0)
+    return LowRank(bt * w, U, V)
+
+
+def lowrank_3d_hard_sphere(N: int, L: float, R: float, M: int) -> LowRank:
+    """3D analogue of section 4.1: with y = rho e, z = rho* e* (rho in [-R,R],
+    a double cover), B_hat = (Bt/4) int int delta(e.e*) psi_3(l,e) psi_3(m,e*)
+    de de*; integrating e* over the great circle orthogonal to e gives
+    B_hat = (Bt/2) int_{hemisphere} psi_3(l,e) Phi(m,e) de, discretised by the
+    hemisphere rule.  Bt = 2^{d-1} C_3 |g|^{gamma+2-d} = 1/pi for gamma = 1."""
+    kx, ky, kz = mode_grid(N, 3)
+    dirs, w = directions_3d(M)
+    bt = 4.0 * C_D[3]
+    T = len(w)
+    U = np.empty((T, kx.size)); V = np.empty((T, kx.size))
+    kap2 = (kx * kx + ky * ky + kz * kz) * (math.pi / L) ** 2
+    for t in range(T):
+        s = math.pi / L * (kx * dirs[t, 0] + ky * dirs[t, 1] + kz * dirs[t, 2])
+        U[t] = psi_line(s, R, 1)
+        qperp = np.sqrt(np.maximum(kap2 - s * s, 0.0))
+        V[t] = disk_integral(qperp, R)
+    return LowRank(0.5 * bt * w, U, V)
+
+
+# ----------------------------------------------------------------------------
+# Plan
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Plan:
+    N: int
+    d: int
+    L: float
+    R: float
+    M: int
+    kind: str
+    sigma: np.ndarray
+    lr: LowRank
+
+    @property
+    def n(self) -> int:
+        return self.N ** self.d
+
+    @property
+    def h(self) -> float:
+        return 2.0 * self.L / self.N
+
+
+def make_plan(N: int, d: int, L: float, M: int, kind: str | None = None,
+              R: float = 6.0, filtered: bool = True) -> Plan:
+    if kind is None:
+        kind = KIND_MAXWELL if d == 2 else KIND_HARD_SPHERE
+    if d == 2 and kind == KIND_MAXWELL:
+        lr = lowrank_2d_maxwell(N, L, R, M)
+    elif d == 3 and kind == KIND_HARD_SPHERE:
+        lr = lowrank_3d_hard_sphere(N, L, R, M)
+    else:
+        raise NotImplementedError(f"oracle kernel {kind} in {d}D")
+    sig = sigma_nd(N, d) if filtered else np.ones(N ** d)
+    return Plan(N, d, L, R, M, kind, sig, lr)
+
+
+# ----------------------------------------------------------------------------
+# Collision term: direct double sum (section 3.2.2, eq. Qsk and eq. Qsr)
+# ----------------------------------------------------------------------------
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _lib.efm_direct_sum.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [dp] * 10
+        _lib.efm_direct_sum_some.argtypes = ([ctypes.c_int, ctypes.c_int, ctypes.c_int] + [dp] * 7
+                                             + [ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)] + [dp] * 4)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class Collision:
+    Q: np.ndarray
+    Qplus: np.ndarray
+    Qminus: np.ndarray
+    imag_max: float
+    Qhat: np.ndarray
+
+
+def collide_modes(plan: Plan, F: np.ndarray) -> Collision:
+    """Q^sigma on the grid from the plain double sum over modes."""
+    lib = _load()
+    Fh = dft(F, plan.L).ravel()
+    Fr = np.ascontiguousarray(Fh.real); Fi = np.ascontiguousarray(Fh.imag)
+    U = np.ascontiguousarray(plan.lr.U.T); V = np.ascontiguousarray(plan.lr.V.T)
+    c = np.ascontiguousarray(plan.lr.c); sig = np.ascontiguousarray(plan.sigma)
+    n = plan.n
+    Gr, Gi, Lr, Li = (np.empty(n) for _ in range(4))
+    lib.efm_direct_sum(plan.d, plan.N, len(c), _p(c), _p(U), _p(V), _p(sig),
+                       _p(Fr), _p(Fi), _p(Gr), _p(Gi), _p(Lr), _p(Li))
+    shp = (plan.N,) * plan.d
+    G = (Gr + 1j * Gi).reshape(shp)
+    Lh = (Lr + 1j * Li).reshape(shp)
+    qp = idft(G, plan.L); qm = idft(Lh, plan.L)
+    q = qp - qm
+    imag = float(max(np.abs(qp.imag).max(), np.abs(qm.imag).max()))
+    return Collision(q.real, qp.real, qm.real, imag, G - Lh)
+
+
+def collide_modes_some(plan: Plan, F: np.ndarray, ks: np.ndarray):
+    """Gain and loss Fourier coefficients at a subset of output modes."""
+    lib = _load()
+    Fh = dft(F, plan.L).ravel()
+    Fr = np.ascontiguousarray(Fh.real); Fi = np.ascontiguousarray(Fh.imag)
+    U = np.ascontiguousarray(plan.lr.U.T); V = np.ascontiguousarray(plan.lr.V.T)
+    c = np.ascontiguousarray(plan.lr.c); sig = np.ascontiguousarray(plan.sigma)
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    Gr, Gi, Lr, Li = (np.empty(ks.size) for _ in range(4))
+    lib.efm_direct_sum_some(plan.d, plan.N, len(c), _p(c), _p(U), _p(V), _p(sig),
+                            _p(Fr), _p(Fi), ctypes.c_int64(ks.size),
+                            ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            _p(Gr), _p(Gi), _p(Lr), _p(Li))
+    return Gr + 1j * Gi, Lr + 1j * Li
+
+
+def collision_frequency(plan: Plan, F: np.ndarray) -> np.ndarray:
+    """l_r with Q-_r = F_r l_r: l_r = sum_m B^s(m,m) Fh_m E_m(r) (the loss
+    identity of section 3.1.2, with the filtered kernel)."""
+    Fh = dft(F, plan.L).ravel()
+    D = plan.sigma * plan.sigma * plan.lr.diagonal()
+    return idft((D * Fh).reshape(F.shape), plan.L).real
+
+
+# ----------------------------------------------------------------------------
+# Point-by-point evaluation through the factorised fast algorithm
+# (section 3.1.1, eq. fastFGM with the collocation evaluation eq. FGM_Qcv;
+#  filtered as in section 4.1).  Explicit exponential sums, no FFT.
+# ----------------------------------------------------------------------------
+
+def collide_points(plan: Plan, F: np.ndarray, idx: np.ndarray):
+    """Q, Q+ and Q- at the flat grid indices idx.
+
+    a_t(r) = sum_k sig_k U_t(k) Fh_k E_k(r),  b_t(r) = sum_k sig_k V_t(k) Fh_k E_k(r)
+    Q+(r)  = sum_t c_t a_t(r) b_t(r)
+    l(r)   = sum_k sig_k^2 (sum_t c_t U_t(k) V_t(k)) Fh_k E_k(r),  Q-(r) = F_r l(r)
+    """
+    Fh = dft(F, plan.L).ravel()
+    kl = mode_grid(plan.N, plan.d)
+    vl = [v[idx] for v in grid_points(plan.N, plan.d, plan.L)]
+    Er = E(kl, vl, plan.L)                       # (P, n)
+    sF = plan.sigma * Fh
+    A = Er @ (plan.lr.U * sF).T                  # (P, T)
+    B = Er @ (plan.lr.V * sF).T
+    qp = (A * B) @ plan.lr.c
+    ell = Er @ (plan.sigma * plan.sigma * plan.lr.diagonal() * Fh)
+    qm = F.ravel()[idx] * ell
+    return (qp - qm).real, qp.real, qm.real, float(np.abs(qp.imag).max() + np.abs(ell.imag).max())
+
+
+# ----------------------------------------------------------------------------
+# DVM form on tiny grids (section 3.2, eq. A_simplified, eq. tildetildeA,
+# eq. Qsr)
+# ----------------------------------------------------------------------------
+
+def kernel_matrix(plan: Plan, symmetrise: bool = True) -> np.ndarray:
+    B = plan.lr.matrix()
+    if symmetrise:
+        B = 0.5 * (B + B.T)
+    return plan.sigma[:, None] * B * plan.sigma[None, :]
+
+
+def G_sigma(plan: Plan, symmetrise: bool = True) -> np.ndarray:
+    """G(a, b) = sum_{i,j in K} B^s(i,j) E_{-i}(h a) E_{-j}(h b) on grid index
+    differences a, b (section 3.2.1, eq. G and section 3.2.2, eq. tildeG without
+    the 1/N^{2d} factor; see the normalisation reading in the design doc)."""
+    kl = mode_grid(plan.N, plan.d)
+    h = plan.h
+    idx = np.arange(plan.N)            # index differences a in [0, N), offset a*h
+    al = [x.ravel() * h for x in np.meshgrid(*([idx] * plan.d), indexing="ij")]
+    Em = np.conj(E(kl, al, plan.L))                   # E_{-i}(a h): (points, modes)
+    return Em @ kernel_matrix(plan, symmetrise) @ Em.T
+
+
+def dvm_tensor(plan: Plan, symmetrise: bool = True) -> np.ndarray:
+    """A[r, s, p, q] = N^{-2d} 1_N(r+s-p-q) G(p-s, q-s)."""
+    n, N, d = plan.n, plan.N, plan.d
+    G = G_sigma(plan, symmetrise)
+    coords = np.stack(np.unravel_index(np.arange(n), (N,) * d), axis=1)
+
+    def flat(c):
+        return np.ravel_multi_index(tuple((c % N).T), (N,) * d)
+
+    A = np.zeros((n, n, n, n))
+    G = G.real
+    allp = np.arange(n)
+    for r in range(n):
+        for s in range(n):
+            q = flat(coords[r] + coords[s] - coords)            # all p at once
+            A[r, s, allp, q] = G[flat(coords - coords[s]), flat(coords[q] - coords[s])]
+    return A / n ** 2
+
+
+def collide_dvm(A: np.ndarray, F: np.ndarray) -> np.ndarray:
+    f = F.ravel()
+    gain = np.einsum("rspq,p,q->r", A, f, f)
+    loss = np.einsum("rspq,r,s->r", A, f, f)
+    return (gain - loss).reshape(F.shape)
+
+
+# ----------------------------------------------------------------------------
+# Diagnostics (Theorem 1; section 4.2: positivity error epsilon, entropy eta)
+# ----------------------------------------------------------------------------
+
+def monitors(plan: Plan, F: np.ndarray, Q: np.ndarray) -> dict:
+    h = plan.h ** plan.d
+    f = F.ravel(); q = Q.ravel()
+    pos = f > 0
+    V = grid_points(plan.N, plan.d, plan.L)
+    return {
+        "mass": h * f.sum(),
+        "sumQ": q.sum(),
+        "sumabsQ": np.abs(q).sum(),
+        "entropy_prod": h * np.sum(q[pos] * np.log(f[pos])),
+        "eta": h * np.sum(f[pos] * np.log(f[pos])),
+        "minF": f.min(),
+        "n_nonpos": int((~pos).sum()),
+        "eps_pos": (np.abs(f).sum() - f.sum()) / np.abs(f).sum(),
+        "momentum": [h * np.sum(q * v) for v in V],
+        "energy": h * np.sum(q * sum(v * v for v in V)),
+    }
+
+
+def fe_step(L_op, F, dt):
+    return F + dt * L_op(F)
+
+
+def ssprk3_step(L_op, F, dt):
+    """Third-order SSP Runge-Kutta (section 4.1), Shu-Osher form."""
+    u1 = F + dt * L_op(F)
+    u2 = 0.75 * F + 0.25 * (u1 + dt * L_op(u1))
+    return F / 3.0 + 2.0 / 3.0 * (u2 + dt * L_op(u2))
+
+
+# ----------------------------------------------------------------------------
+# Closed forms used as pins
+# ----------------------------------------------------------------------------
+
+def bkw_S(d: int, t: float) -> float:
+    return 1.0 - math.exp(-t / 8.0) / 2.0 if d == 2 else 1.0 - 2.0 * math.exp(-t / 6.0) / 5.0
+
+
+def bkw_f(d: int, t: float, v2: np.ndarray) -> np.ndarray:
+    """BKW solution (section 4.2, Example 1 in 2D, Example 4 in 3D)."""
+    S = bkw_S(d, t)
+    if d == 2:
+        return (1 / (2 * math.pi * S) * np.exp(-v2 / (2 * S))
+                * ((2 * S - 1) / S + (1 - S) / (2 * S * S) * v2))
+    return ((2 * math.pi * S) ** -1.5 * np.exp(-v2 / (2 * S))
+            * ((5 * S - 3) / (2 * S) + (1 - S) / (2 * S * S) * v2))
+
+
+def bkw_dfdt(d: int, t: float, v2: np.ndarray) -> np.ndarray:
+    """d f / d t of the BKW solution = (df/dS)(dS/dt), differentiated by hand."""
+    S = bkw_S(d, t)
+    if d == 2:
+        dS = math.exp(-t / 8.0) / 16.0
+        g = np.exp(-v2 / (2 * S))
+        P = (2 * S - 1) / S + (1 - S) / (2 * S * S) * v2
+        dP = 1.0 / (S * S) + v2 * (-1.0 / (2 * S * S) - (1 - S) / S ** 3)
+        pref = 1 / (2 * math.pi * S)
+        dpref = -1 / (2 * math.pi * S * S)
+        dg = g * v2 / (2 * S * S)
+        return (dpref * g * P + pref * dg * P + pref * g * dP) * dS
+    dS = 2.0 * math.exp(-t / 6.0) / 30.0
+    g = np.exp(-v2 / (2 * S))
+    P = (5 * S - 3) / (2 * S) + (1 - S) / (2 * S * S) * v2
+    dP = 3.0 / (2 * S * S) + v2 * (-1.0 / (2 * S * S) - (1 - S) / S ** 3)
+    pref = (2 * math.pi * S) ** -1.5
+    dpref = -1.5 * (2 * math.pi) ** -1.5 * S ** -2.5
+    dg = g * v2 / (2 * S * S)
+    return (dpref * g * P + pref * dg * P + pref * g * dP) * dS
