@@ -1,0 +1,187 @@
+/*
+ * ec.h -- C ABI of the MI355X library for the entropic Fourier method (EFM)
+ * collision operator (Z. Cai, Y. Fan, L. Ying, "An entropic Fourier method for
+ * the Boltzmann equation", arXiv 1704.07369).
+ *
+ * The library evaluates, for many independent space-homogeneous cells, the
+ * discrete collision term
+ *
+ *     Q_r = sum_{l,m in K} (B^s(l,m) - B^s(m,m)) Fh_l Fh_m E_{l+m}(r),  r in X
+ *
+ * (section 3.2.2, eq. Qsk / eq. Qsr) with the filtered low-rank kernel modes of
+ * the fast algorithm (section 4.1, eq. fastAlg and its filtered form), by
+ * 2 M' + 2 FFTs per cell: one forward transform, M' inverse transforms of
+ * (alpha_t + i beta_t) Fh (the gain sum_t a_t b_t, section 3.3), and one
+ * inverse transform of the diagonal multiplier (the loss F_r l_r, section
+ * 3.1.2).
+ *
+ * Conventions (the input contract of section 3.3, eq. I_N):
+ *  - velocity box [-L, L]^d, N points per axis, h = 2L/N, v_j = -L + j h;
+ *  - a cell is N^d FP64 point samples F_r = f(v_r) >= 0, C order, last axis
+ *    fastest;
+ *  - all device pointers are owned by the caller; the library owns only its
+ *    plans, batches and their workspaces;
+ *  - every call returns 0 on success or a negative EC_ERR_* code; the message
+ *    of the last failure on the calling thread is ec_last_error().  Nothing
+ *    aborts, throws or exits across this boundary.  Asynchronous device
+ *    faults surface at the next call that synchronises.
+ *  - calls that take a hip stream (void*; NULL = the null stream) only
+ *    enqueue work on it: no host synchronisation, no allocation.
+ */
+#ifndef EC_H_
+#define EC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define EC_OK               0
+#define EC_ERR_ARG         -1   /* invalid argument (null, size, range)     */
+#define EC_ERR_DEVICE      -2   /* HIP runtime error                        */
+#define EC_ERR_OOM         -3   /* device or host allocation failed         */
+#define EC_ERR_UNSUPPORTED -4   /* valid but not implemented (N, d, kind)   */
+#define EC_ERR_DOMAIN      -5   /* numerical precondition violated          */
+
+/* ---- collision kernels -------------------------------------------------
+ * B(g, w) = C_d |g|^gamma with C_2 = 1/(2 pi), C_3 = 1/(4 pi) (section 4.2).
+ * In Carleman form (section 1, eq. Carleman)
+ *   Bt(y, z) = 2^{d-1} C_d (|y|^2 + |z|^2)^{(gamma + 2 - d)/2},
+ * which is constant (= 1/pi) -- hence separable in the fast algorithm --
+ * for Maxwell molecules in 2D (gamma = 0) and hard spheres in 3D (gamma = 1).
+ */
+#define EC_KERNEL_MAXWELL     0   /* gamma = 0                              */
+#define EC_KERNEL_HARD_SPHERE 1   /* gamma = 1                              */
+#define EC_KERNEL_VHS         2   /* general gamma (non-separable; reserved)*/
+
+typedef struct ec_kernel {
+  int kind;          /* EC_KERNEL_*                                          */
+  double gamma;      /* used by EC_KERNEL_VHS only                           */
+  double R;          /* truncation radius of the Carleman integrals (section
+                        1.2, eq. approximated_collision); R <= 0 selects the
+                        largest R allowed by T >= (3 sqrt 2 + 1) R / 4        */
+  int n_radial;      /* radial nodes of a non-separable kernel (reserved)    */
+} ec_kernel;
+
+/* ---- precision of the transforms --------------------------------------- */
+#define EC_FP64   0   /* transforms, products and sums in FP64              */
+#define EC_FP32   1   /* transforms and products in FP32, sum over terms,
+                         loss combine and reductions in FP64                */
+
+typedef struct ec_plan ec_plan;
+typedef struct ec_batch ec_batch;
+
+/*
+ * ec_setup_kernel -- build the FP64 tables of one (N, d, L, kernel, M) and
+ * upload them to the current HIP device.
+ *   N      points per axis; supported: d = 3: 8, 12, 16, 24, 32;
+ *          d = 2: 8, 12, 16, 24, 32.
+ *   d      2 or 3.
+ *   L      half-width of the velocity box (> 0).
+ *   M      number of products in the gain: d = 2: samples theta_t = t pi/(2M)
+ *          in [0, pi/2), each paired with theta_t + pi/2 (section 4.1, eq.
+ *          discrete_hatB; section 4.2, Table 2 convention); d = 3: directions
+ *          of a hemisphere product rule (Gauss-Legendre in cos(theta) times
+ *          uniform azimuth, positive weights summing to 2 pi).
+ * Precomputes (section 3.2.2, eq. JacksonFilter2; section 4.1):
+ *   sigma(k)  the modified Jackson filter, n = N/2 for even N (sigma(-N/2) = 0);
+ *   alpha_t(k) = N^-d w_t sigma(k) psi_t(k),  beta_t(k) = N^-d sigma(k) phi_t(k),
+ *   D(k) = N^-d sigma(k)^2 sum_t w_t psi_t(k) phi_t(k)  (the diagonal
+ *   B^s(k,k) of the same low-rank kernel, which gives exact mass conservation).
+ * The plan owns its device memory until ec_plan_destroy.
+ */
+int ec_setup_kernel(int N, int d, double L, const ec_kernel* kernel, int M,
+                    ec_plan** out);
+int ec_plan_destroy(ec_plan* plan);
+
+/* Number of gain products M' of the plan (= M for the separable kernels). */
+int ec_plan_terms(const ec_plan* plan, int* n_terms);
+
+/*
+ * ec_plan_tables -- host copy of the spectral multipliers, for inspection.
+ * gamma: [M'+1][N^d] complex numbers stored as (re, im) FP64 pairs, modes in
+ * FFT index order (index i holds the mode i for i < N/2, i - N otherwise),
+ * axes ordered (k0, k2, k1) -- first axis slowest, then the last axis, then
+ * the middle axis fastest (d = 2: (k1_is_absent) i.e. [k_last][k_first]).
+ * Entry t < M' is alpha_t + i beta_t; entry M' is D + 0 i.
+ * Host memory owned by the caller; size = 2 (M'+1) N^d doubles.
+ */
+int ec_plan_tables(const ec_plan* plan, double* gamma);
+
+/* Same tables without a device (host only; used by CPU tests). */
+int ec_host_tables(int N, int d, double L, const ec_kernel* kernel, int M,
+                   int* n_terms, double* gamma /* may be NULL to query */);
+
+/*
+ * ec_batch_create -- a packed batch of cells grouped by plan.
+ *   plans[g], counts[g]: group g holds counts[g] cells of plans[g] (the plans
+ *   must stay alive while the batch exists).
+ *   precision: EC_FP64 or EC_FP32.
+ * Layout of f and Q for every call on the batch: cells in group order, each
+ * cell N_g^d contiguous FP64 values starting at a 256-byte aligned element
+ * offset (ec_batch_offsets).  Workspaces for all later calls are allocated
+ * here; ec_collide and ec_step never allocate.
+ */
+int ec_batch_create(const ec_plan* const* plans, const int64_t* counts,
+                    int n_groups, int precision, ec_batch** out);
+int ec_batch_destroy(ec_batch* batch);
+/* n_cells; total FP64 elements of the packed array (including padding). */
+int ec_batch_size(const ec_batch* batch, int64_t* n_cells, int64_t* n_elems);
+/* offsets[c] = element offset of cell c (host array of n_cells). */
+int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
+/* Cells per pass of the slab/pencil pipeline (autotuned; 0 = default). */
+int ec_batch_set_chunk(ec_batch* batch, int group, int cells_per_pass);
+
+/*
+ * ec_collide -- Q = Q^s[F] for every cell of the batch (section 3.2.2, eq. Qsr
+ * evaluated by the fast algorithm of section 4.1).  f, Q: device arrays of
+ * ec_batch_size().n_elems FP64; f and Q must not alias.  Padding is ignored.
+ */
+int ec_collide(ec_batch* batch, const double* f, double* Q, void* hip_stream);
+
+/*
+ * ec_entropy_prod -- per cell, out[c] = h^d sum_{F_r > 0} Q_r ln F_r (the
+ * discrete H-functional of Theorem 1, eq. Htheorem; <= 0 in exact arithmetic
+ * for F >= 0) and, if n_nonpos != NULL, n_nonpos[c] = #{r : F_r <= 0}.
+ * Deterministic (fixed reduction order).  Device arrays.
+ */
+int ec_entropy_prod(ec_batch* batch, const double* f, const double* Q,
+                    double* out, int32_t* n_nonpos, void* hip_stream);
+
+/*
+ * ec_monitors -- per cell EC_NMON FP64 diagnostics of (f, Q), device array
+ * out[c * EC_NMON + i]: mass h^d sum F, sum Q, h^d sum_{F>0} Q ln F,
+ * eta = h^d sum_{F>0} F ln F (section 4.2), min F, the positivity error
+ * epsilon = (sum|F| - sum F)/sum|F| (section 4.2), sum |Q|.
+ */
+#define EC_NMON 7
+#define EC_MON_MASS      0
+#define EC_MON_SUMQ      1
+#define EC_MON_ENTPROD   2
+#define EC_MON_ETA       3
+#define EC_MON_MINF      4
+#define EC_MON_EPS       5
+#define EC_MON_SUMABSQ   6
+int ec_monitors(ec_batch* batch, const double* f, const double* Q, double* out,
+                void* hip_stream);
+
+/*
+ * ec_step -- n_steps forward-Euler steps F <- F + dt Q^s[F] of the EFM ODE
+ * (section 3.3, eq. modifiedIVP), in place on f, captured once into a HIP
+ * graph and replayed.  If monitors != NULL it receives, per step and cell,
+ * (mass, eta) of the state after the step: monitors[(s * n_cells + c) * 2 + i].
+ * Positivity is kept when dt max_r l_r <= 1 (proof of Theorem 1).
+ */
+int ec_step(ec_batch* batch, double* f, double dt, int n_steps,
+            double* monitors, void* hip_stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ec_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EC_H_ */

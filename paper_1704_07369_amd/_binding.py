@@ -1,0 +1,194 @@
+"""ctypes binding of libefm.so: the C-ABI functions under the same names.
+
+Argument marshalling only -- every step of the computation runs in the HIP
+library.  Device arrays may be passed as torch tensors (their data_ptr() is
+used; torch is only the allocator) or as integer device addresses.  Streams
+default to torch's current stream on the current device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libefm.so")
+
+EC_OK = 0
+EC_ERR_ARG, EC_ERR_DEVICE, EC_ERR_OOM, EC_ERR_UNSUPPORTED, EC_ERR_DOMAIN = -1, -2, -3, -4, -5
+EC_KERNEL_MAXWELL, EC_KERNEL_HARD_SPHERE, EC_KERNEL_VHS = 0, 1, 2
+EC_FP64, EC_FP32 = 0, 1
+EC_NMON = 7
+MON_NAMES = ["mass", "sumQ", "entropy_prod", "eta", "minF", "eps_pos", "sumabsQ"]
+
+_c_int, _c_double, _c_i64, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_void_p
+
+
+class EcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"EC error {code}: {msg}")
+        self.code = code
+
+
+class ec_kernel(ctypes.Structure):
+    _fields_ = [("kind", _c_int), ("gamma", _c_double), ("R", _c_double), ("n_radial", _c_int)]
+
+
+_SIGS = {
+    "ec_last_error": ([], ctypes.c_char_p),
+    "ec_setup_kernel": ([_c_int, _c_int, _c_double, ctypes.POINTER(ec_kernel), _c_int,
+                         ctypes.POINTER(_vp)], _c_int),
+    "ec_plan_destroy": ([_vp], _c_int),
+    "ec_plan_terms": ([_vp, ctypes.POINTER(_c_int)], _c_int),
+    "ec_plan_tables": ([_vp, ctypes.POINTER(_c_double)], _c_int),
+    "ec_host_tables": ([_c_int, _c_int, _c_double, ctypes.POINTER(ec_kernel), _c_int,
+                        ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)], _c_int),
+    "ec_batch_create": ([ctypes.POINTER(_vp), ctypes.POINTER(_c_i64), _c_int, _c_int,
+                         ctypes.POINTER(_vp)], _c_int),
+    "ec_batch_destroy": ([_vp], _c_int),
+    "ec_batch_size": ([_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i64)], _c_int),
+    "ec_batch_offsets": ([_vp, ctypes.POINTER(_c_i64)], _c_int),
+    "ec_batch_set_chunk": ([_vp, _c_int, _c_int], _c_int),
+    "ec_collide": ([_vp, _vp, _vp, _vp], _c_int),
+    "ec_entropy_prod": ([_vp, _vp, _vp, _vp, _vp, _vp], _c_int),
+    "ec_monitors": ([_vp, _vp, _vp, _vp, _vp], _c_int),
+    "ec_step": ([_vp, _vp, _c_double, _c_int, _vp, _vp], _c_int),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libefm.so; raise if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1704_07369_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS.keys())
+
+
+def _check(rc):
+    if rc != EC_OK:
+        raise EcError(rc, lib().ec_last_error().decode())
+    return rc
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    raise TypeError(f"cannot take a device address of {type(x)}")
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def make_kernel(kind=EC_KERNEL_HARD_SPHERE, gamma=1.0, R=6.0, n_radial=0):
+    return ec_kernel(kind, gamma, R, n_radial)
+
+
+# ---- same-name wrappers -----------------------------------------------------
+
+def ec_last_error():
+    return lib().ec_last_error().decode()
+
+
+def ec_setup_kernel(N, d, L, kernel, M):
+    h = _vp()
+    _check(lib().ec_setup_kernel(N, d, L, ctypes.byref(kernel), M, ctypes.byref(h)))
+    return h.value
+
+
+def ec_plan_destroy(plan):
+    return _check(lib().ec_plan_destroy(plan))
+
+
+def ec_plan_terms(plan):
+    t = _c_int()
+    _check(lib().ec_plan_terms(plan, ctypes.byref(t)))
+    return t.value
+
+
+def ec_plan_tables(plan, n_points):
+    J = ec_plan_terms(plan) + 1
+    out = np.empty(2 * J * n_points)
+    _check(lib().ec_plan_tables(plan, out.ctypes.data_as(ctypes.POINTER(_c_double))))
+    return (out[0::2] + 1j * out[1::2]).reshape(J, n_points)
+
+
+def ec_host_tables(N, d, L, kernel, M):
+    t = _c_int()
+    _check(lib().ec_host_tables(N, d, L, ctypes.byref(kernel), M, ctypes.byref(t), None))
+    n = N ** d
+    out = np.empty(2 * (t.value + 1) * n)
+    _check(lib().ec_host_tables(N, d, L, ctypes.byref(kernel), M, ctypes.byref(t),
+                                out.ctypes.data_as(ctypes.POINTER(_c_double))))
+    return (out[0::2] + 1j * out[1::2]).reshape(t.value + 1, n)
+
+
+def ec_batch_create(plans, counts, precision=EC_FP64):
+    n = len(plans)
+    pa = (_vp * n)(*plans)
+    ca = (_c_i64 * n)(*counts)
+    h = _vp()
+    _check(lib().ec_batch_create(pa, ca, n, precision, ctypes.byref(h)))
+    return h.value
+
+
+def ec_batch_destroy(batch):
+    return _check(lib().ec_batch_destroy(batch))
+
+
+def ec_batch_size(batch):
+    c, e = _c_i64(), _c_i64()
+    _check(lib().ec_batch_size(batch, ctypes.byref(c), ctypes.byref(e)))
+    return c.value, e.value
+
+
+def ec_batch_offsets(batch):
+    n, _ = ec_batch_size(batch)
+    out = np.empty(n, dtype=np.int64)
+    _check(lib().ec_batch_offsets(batch, out.ctypes.data_as(ctypes.POINTER(_c_i64))))
+    return out
+
+
+def ec_batch_set_chunk(batch, group, cells_per_pass):
+    return _check(lib().ec_batch_set_chunk(batch, group, cells_per_pass))
+
+
+def ec_collide(batch, f, Q, stream=None):
+    return _check(lib().ec_collide(batch, _ptr(f), _ptr(Q), _stream(stream)))
+
+
+def ec_entropy_prod(batch, f, Q, out, n_nonpos=None, stream=None):
+    return _check(lib().ec_entropy_prod(batch, _ptr(f), _ptr(Q), _ptr(out), _ptr(n_nonpos),
+                                        _stream(stream)))
+
+
+def ec_monitors(batch, f, Q, out, stream=None):
+    return _check(lib().ec_monitors(batch, _ptr(f), _ptr(Q), _ptr(out), _stream(stream)))
+
+
+def ec_step(batch, f, dt, n_steps, monitors=None, stream=None):
+    return _check(lib().ec_step(batch, _ptr(f), dt, n_steps, _ptr(monitors), _stream(stream)))

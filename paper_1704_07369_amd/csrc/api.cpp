@@ -1,0 +1,380 @@
+// C ABI of the EFM collision library (see include/ec.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ec.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace efm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(EC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename F>
+int guarded(F&& fn) {
+  try {
+    return fn();
+  } catch (const std::bad_alloc&) {
+    return fail(EC_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(EC_ERR_ARG, e.what());
+  } catch (...) {
+    return fail(EC_ERR_ARG, "unknown exception");
+  }
+}
+
+}  // namespace
+
+struct ec_plan {
+  HostTables host;
+  int device = 0;
+  void* d_gamma64 = nullptr;   // [J][n] double pairs
+  void* d_gamma32 = nullptr;   // [J][n] float pairs
+};
+
+struct BatchGroup {
+  const ec_plan* plan = nullptr;
+  int64_t count = 0;
+  int64_t first = 0;   // first batch cell of the group
+  int chunk = 0;       // cells per pass
+};
+
+struct StepGraph {
+  hipGraphExec_t exec = nullptr;
+  double* f = nullptr;
+  double dt = 0.0;
+  double* mon = nullptr;
+};
+
+struct ec_batch {
+  int precision = EC_FP64;
+  int device = 0;
+  std::vector<BatchGroup> groups;
+  int64_t n_cells = 0, n_elems = 0;
+  std::vector<int64_t> offsets;
+  int64_t* d_off = nullptr;
+  int* d_n = nullptr;
+  double* d_hd = nullptr;
+  void* d_W = nullptr;
+  void* d_Z = nullptr;
+  size_t W_bytes = 0, Z_bytes = 0;
+  int* d_step = nullptr;
+  StepGraph graph;
+};
+
+namespace {
+
+int default_chunk(const HostTables& T, int64_t count) {
+  // aim for about 2048 waves in the slab pass (N0 * N threads per cell)
+  const int64_t threads_per_cell = (int64_t)T.n0 * T.n1;
+  int64_t c = (2048 * 64 + threads_per_cell - 1) / threads_per_cell;
+  c = std::max<int64_t>(1, std::min<int64_t>(c, count));
+  return (int)c;
+}
+
+int alloc_workspaces(ec_batch* b) {
+  const size_t cs = b->precision == EC_FP32 ? 8 : 16;
+  size_t wmax = 0, zmax = 0;
+  for (auto& g : b->groups) {
+    const HostTables& T = g.plan->host;
+    wmax = std::max(wmax, (size_t)g.chunk * T.n * cs);
+    if (T.d == 3) zmax = std::max(zmax, (size_t)g.chunk * T.J * T.n * cs);
+  }
+  if (b->d_W) { (void)hipFree(b->d_W); b->d_W = nullptr; }
+  if (b->d_Z) { (void)hipFree(b->d_Z); b->d_Z = nullptr; }
+  b->W_bytes = wmax;
+  b->Z_bytes = zmax;
+  if (wmax && hipMalloc(&b->d_W, wmax) != hipSuccess) return fail(EC_ERR_OOM, "workspace W");
+  if (zmax && hipMalloc(&b->d_Z, zmax) != hipSuccess) return fail(EC_ERR_OOM, "workspace Z");
+  return EC_OK;
+}
+
+void drop_graph(ec_batch* b) {
+  if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
+  b->graph = StepGraph{};
+}
+
+int run_collide(ec_batch* b, const double* f, double* Q, double dt, hipStream_t s) {
+  for (auto& g : b->groups) {
+    const HostTables& T = g.plan->host;
+    for (int64_t c0 = 0; c0 < g.count; c0 += g.chunk) {
+      ChunkArgs a;
+      a.N = T.N; a.d = T.d; a.precision = b->precision; a.J = T.J;
+      a.gamma = b->precision == EC_FP32 ? g.plan->d_gamma32 : g.plan->d_gamma64;
+      a.W = b->d_W; a.Z = b->d_Z;
+      a.f = f; a.Q = Q; a.off = b->d_off;
+      a.cell0 = g.first + c0;
+      a.ncells = (int)std::min<int64_t>(g.chunk, g.count - c0);
+      a.dt = dt;
+      HIPCHK(launch_chunk(a, s));
+    }
+  }
+  return EC_OK;
+}
+
+int check_batch_ptrs(ec_batch* b, const void* f, const void* Q) {
+  if (!b) return fail(EC_ERR_ARG, "batch is null");
+  if (!f) return fail(EC_ERR_ARG, "f is null");
+  if (Q && f == Q) return fail(EC_ERR_ARG, "f and Q must not alias");
+  return EC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ec_last_error(void) { return g_err.c_str(); }
+
+int ec_host_tables(int N, int d, double L, const ec_kernel* kernel, int M, int* n_terms,
+                   double* gamma) {
+  return guarded([&]() -> int {
+    if (!kernel) return fail(EC_ERR_ARG, "kernel is null");
+    HostTables T;
+    std::string err;
+    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, M, T, err);
+    if (rc) return fail(rc, err);
+    if (n_terms) *n_terms = T.terms;
+    if (gamma) std::memcpy(gamma, T.gamma.data(), T.gamma.size() * sizeof(double));
+    return EC_OK;
+  });
+}
+
+int ec_setup_kernel(int N, int d, double L, const ec_kernel* kernel, int M, ec_plan** out) {
+  return guarded([&]() -> int {
+    if (!kernel || !out) return fail(EC_ERR_ARG, "null argument");
+    *out = nullptr;
+    auto* p = new ec_plan();
+    std::string err;
+    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, M, p->host, err);
+    if (rc) { delete p; return fail(rc, err); }
+    if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(EC_ERR_DEVICE, "no HIP device"); }
+    const size_t cnt = p->host.gamma.size();
+    std::vector<float> g32(cnt);
+    for (size_t i = 0; i < cnt; ++i) g32[i] = (float)p->host.gamma[i];
+    if (hipMalloc(&p->d_gamma64, cnt * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->d_gamma32, cnt * sizeof(float)) != hipSuccess) {
+      ec_plan_destroy(p);
+      return fail(EC_ERR_OOM, "plan tables");
+    }
+    if (hipMemcpy(p->d_gamma64, p->host.gamma.data(), cnt * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_gamma32, g32.data(), cnt * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      ec_plan_destroy(p);
+      return fail(EC_ERR_DEVICE, "upload of plan tables failed");
+    }
+    *out = p;
+    return EC_OK;
+  });
+}
+
+int ec_plan_destroy(ec_plan* p) {
+  if (!p) return EC_OK;
+  if (p->d_gamma64) (void)hipFree(p->d_gamma64);
+  if (p->d_gamma32) (void)hipFree(p->d_gamma32);
+  delete p;
+  return EC_OK;
+}
+
+int ec_plan_terms(const ec_plan* p, int* n_terms) {
+  if (!p || !n_terms) return fail(EC_ERR_ARG, "null argument");
+  *n_terms = p->host.terms;
+  return EC_OK;
+}
+
+int ec_plan_tables(const ec_plan* p, double* gamma) {
+  if (!p || !gamma) return fail(EC_ERR_ARG, "null argument");
+  std::memcpy(gamma, p->host.gamma.data(), p->host.gamma.size() * sizeof(double));
+  return EC_OK;
+}
+
+int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_groups,
+                    int precision, ec_batch** out) {
+  return guarded([&]() -> int {
+    if (!plans || !counts || !out || n_groups < 1) return fail(EC_ERR_ARG, "null argument or no groups");
+    if (precision != EC_FP64 && precision != EC_FP32) return fail(EC_ERR_ARG, "precision");
+    *out = nullptr;
+    auto* b = new ec_batch();
+    b->precision = precision;
+    if (hipGetDevice(&b->device) != hipSuccess) { delete b; return fail(EC_ERR_DEVICE, "no HIP device"); }
+    int64_t cell = 0, elem = 0;
+    std::vector<int> ns;
+    std::vector<double> hds;
+    for (int g = 0; g < n_groups; ++g) {
+      if (!plans[g] || counts[g] < 0) { delete b; return fail(EC_ERR_ARG, "bad group"); }
+      BatchGroup bg;
+      bg.plan = plans[g];
+      bg.count = counts[g];
+      bg.first = cell;
+      bg.chunk = default_chunk(plans[g]->host, std::max<int64_t>(1, counts[g]));
+      const HostTables& T = plans[g]->host;
+      const double hd = std::pow(2.0 * T.L / T.N, T.d);
+      for (int64_t c = 0; c < counts[g]; ++c) {
+        b->offsets.push_back(elem);
+        ns.push_back((int)T.n);
+        hds.push_back(hd);
+        elem += (T.n + 31) / 32 * 32;   // 256-byte aligned cells
+      }
+      cell += counts[g];
+      b->groups.push_back(bg);
+    }
+    b->n_cells = cell;
+    b->n_elems = elem;
+    if (cell > 0) {
+      if (hipMalloc(&b->d_off, cell * sizeof(int64_t)) != hipSuccess ||
+          hipMalloc(&b->d_n, cell * sizeof(int)) != hipSuccess ||
+          hipMalloc(&b->d_hd, cell * sizeof(double)) != hipSuccess) {
+        ec_batch_destroy(b);
+        return fail(EC_ERR_OOM, "batch metadata");
+      }
+      if (hipMemcpy(b->d_off, b->offsets.data(), cell * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(b->d_n, ns.data(), cell * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(b->d_hd, hds.data(), cell * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        ec_batch_destroy(b);
+        return fail(EC_ERR_DEVICE, "upload of batch metadata failed");
+      }
+    }
+    if (hipMalloc(&b->d_step, sizeof(int)) != hipSuccess) { ec_batch_destroy(b); return fail(EC_ERR_OOM, "step counter"); }
+    int rc = alloc_workspaces(b);
+    if (rc) { ec_batch_destroy(b); return rc; }
+    *out = b;
+    return EC_OK;
+  });
+}
+
+int ec_batch_destroy(ec_batch* b) {
+  if (!b) return EC_OK;
+  drop_graph(b);
+  if (b->d_off) (void)hipFree(b->d_off);
+  if (b->d_n) (void)hipFree(b->d_n);
+  if (b->d_hd) (void)hipFree(b->d_hd);
+  if (b->d_W) (void)hipFree(b->d_W);
+  if (b->d_Z) (void)hipFree(b->d_Z);
+  if (b->d_step) (void)hipFree(b->d_step);
+  delete b;
+  return EC_OK;
+}
+
+int ec_batch_size(const ec_batch* b, int64_t* n_cells, int64_t* n_elems) {
+  if (!b) return fail(EC_ERR_ARG, "batch is null");
+  if (n_cells) *n_cells = b->n_cells;
+  if (n_elems) *n_elems = b->n_elems;
+  return EC_OK;
+}
+
+int ec_batch_offsets(const ec_batch* b, int64_t* offsets) {
+  if (!b || !offsets) return fail(EC_ERR_ARG, "null argument");
+  std::memcpy(offsets, b->offsets.data(), b->offsets.size() * sizeof(int64_t));
+  return EC_OK;
+}
+
+int ec_batch_set_chunk(ec_batch* b, int group, int cells_per_pass) {
+  return guarded([&]() -> int {
+    if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
+    BatchGroup& g = b->groups[group];
+    int c = cells_per_pass > 0 ? cells_per_pass : default_chunk(g.plan->host, std::max<int64_t>(1, g.count));
+    g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, std::max<int64_t>(1, g.count)));
+    drop_graph(b);
+    HIPCHK(hipDeviceSynchronize());
+    return alloc_workspaces(b);
+  });
+}
+
+int ec_collide(ec_batch* b, const double* f, double* Q, void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_batch_ptrs(b, f, Q);
+    if (rc) return rc;
+    if (!Q) return fail(EC_ERR_ARG, "Q is null");
+    return run_collide(b, f, Q, 0.0, (hipStream_t)stream);
+  });
+}
+
+int ec_entropy_prod(ec_batch* b, const double* f, const double* Q, double* out,
+                    int32_t* n_nonpos, void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_batch_ptrs(b, f, Q);
+    if (rc) return rc;
+    if (!Q || !out) return fail(EC_ERR_ARG, "Q or out is null");
+    HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, nullptr, out,
+                           n_nonpos, nullptr, nullptr, 0, (hipStream_t)stream));
+    return EC_OK;
+  });
+}
+
+int ec_monitors(ec_batch* b, const double* f, const double* Q, double* out, void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_batch_ptrs(b, f, Q);
+    if (rc) return rc;
+    if (!out) return fail(EC_ERR_ARG, "out is null");
+    HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, out, nullptr,
+                           nullptr, nullptr, nullptr, 0, (hipStream_t)stream));
+    return EC_OK;
+  });
+}
+
+int ec_step(ec_batch* b, double* f, double dt, int n_steps, double* monitors, void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_batch_ptrs(b, f, nullptr);
+    if (rc) return rc;
+    if (n_steps < 0 || !(dt > 0.0)) return fail(EC_ERR_ARG, "need dt > 0 and n_steps >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    if (n_steps == 0) return EC_OK;
+    if (!(b->graph.exec && b->graph.f == f && b->graph.dt == dt && b->graph.mon == monitors)) {
+      drop_graph(b);
+      // capture one step; replays advance the device step counter
+      hipStream_t cap;
+      HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      int rc2 = EC_OK;
+      if (e == hipSuccess) {
+        rc2 = run_collide(b, f, f, dt, cap);
+        if (rc2 == EC_OK && monitors) {
+          hipError_t e2 = launch_monitors(f, nullptr, b->d_off, b->d_n, b->d_hd, 0, b->n_cells,
+                                          nullptr, nullptr, nullptr, b->d_step, monitors,
+                                          b->n_cells, cap);
+          if (e2 == hipSuccess) e2 = launch_inc_int(b->d_step, cap);
+          if (e2 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e2));
+        }
+        hipError_t e3 = hipStreamEndCapture(cap, &graph);
+        if (rc2 == EC_OK && e3 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e3));
+      } else {
+        rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e));
+      }
+      if (rc2 == EC_OK) {
+        hipError_t e4 = hipGraphInstantiate(&b->graph.exec, graph, nullptr, nullptr, 0);
+        if (e4 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e4));
+      }
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipStreamDestroy(cap);
+      if (rc2) { drop_graph(b); return rc2; }
+      b->graph.f = f;
+      b->graph.dt = dt;
+      b->graph.mon = monitors;
+    }
+    HIPCHK(launch_set_int(b->d_step, 0, s));
+    for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(b->graph.exec, s));
+    return EC_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,43 @@
+// Internal launch interface of the HIP kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace efm {
+
+// One pass of the collision pipeline over `ncells` consecutive cells of one
+// plan: forward transform -> per-term multiply and inverse x transform ->
+// per-term inverse slab transform with FP64 gain accumulation, loss and
+// combine.  dt == 0 writes Q; dt != 0 writes Q = F + dt Q^s[F] (Q may equal f).
+struct ChunkArgs {
+  int N = 0, d = 0, precision = 0;
+  int J = 0;                       // products + 1 (loss)
+  const void* gamma = nullptr;     // [J][n] complex (FP64 or FP32 pairs)
+  void* W = nullptr;               // workspace [ncells][n] complex
+  void* Z = nullptr;               // workspace [ncells][J][n] complex (3D only)
+  const double* f = nullptr;
+  double* Q = nullptr;
+  const int64_t* off = nullptr;    // device: element offset of every batch cell
+  int64_t cell0 = 0;               // first batch cell of the pass
+  int ncells = 0;
+  double dt = 0.0;
+};
+
+hipError_t launch_chunk(const ChunkArgs& a, hipStream_t s);
+
+// Per-cell reductions (fixed order, deterministic).  Any output may be null.
+//   full:    [cell][EC_NMON]
+//   entprod: [cell]      n_nonpos: [cell]
+//   step_mon: (mass, eta) at [(*step) * ncells + cell][2], step read on device
+hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
+                           const int* cell_n, const double* cell_hd, int64_t cell0,
+                           int64_t ncells, double* full, double* entprod,
+                           int32_t* n_nonpos, const int* step, double* step_mon,
+                           int64_t step_stride, hipStream_t s);
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
+hipError_t launch_inc_int(int* p, hipStream_t s);
+
+}  // namespace efm

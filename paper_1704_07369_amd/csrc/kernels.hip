@@ -1,0 +1,306 @@
+// HIP kernels of the EFM collision operator for gfx950 (CDNA4, wave64).
+//
+// Data flow of one pass over a set of cells (cell dims (N0, N, N): N0 = N in
+// 3D, N0 = 1 in 2D; F and Q are C-ordered [x][y][z]):
+//
+//   k_fwd   one block row per (cell, x) slab: forward DFT along y (register
+//           line), LDS transpose, forward DFT along z ->
+//           W[cell][x][k2][k1]                       (k1 fastest)
+//   k_pencil (3D) one thread per (cell, k2, k1) pencil: forward DFT along x
+//           (the 3D transform of F is complete), then for every term j:
+//           multiply by gamma_j = alpha_j + i beta_j, inverse DFT along x ->
+//           Z[cell][j][x][k2][k1]
+//   k_slab  one block row per (cell, x) slab, one thread per k1 row: for every
+//           term j: inverse DFT along z, LDS transpose, inverse DFT along y ->
+//           c_j(x, y, z); gain += Re c_j Im c_j in FP64 (j < J-1), loss
+//           l = Re c_{J-1}; then Q = gain - F l (or F + dt Q, in place).
+//           In 2D the x pass is empty and k_slab reads gamma_j W directly.
+//
+// Every access is coalesced: consecutive threads touch consecutive k1 (or z).
+// Transforms are unnormalised; N^-d, the quadrature weights and the filter
+// live in gamma (host tables).
+#include "kernels.h"
+
+#include "fft.h"
+
+namespace efm {
+
+template <int N>
+constexpr int slabs_per_block() {
+  return N >= 32 ? 2 : (N >= 16 ? 128 / N : 96 / N);   // 64 / 128 / 120 / 96 threads
+}
+
+// ---------------------------------------------------------------------------
+// forward 2D transform of each (cell, x) slab
+// ---------------------------------------------------------------------------
+template <typename R, int N0, int N>
+__global__ __launch_bounds__(slabs_per_block<N>() * N) void k_fwd(
+    const double* __restrict__ f, const int64_t* __restrict__ off, int64_t cell0,
+    int ncells, cx<R>* __restrict__ W) {
+  constexpr int SPB = slabs_per_block<N>();
+  __shared__ cx<R> lds[SPB][N][N + 1];
+  const int s = threadIdx.x / N, i = threadIdx.x % N;
+  const int64_t slab = (int64_t)blockIdx.x * SPB + s;
+  const bool active = slab < (int64_t)ncells * N0;
+  const int cc = active ? (int)(slab / N0) : 0;
+  const int x = active ? (int)(slab % N0) : 0;
+  cx<R> v[N];
+  {
+    const double* fc = f + off[cell0 + cc] + (int64_t)x * N * N;
+#pragma unroll
+    for (int y = 0; y < N; ++y) v[y] = {(R)fc[y * N + i], (R)0};
+  }
+  fft_line<N, -1>(v);                       // along y: (k1, z = i)
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) lds[s][k1][i] = v[k1];
+  __syncthreads();
+#pragma unroll
+  for (int z = 0; z < N; ++z) v[z] = lds[s][i][z];
+  fft_line<N, -1>(v);                       // along z: (k1 = i, k2)
+  if (active) {
+    cx<R>* Wc = W + ((int64_t)cc * N0 + x) * N * N;
+#pragma unroll
+    for (int k2 = 0; k2 < N; ++k2) Wc[k2 * N + i] = v[k2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x pencils: finish the forward transform, then per term multiply + inverse
+// ---------------------------------------------------------------------------
+constexpr int PENCIL_BS = 64;
+
+template <typename R, int N0, int N>
+__global__ __launch_bounds__(PENCIL_BS) void k_pencil(
+    const cx<R>* __restrict__ W, const cx<R>* __restrict__ G, int J, int ncells,
+    cx<R>* __restrict__ Z) {
+  constexpr int P = N * N;
+  __shared__ cx<R> fh[N0][PENCIL_BS];
+  const int64_t gid = (int64_t)blockIdx.x * PENCIL_BS + threadIdx.x;
+  const bool active = gid < (int64_t)ncells * P;
+  const int cc = active ? (int)(gid / P) : 0;
+  const int p = active ? (int)(gid % P) : 0;
+  cx<R> v[N0];
+  {
+    const cx<R>* Wc = W + (int64_t)cc * N0 * P + p;
+#pragma unroll
+    for (int k = 0; k < N0; ++k) v[k] = Wc[(int64_t)k * P];
+  }
+  fft_line<N0, -1>(v);                      // along x: Fh(k0, p), unnormalised
+#pragma unroll
+  for (int k = 0; k < N0; ++k) fh[k][threadIdx.x] = v[k];   // own column only
+  for (int j = 0; j < J; ++j) {
+    const cx<R>* Gj = G + (int64_t)j * N0 * P + p;
+#pragma unroll
+    for (int k = 0; k < N0; ++k) v[k] = cmul(Gj[(int64_t)k * P], fh[k][threadIdx.x]);
+    fft_line<N0, +1>(v);
+    if (active) {
+      cx<R>* Zj = Z + ((int64_t)cc * J + j) * N0 * P + p;
+#pragma unroll
+      for (int xx = 0; xx < N0; ++xx) Zj[(int64_t)xx * P] = v[xx];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// slabs: per term inverse 2D transform, FP64 gain accumulation, loss, combine
+// ---------------------------------------------------------------------------
+template <typename R, int N0, int N>
+__global__ __launch_bounds__(slabs_per_block<N>() * N) void k_slab(
+    const cx<R>* __restrict__ Z, const cx<R>* __restrict__ G, int J,
+    const double* f, const int64_t* __restrict__ off, int64_t cell0, int ncells,
+    double* Q, double dt) {
+  constexpr int SPB = slabs_per_block<N>();
+  constexpr int P = N * N;
+  __shared__ cx<R> lds[SPB][N][N + 1];
+  const int s = threadIdx.x / N, i = threadIdx.x % N;
+  const int64_t slab = (int64_t)blockIdx.x * SPB + s;
+  const bool active = slab < (int64_t)ncells * N0;
+  const int cc = active ? (int)(slab / N0) : 0;
+  const int x = active ? (int)(slab % N0) : 0;
+  double acc[N];
+#pragma unroll
+  for (int y = 0; y < N; ++y) acc[y] = 0.0;
+  cx<R> v[N];
+  for (int j = 0; j < J; ++j) {
+    if constexpr (N0 == 1) {
+      // 2D: the spectrum of the cell is W itself; multiply on the fly
+      const cx<R>* Wc = Z + (int64_t)cc * P;
+      const cx<R>* Gj = G + (int64_t)j * P;
+#pragma unroll
+      for (int k2 = 0; k2 < N; ++k2) v[k2] = cmul(Gj[k2 * N + i], Wc[k2 * N + i]);
+    } else {
+      const cx<R>* Zs = Z + (((int64_t)cc * J + j) * N0 + x) * P;
+#pragma unroll
+      for (int k2 = 0; k2 < N; ++k2) v[k2] = Zs[k2 * N + i];
+    }
+    fft_line<N, +1>(v);                     // along z: (k1 = i, z)
+    __syncthreads();                        // readers of the previous term are done
+#pragma unroll
+    for (int z = 0; z < N; ++z) lds[s][i][z] = v[z];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < N; ++k1) v[k1] = lds[s][k1][i];
+    fft_line<N, +1>(v);                     // along y: c_j(x, y, z = i)
+    if (j + 1 < J) {
+#pragma unroll
+      for (int y = 0; y < N; ++y) acc[y] += (double)v[y].x * (double)v[y].y;
+    }
+  }
+  if (active) {
+    const int64_t base = off[cell0 + cc] + (int64_t)x * P;
+    const double* fc = f + base;
+    double* qc = Q + base;
+#pragma unroll
+    for (int y = 0; y < N; ++y) {
+      const double fv = fc[y * N + i];
+      const double q = acc[y] - fv * (double)v[y].x;
+      qc[y * N + i] = (dt == 0.0) ? q : fv + dt * q;
+    }
+  }
+}
+
+template <typename R, int N0, int N>
+static hipError_t launch_chunk_t(const ChunkArgs& a, hipStream_t st) {
+  constexpr int SPB = slabs_per_block<N>();
+  const int64_t slabs = (int64_t)a.ncells * N0;
+  const int slab_blocks = (int)((slabs + SPB - 1) / SPB);
+  const cx<R>* G = (const cx<R>*)a.gamma;
+  cx<R>* W = (cx<R>*)a.W;
+  cx<R>* Z = (cx<R>*)a.Z;
+  hipLaunchKernelGGL((k_fwd<R, N0, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
+                     a.f, a.off, a.cell0, a.ncells, W);
+  if constexpr (N0 > 1) {
+    const int64_t pencils = (int64_t)a.ncells * N * N;
+    const int pblocks = (int)((pencils + PENCIL_BS - 1) / PENCIL_BS);
+    hipLaunchKernelGGL((k_pencil<R, N0, N>), dim3(pblocks), dim3(PENCIL_BS), 0, st,
+                       W, G, a.J, a.ncells, Z);
+    hipLaunchKernelGGL((k_slab<R, N0, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
+                       Z, G, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
+  } else {
+    hipLaunchKernelGGL((k_slab<R, 1, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
+                       W, G, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_chunk_r(const ChunkArgs& a, hipStream_t st) {
+#define EFM_CASE(NN)                                                   \
+  case NN:                                                             \
+    return a.d == 3 ? launch_chunk_t<R, NN, NN>(a, st) : launch_chunk_t<R, 1, NN>(a, st);
+  switch (a.N) {
+    EFM_CASE(8)
+    EFM_CASE(12)
+    EFM_CASE(16)
+    EFM_CASE(24)
+    EFM_CASE(32)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef EFM_CASE
+}
+
+hipError_t launch_chunk(const ChunkArgs& a, hipStream_t st) {
+  if (a.ncells <= 0) return hipSuccess;
+  return a.precision == 1 ? launch_chunk_r<float>(a, st) : launch_chunk_r<double>(a, st);
+}
+
+// ---------------------------------------------------------------------------
+// per-cell reductions
+// ---------------------------------------------------------------------------
+constexpr int MON_BS = 256;
+constexpr int MON_Q = 8;   // reduced quantities
+
+__global__ __launch_bounds__(MON_BS) void k_monitors(
+    const double* __restrict__ f, const double* __restrict__ Q,
+    const int64_t* __restrict__ off, const int* __restrict__ cell_n,
+    const double* __restrict__ cell_hd, int64_t cell0, double* full,
+    double* entprod, int32_t* n_nonpos, const int* step, double* step_mon,
+    int64_t step_stride) {
+  __shared__ double red[MON_Q][MON_BS];
+  const int64_t c = cell0 + blockIdx.x;
+  const double* fc = f + off[c];
+  const double* qc = Q ? Q + off[c] : nullptr;
+  const int n = cell_n[c];
+  // 0 mass, 1 sumQ, 2 sum Q ln F, 3 sum F ln F, 4 min F, 5 sum |F|, 6 sum |Q|, 7 #F<=0
+  double a[MON_Q] = {0, 0, 0, 0, 1.0e300, 0, 0, 0};
+  for (int r = threadIdx.x; r < n; r += MON_BS) {
+    const double fv = fc[r];
+    const double qv = qc ? qc[r] : 0.0;
+    a[0] += fv;
+    a[1] += qv;
+    if (fv > 0.0) {
+      const double lf = log(fv);
+      a[2] += qv * lf;
+      a[3] += fv * lf;
+    } else {
+      a[7] += 1.0;
+    }
+    a[4] = fmin(a[4], fv);
+    a[5] += fabs(fv);
+    a[6] += fabs(qv);
+  }
+#pragma unroll
+  for (int k = 0; k < MON_Q; ++k) red[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int w = MON_BS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < MON_Q; ++k) {
+        if (k == 4) red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        else red[k][threadIdx.x] += red[k][threadIdx.x + w];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double hd = cell_hd[c];
+    const double mass = hd * red[0][0];
+    const double eta = hd * red[3][0];
+    const double ep = hd * red[2][0];
+    const int64_t lc = blockIdx.x;
+    if (full) {
+      double* o = full + lc * 7;
+      o[0] = mass;
+      o[1] = red[1][0];
+      o[2] = ep;
+      o[3] = eta;
+      o[4] = red[4][0];
+      o[5] = red[5][0] > 0.0 ? (red[5][0] - red[0][0]) / red[5][0] : 0.0;
+      o[6] = red[6][0];
+    }
+    if (entprod) entprod[lc] = ep;
+    if (n_nonpos) n_nonpos[lc] = (int32_t)red[7][0];
+    if (step_mon) {
+      double* o = step_mon + ((int64_t)(*step) * step_stride + lc) * 2;
+      o[0] = mass;
+      o[1] = eta;
+    }
+  }
+}
+
+hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
+                           const int* cell_n, const double* cell_hd, int64_t cell0,
+                           int64_t ncells, double* full, double* entprod,
+                           int32_t* n_nonpos, const int* step, double* step_mon,
+                           int64_t step_stride, hipStream_t s) {
+  if (ncells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_monitors, dim3((unsigned)ncells), dim3(MON_BS), 0, s, f, Q, off,
+                     cell_n, cell_hd, cell0, full, entprod, n_nonpos, step, step_mon,
+                     step_stride);
+  return hipGetLastError();
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+__global__ void k_inc_int(int* p) { *p += 1; }
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+hipError_t launch_inc_int(int* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_inc_int, dim3(1), dim3(1), 0, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace efm

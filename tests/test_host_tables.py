@@ -1,0 +1,104 @@
+"""CPU tests of the library's host logic: the spectral multipliers built by the
+C++ plan code (closed forms) against the oracle (quadrature of the defining
+integrals), and the layout/normalisation contract the kernels rely on."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import efm
+
+E = pytest.importorskip("paper_1704_07369_amd")
+
+R = 6.0
+
+
+def _kernel(d):
+    if d == 2:
+        return E.make_kernel(E.EC_KERNEL_MAXWELL, 0.0, R)
+    return E.make_kernel(E.EC_KERNEL_HARD_SPHERE, 1.0, R)
+
+
+def _as_nat(G, N, d):
+    """Library layout [j][k0][k2][k1] (2D: [j][k2][k1]) -> [j][k0][k1][k2]."""
+    J = G.shape[0]
+    if d == 3:
+        return G.reshape(J, N, N, N).transpose(0, 1, 3, 2)
+    return G.reshape(J, N, N).transpose(0, 2, 1)
+
+
+def model_pipeline(G, F):
+    """What the kernels compute, with library FFTs: c_j = IDFT(gamma_j DFT F)
+    (unnormalised both ways), Q = sum_{j<J-1} Re c_j Im c_j - F Re c_{J-1}."""
+    n = F.size
+    Fh = np.fft.fftn(F)
+    qp = np.zeros(F.shape)
+    for j in range(G.shape[0] - 1):
+        c = np.fft.ifftn(G[j] * Fh) * n
+        qp += c.real * c.imag
+    ell = (np.fft.ifftn(G[-1] * Fh) * n).real
+    return qp - F * ell, qp, ell
+
+
+@pytest.mark.parametrize("N,d,L,M", [(8, 2, 7.863961030678928, 3), (16, 2, 8.0, 16),
+                                     (12, 2, 8.0, 16), (8, 3, 8.0, 8), (12, 3, 8.0, 32),
+                                     (16, 3, 8.0, 32)])
+def test_library_tables_reproduce_oracle_operator(N, d, L, M):
+    G = _as_nat(E.ec_host_tables(N, d, L, _kernel(d), M), N, d)
+    assert G.shape[0] == M + 1
+    p = efm.make_plan(N, d, L, M, R=R)
+    F = synth.sample_mixture(synth.mixture_anisotropic(7 + N + d, d), N, L)
+    q, qp, ell = model_pipeline(G, F)
+    ref = efm.collide_modes(p, F)
+    scale = np.linalg.norm(ref.Qplus)
+    assert np.linalg.norm(q - ref.Q) < 1e-13 * scale
+    assert np.linalg.norm(qp - ref.Qplus) < 1e-13 * scale
+    assert np.abs(ell - efm.collision_frequency(p, F)).max() < 1e-13 * np.abs(ell).max()
+
+
+def test_library_table_symmetries_and_zero_band():
+    """Multipliers are even in k, vanish wherever sigma does (|k_i| >= N/2),
+    and D is the diagonal of the same low-rank kernel (mass conservation:
+    sum over k of alpha_t beta_t weights equals D)."""
+    N, d, L, M = 16, 3, 8.0, 32
+    G = _as_nat(E.ec_host_tables(N, d, L, _kernel(d), M), N, d)
+    k = np.fft.fftfreq(N, 1.0 / N).round().astype(int)
+    neg = (-np.arange(N)) % N
+    for j in range(M + 1):
+        g = G[j]
+        assert np.abs(g - g[np.ix_(neg, neg, neg)]).max() <= 1e-15 * np.abs(g).max()
+    edge = np.abs(k) >= N // 2
+    assert np.all(G[:, edge, :, :] == 0) and np.all(G[:, :, edge, :] == 0) and np.all(G[:, :, :, edge] == 0)
+    D = sum(G[j].real * G[j].imag for j in range(M)) * N ** d
+    assert np.abs(D - G[M].real).max() < 1e-14 * np.abs(G[M].real).max()
+
+
+def test_library_rejects_bad_arguments():
+    k = _kernel(3)
+    with pytest.raises(E.EcError) as ei:
+        E.ec_host_tables(20, 3, 8.0, k, 32)
+    assert ei.value.code == E.EC_ERR_UNSUPPORTED
+    with pytest.raises(E.EcError) as ei:
+        E.ec_host_tables(16, 4, 8.0, k, 32)
+    assert ei.value.code == E.EC_ERR_ARG
+    with pytest.raises(E.EcError) as ei:
+        E.ec_host_tables(16, 3, -1.0, k, 32)
+    assert ei.value.code == E.EC_ERR_ARG
+    with pytest.raises(E.EcError):
+        E.ec_host_tables(16, 3, 8.0, E.make_kernel(E.EC_KERNEL_VHS, 0.5, R), 32)
+    assert "kernel" in E.ec_last_error()
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "include", "ec.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(ec_\w+)\s*\(", hdr, re.M))
+    assert declared, "no declarations parsed"
+    lib = ctypes.CDLL(E.binding.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared <= set(E.binding.exported_symbols())
