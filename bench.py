@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Collision evaluations per second of the EFM operator on one MI355X.
+
+Workload (the headline of the method: N = 32^3, M = 32): 3D hard-sphere
+kernel, box [-8, 8]^3, R = 6, 32 hemisphere directions, a batch of 1024
+independent cells, each a seeded sum of 2-4 anisotropic Gaussians (means
+U[-2,2]^3, diagonal temperatures U[0.3,2], Dirichlet weights; seed 2001 + cell).
+One step = one ec_collide over the whole batch (every cell's Q).  Inputs are
+resident in HBM before the timed region.  FP64 is the headline value; FP32
+transforms and single-cell latency are reported beside it, each with its
+error against the CPU oracle on sampled points.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "collision evals/sec at N=32^3,M=32: FP64 vs mixed vs surrogate at stated rel err"
+PEAK_FP64 = 78.6    # TFLOP/s, MI355X vector FP64
+PEAK_FP32 = 157.3   # TFLOP/s, MI355X vector FP32
+N, D, L, M, R = 32, 3, 8.0, 32, 6.0
+KNAMES = ["k_fwd", "k_pencil", "k_slab"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_flops(n_side: int, d: int, terms: int) -> list:
+    """Algorithmic flops per cell of each kernel (nominal 2.5 n log2 n per real
+    and 5 n log2 n per complex transform, split by axes passes; products and
+    sums as written in the algorithm)."""
+    n = n_side ** d
+    lg = math.log2(n)
+    if d == 3:
+        fwd = (2.0 / 3.0) * 2.5 * n * lg
+        pencil = (1.0 / 3.0) * 2.5 * n * lg + terms * (1.0 / 3.0) * 5.0 * n * lg \
+            + (1.0 / 3.0) * 2.5 * n * lg + terms * 6.0 * n + 2.0 * n
+        slab = terms * (2.0 / 3.0) * 5.0 * n * lg + (2.0 / 3.0) * 2.5 * n * lg \
+            + terms * 2.0 * n + 2.0 * n
+    else:
+        fwd = 2.5 * n * lg
+        pencil = 0.0
+        slab = terms * 5.0 * n * lg + 2.5 * n * lg + terms * 8.0 * n + 4.0 * n
+    return [fwd, pencil, slab]
+
+
+def make_cells(n_cells, seed0=2001):
+    import synth
+    return [synth.sample_mixture(synth.mixture_anisotropic(seed0 + c, D), N, L) for c in range(n_cells)]
+
+
+def time_collide(E, torch, plan, cells, precision, steps, warmup, profile):
+    b = E.Batch([plan], [len(cells)], precision)
+    f = torch.from_numpy(E.pack(b, cells)).to("cuda:0")
+    Q = torch.zeros_like(f)
+    for _ in range(warmup):
+        b.collide(f, Q)
+    torch.cuda.synchronize()
+    if profile:
+        b.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.collide(f, Q)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = None
+    if profile:
+        ms, la, ce = b.profile_read()
+        b.profile(False)
+        prof = (ms[0], la[0], ce[0])
+    return b, f, Q, (t1 - t0), prof
+
+
+def sampled_error(E, b, Q, cells, cell_ids, oplan, efm, npts=64):
+    import numpy as np
+    qh = E.unpack(b, Q.cpu().numpy())
+    rng = np.random.default_rng(12345)
+    worst = 0.0
+    for c in cell_ids:
+        idx = rng.choice(N ** D, npts, replace=False)
+        q, qp, _, _ = efm.collide_points(oplan, cells[c], idx)
+        worst = max(worst, float(np.abs(qh[c].ravel()[idx] - q).max() / np.abs(qp).max()))
+    return worst
+
+
+def roofline(prof, flops_cell, peak):
+    ms, launches, cells = prof
+    avg = [ms[k] / max(1, launches[k]) for k in range(3)]
+    k = max(range(3), key=lambda i: ms[i])
+    cells_per_launch = cells / max(1, launches[k])
+    achieved = flops_cell[k] * cells_per_launch / (avg[k] * 1e-3) / 1e12
+    return {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4), "traffic": None, "kernel": KNAMES[k],
+        "avg_launch_ms": round(avg[k], 4), "cells_per_launch": cells_per_launch,
+        "flops_per_launch": flops_cell[k] * cells_per_launch,
+        "kernel_ms_per_step": {KNAMES[i]: round(ms[i], 3) for i in range(3)},
+    }
+
+
+def cpu_baseline(cells, efm, oplan):
+    """The oracle (plain double sum over modes, OpenMP) on one cell of the
+    workload; evals/s = 1 / time of one full evaluation."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    efm._load()
+    t0 = time.perf_counter()
+    efm.collide_modes(oplan, cells[0])
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": "1 of the 1024 cells, full 32^3 direct double sum over modes (M=32), "
+                      f"{t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cells", type=int, default=1024)
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the oracle timing")
+    ap.add_argument("--skip-parity", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): cells are independent, "
+              "the multi-GPU split is a design note in DESIGN.md, not a measured path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+    import paper_1704_07369_amd as E
+
+    assert torch.cuda.is_available(), "no GPU"
+    log(f"bench: building {args.cells} cells of {N}^3")
+    cells = make_cells(args.cells)
+    plan = E.Plan(N, D, L, M, R=R)
+    terms = plan.terms()
+    flops = kernel_flops(N, D, terms)
+    flops_eval = sum(flops)
+
+    log("bench: FP64 timed region")
+    b64, f64, Q64, t64, prof64 = time_collide(E, torch, plan, cells, E.EC_FP64, args.steps,
+                                              args.warmup, True)
+    ev64 = args.cells * args.steps / t64
+    log(f"bench: FP64 {ev64:.4g} evals/s")
+    log("bench: FP32 timed region")
+    b32, f32, Q32, t32, prof32 = time_collide(E, torch, plan, cells, E.EC_FP32, args.steps,
+                                              args.warmup, True)
+    ev32 = args.cells * args.steps / t32
+    log(f"bench: FP32 {ev32:.4g} evals/s")
+    log("bench: single-cell latency")
+    one = cells[:1]
+    reps = max(10, args.steps)
+    _, _, _, t1_64, _ = time_collide(E, torch, plan, one, E.EC_FP64, reps, 2, False)
+    _, _, _, t1_32, _ = time_collide(E, torch, plan, one, E.EC_FP32, reps, 2, False)
+
+    out = {
+        "metric": METRIC, "value": ev64, "unit": "evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t64 / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D hard-sphere EFM collision operator, N=32^3, M=32 directions, "
+                               f"L=8, R=6, batch of {args.cells} Gaussian-mixture cells, FP64",
+                   "d": D, "N": N, "M": M, "L": L, "R": R, "cells": args.cells,
+                   "kernel": "hard_sphere", "flops_per_eval": flops_eval},
+        "roofline": roofline(prof64, flops, PEAK_FP64),
+        "fp32": {"value": ev32, "ms_per_step": t32 / args.steps * 1e3,
+                 "roofline": roofline(prof32, flops, PEAK_FP32)},
+        "single_cell": {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6},
+    }
+    if not args.skip_parity or not args.skip_cpu:
+        from oracle import efm
+        log("bench: oracle tables (quadrature)")
+        oplan = efm.make_plan(N, D, L, M, R=R)
+        if not args.skip_parity:
+            log("bench: sampled parity vs oracle")
+            out["parity"] = {
+                "metric": "max_r |Q - Q_oracle| / max_r |Q+_oracle| on 64 sampled points x 2 cells",
+                "fp64": sampled_error(E, b64, Q64, cells, [0, args.cells - 1], oplan, efm),
+                "fp32": sampled_error(E, b32, Q32, cells, [0, args.cells - 1], oplan, efm),
+            }
+        if not args.skip_cpu:
+            log("bench: CPU baseline (oracle)")
+            out["cpu_baseline"] = cpu_baseline(cells, efm, oplan)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

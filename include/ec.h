@@ -177,6 +177,18 @@ int ec_monitors(ec_batch* batch, const double* f, const double* Q, double* out,
 int ec_step(ec_batch* batch, double* f, double dt, int n_steps,
             double* monitors, void* hip_stream);
 
+/*
+ * Profiling of ec_collide (tracing).  While enabled, every pass of ec_collide
+ * records HIP events on its stream around its three kernels (forward slab
+ * transform, x-pencil pass, slab pass).  ec_profile_read waits for them and
+ * returns, per group g of the batch, ms[3g + k] = summed duration of kernel k
+ * and launches[3g + k] = number of launches, and cells[g] = cells processed;
+ * then it forgets the records.  Host arrays of 3 * n_groups (cells: n_groups).
+ * In 2D the x-pencil pass is empty (its duration is ~0).
+ */
+int ec_profile(ec_batch* batch, int enable);
+int ec_profile_read(ec_batch* batch, double* ms, int64_t* launches, int64_t* cells);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* ec_last_error(void);
 

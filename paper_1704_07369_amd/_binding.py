@@ -54,6 +54,9 @@ _SIGS = {
     "ec_entropy_prod": ([_vp, _vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_monitors": ([_vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_step": ([_vp, _vp, _c_double, _c_int, _vp, _vp], _c_int),
+    "ec_profile": ([_vp, _c_int], _c_int),
+    "ec_profile_read": ([_vp, ctypes.POINTER(_c_double), ctypes.POINTER(_c_i64),
+                         ctypes.POINTER(_c_i64)], _c_int),
 }
 
 _lib = None
@@ -66,6 +69,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1704_07369_amd.build`")
+        # torch ships its own HIP runtime with the same soname
+        # (libamdhip64.so.7).  Loading torch first makes the dynamic loader
+        # reuse that copy for libefm.so, so one HIP runtime serves both the
+        # allocator/streams and the kernels of this library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             fn = getattr(L, name)
@@ -192,3 +203,17 @@ def ec_monitors(batch, f, Q, out, stream=None):
 
 def ec_step(batch, f, dt, n_steps, monitors=None, stream=None):
     return _check(lib().ec_step(batch, _ptr(f), dt, n_steps, _ptr(monitors), _stream(stream)))
+
+
+def ec_profile(batch, enable=True):
+    return _check(lib().ec_profile(batch, 1 if enable else 0))
+
+
+def ec_profile_read(batch, n_groups):
+    ms = np.zeros(3 * n_groups)
+    la = np.zeros(3 * n_groups, dtype=np.int64)
+    ce = np.zeros(n_groups, dtype=np.int64)
+    _check(lib().ec_profile_read(batch, ms.ctypes.data_as(ctypes.POINTER(_c_double)),
+                                 la.ctypes.data_as(ctypes.POINTER(_c_i64)),
+                                 ce.ctypes.data_as(ctypes.POINTER(_c_i64))))
+    return ms.reshape(n_groups, 3), la.reshape(n_groups, 3), ce

@@ -70,6 +70,12 @@ class Batch:
     def step(self, f, dt, n_steps, monitors=None, stream=None):
         B.ec_step(self.handle, f, dt, n_steps, monitors, stream)
 
+    def profile(self, enable=True):
+        B.ec_profile(self.handle, enable)
+
+    def profile_read(self):
+        return B.ec_profile_read(self.handle, len(self.plans))
+
     def close(self):
         if self.handle:
             B.ec_batch_destroy(self.handle)

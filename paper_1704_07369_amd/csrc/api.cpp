@@ -65,9 +65,19 @@ struct StepGraph {
   double* f = nullptr;
   double dt = 0.0;
   double* mon = nullptr;
+  int cap = 0;
+};
+
+struct ProfRec {
+  int group;
+  int ncells;
+  hipEvent_t ev[4];
 };
 
 struct ec_batch {
+  bool profiling = false;
+  std::vector<ProfRec> prof;        // recorded, not yet read
+  std::vector<hipEvent_t> ev_pool;  // free events
   int precision = EC_FP64;
   int device = 0;
   std::vector<BatchGroup> groups;
@@ -110,13 +120,33 @@ int alloc_workspaces(ec_batch* b) {
   return EC_OK;
 }
 
+void release_prof(ec_batch* b) {
+  for (auto& r : b->prof)
+    for (int k = 0; k < 4; ++k) b->ev_pool.push_back(r.ev[k]);
+  b->prof.clear();
+}
+
 void drop_graph(ec_batch* b) {
   if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
   b->graph = StepGraph{};
 }
 
-int run_collide(ec_batch* b, const double* f, double* Q, double dt, hipStream_t s) {
+hipEvent_t take_event(ec_batch* b) {
+  if (!b->ev_pool.empty()) {
+    hipEvent_t e = b->ev_pool.back();
+    b->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int run_collide(ec_batch* b, const double* f, double* Q, double dt, hipStream_t s,
+                bool profile = false) {
+  int gi = -1;
   for (auto& g : b->groups) {
+    ++gi;
     const HostTables& T = g.plan->host;
     for (int64_t c0 = 0; c0 < g.count; c0 += g.chunk) {
       ChunkArgs a;
@@ -127,7 +157,18 @@ int run_collide(ec_batch* b, const double* f, double* Q, double dt, hipStream_t 
       a.cell0 = g.first + c0;
       a.ncells = (int)std::min<int64_t>(g.chunk, g.count - c0);
       a.dt = dt;
+      ProfRec rec{};
+      if (profile) {
+        rec.group = gi;
+        rec.ncells = a.ncells;
+        for (int k = 0; k < 4; ++k) {
+          rec.ev[k] = take_event(b);
+          if (!rec.ev[k]) return fail(EC_ERR_DEVICE, "hipEventCreate failed");
+        }
+        a.ev = rec.ev;
+      }
       HIPCHK(launch_chunk(a, s));
+      if (profile) b->prof.push_back(rec);
     }
   }
   return EC_OK;
@@ -264,6 +305,8 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
 int ec_batch_destroy(ec_batch* b) {
   if (!b) return EC_OK;
   drop_graph(b);
+  release_prof(b);
+  for (auto e : b->ev_pool) (void)hipEventDestroy(e);
   if (b->d_off) (void)hipFree(b->d_off);
   if (b->d_n) (void)hipFree(b->d_n);
   if (b->d_hd) (void)hipFree(b->d_hd);
@@ -304,7 +347,34 @@ int ec_collide(ec_batch* b, const double* f, double* Q, void* stream) {
     int rc = check_batch_ptrs(b, f, Q);
     if (rc) return rc;
     if (!Q) return fail(EC_ERR_ARG, "Q is null");
-    return run_collide(b, f, Q, 0.0, (hipStream_t)stream);
+    return run_collide(b, f, Q, 0.0, (hipStream_t)stream, b->profiling);
+  });
+}
+
+int ec_profile(ec_batch* b, int enable) {
+  if (!b) return fail(EC_ERR_ARG, "batch is null");
+  b->profiling = enable != 0;
+  return EC_OK;
+}
+
+int ec_profile_read(ec_batch* b, double* ms, int64_t* launches, int64_t* cells) {
+  return guarded([&]() -> int {
+    if (!b || !ms || !launches || !cells) return fail(EC_ERR_ARG, "null argument");
+    const int G = (int)b->groups.size();
+    for (int i = 0; i < 3 * G; ++i) { ms[i] = 0.0; launches[i] = 0; }
+    for (int g = 0; g < G; ++g) cells[g] = 0;
+    for (auto& r : b->prof) {
+      HIPCHK(hipEventSynchronize(r.ev[3]));
+      for (int k = 0; k < 3; ++k) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, r.ev[k], r.ev[k + 1]));
+        ms[3 * r.group + k] += t;
+        launches[3 * r.group + k] += 1;
+      }
+      cells[r.group] += r.ncells;
+    }
+    release_prof(b);
+    return EC_OK;
   });
 }
 
@@ -315,7 +385,7 @@ int ec_entropy_prod(ec_batch* b, const double* f, const double* Q, double* out,
     if (rc) return rc;
     if (!Q || !out) return fail(EC_ERR_ARG, "Q or out is null");
     HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, nullptr, out,
-                           n_nonpos, nullptr, nullptr, 0, (hipStream_t)stream));
+                           n_nonpos, nullptr, nullptr, 0, 0, (hipStream_t)stream));
     return EC_OK;
   });
 }
@@ -326,7 +396,7 @@ int ec_monitors(ec_batch* b, const double* f, const double* Q, double* out, void
     if (rc) return rc;
     if (!out) return fail(EC_ERR_ARG, "out is null");
     HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, out, nullptr,
-                           nullptr, nullptr, nullptr, 0, (hipStream_t)stream));
+                           nullptr, nullptr, nullptr, 0, 0, (hipStream_t)stream));
     return EC_OK;
   });
 }
@@ -338,24 +408,26 @@ int ec_step(ec_batch* b, double* f, double dt, int n_steps, double* monitors, vo
     if (n_steps < 0 || !(dt > 0.0)) return fail(EC_ERR_ARG, "need dt > 0 and n_steps >= 0");
     hipStream_t s = (hipStream_t)stream;
     if (n_steps == 0) return EC_OK;
-    if (!(b->graph.exec && b->graph.f == f && b->graph.dt == dt && b->graph.mon == monitors)) {
+    const int cap = monitors ? n_steps : 0;
+    if (!(b->graph.exec && b->graph.f == f && b->graph.dt == dt && b->graph.mon == monitors &&
+          b->graph.cap == cap)) {
       drop_graph(b);
       // capture one step; replays advance the device step counter
-      hipStream_t cap;
-      HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipStream_t cap_stream;
+      HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
       hipGraph_t graph = nullptr;
-      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
       int rc2 = EC_OK;
       if (e == hipSuccess) {
-        rc2 = run_collide(b, f, f, dt, cap);
+        rc2 = run_collide(b, f, f, dt, cap_stream);
         if (rc2 == EC_OK && monitors) {
           hipError_t e2 = launch_monitors(f, nullptr, b->d_off, b->d_n, b->d_hd, 0, b->n_cells,
                                           nullptr, nullptr, nullptr, b->d_step, monitors,
-                                          b->n_cells, cap);
-          if (e2 == hipSuccess) e2 = launch_inc_int(b->d_step, cap);
+                                          b->n_cells, n_steps, cap_stream);
+          if (e2 == hipSuccess) e2 = launch_inc_int(b->d_step, cap_stream);
           if (e2 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e2));
         }
-        hipError_t e3 = hipStreamEndCapture(cap, &graph);
+        hipError_t e3 = hipStreamEndCapture(cap_stream, &graph);
         if (rc2 == EC_OK && e3 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e3));
       } else {
         rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e));
@@ -365,11 +437,12 @@ int ec_step(ec_batch* b, double* f, double dt, int n_steps, double* monitors, vo
         if (e4 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e4));
       }
       if (graph) (void)hipGraphDestroy(graph);
-      (void)hipStreamDestroy(cap);
+      (void)hipStreamDestroy(cap_stream);
       if (rc2) { drop_graph(b); return rc2; }
       b->graph.f = f;
       b->graph.dt = dt;
       b->graph.mon = monitors;
+      b->graph.cap = cap;
     }
     HIPCHK(launch_set_int(b->d_step, 0, s));
     for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(b->graph.exec, s));

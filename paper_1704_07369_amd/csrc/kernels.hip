@@ -167,19 +167,24 @@ static hipError_t launch_chunk_t(const ChunkArgs& a, hipStream_t st) {
   const cx<R>* G = (const cx<R>*)a.gamma;
   cx<R>* W = (cx<R>*)a.W;
   cx<R>* Z = (cx<R>*)a.Z;
+  if (a.ev) (void)hipEventRecord(a.ev[0], st);
   hipLaunchKernelGGL((k_fwd<R, N0, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
                      a.f, a.off, a.cell0, a.ncells, W);
+  if (a.ev) (void)hipEventRecord(a.ev[1], st);
   if constexpr (N0 > 1) {
     const int64_t pencils = (int64_t)a.ncells * N * N;
     const int pblocks = (int)((pencils + PENCIL_BS - 1) / PENCIL_BS);
     hipLaunchKernelGGL((k_pencil<R, N0, N>), dim3(pblocks), dim3(PENCIL_BS), 0, st,
                        W, G, a.J, a.ncells, Z);
+    if (a.ev) (void)hipEventRecord(a.ev[2], st);
     hipLaunchKernelGGL((k_slab<R, N0, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
                        Z, G, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
   } else {
+    if (a.ev) (void)hipEventRecord(a.ev[2], st);
     hipLaunchKernelGGL((k_slab<R, 1, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
                        W, G, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
   }
+  if (a.ev) (void)hipEventRecord(a.ev[3], st);
   return hipGetLastError();
 }
 
@@ -216,7 +221,7 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
     const int64_t* __restrict__ off, const int* __restrict__ cell_n,
     const double* __restrict__ cell_hd, int64_t cell0, double* full,
     double* entprod, int32_t* n_nonpos, const int* step, double* step_mon,
-    int64_t step_stride) {
+    int64_t step_stride, int step_cap) {
   __shared__ double red[MON_Q][MON_BS];
   const int64_t c = cell0 + blockIdx.x;
   const double* fc = f + off[c];
@@ -271,7 +276,7 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
     }
     if (entprod) entprod[lc] = ep;
     if (n_nonpos) n_nonpos[lc] = (int32_t)red[7][0];
-    if (step_mon) {
+    if (step_mon && *step >= 0 && *step < step_cap) {
       double* o = step_mon + ((int64_t)(*step) * step_stride + lc) * 2;
       o[0] = mass;
       o[1] = eta;
@@ -283,11 +288,11 @@ hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
                            const int* cell_n, const double* cell_hd, int64_t cell0,
                            int64_t ncells, double* full, double* entprod,
                            int32_t* n_nonpos, const int* step, double* step_mon,
-                           int64_t step_stride, hipStream_t s) {
+                           int64_t step_stride, int step_cap, hipStream_t s) {
   if (ncells <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_monitors, dim3((unsigned)ncells), dim3(MON_BS), 0, s, f, Q, off,
                      cell_n, cell_hd, cell0, full, entprod, n_nonpos, step, step_mon,
-                     step_stride);
+                     step_stride, step_cap);
   return hipGetLastError();
 }
 

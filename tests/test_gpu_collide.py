@@ -180,15 +180,15 @@ def test_step_graph_matches_oracle_euler():
     b.step(f, dt, steps, mon)
     torch.cuda.synchronize()
     got = E.unpack(b, f.cpu().numpy())
-    mon = mon.cpu().numpy().reshape(steps, 2, 2)
+    monh = mon.cpu().numpy().reshape(steps, 2, 2)
     op = oplan(N, 3, L, M)
     for c in range(2):
         F = cells[c].copy()
         for s in range(steps):
             F = efm.fe_step(lambda u: efm.collide_modes(op, u).Q, F, dt)
             m = efm.monitors(op, F, np.zeros_like(F))
-            assert mon[s, c, 0] == pytest.approx(m["mass"], rel=1e-12)
-            assert mon[s, c, 1] == pytest.approx(m["eta"], rel=1e-11)
+            assert monh[s, c, 0] == pytest.approx(m["mass"], rel=1e-12)
+            assert monh[s, c, 1] == pytest.approx(m["eta"], rel=1e-11)
         assert np.abs(got[c] - F).max() <= 1e-12 * np.abs(F).max()
     # a second call replays the cached graph from the new state
     b.step(f, dt, 1, mon)
