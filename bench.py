@@ -29,7 +29,7 @@ METRIC = "collision evals/sec at N=32^3,M=32: FP64 vs mixed vs surrogate at stat
 PEAK_FP64 = 78.6    # TFLOP/s, MI355X vector FP64
 PEAK_FP32 = 157.3   # TFLOP/s, MI355X vector FP32
 N, D, L, M, R = 32, 3, 8.0, 32, 6.0
-KNAMES = ["k_fwd", "k_pencil", "k_slab"]
+KNAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe"]
 
 
 def log(msg):
@@ -79,6 +79,7 @@ def time_collide(E, torch, plan, cells, precision, steps, warmup, profile):
         ms, la, ce = b.profile_read()
         b.profile(False)
         prof = (ms[0], la[0], ce[0])
+    log(f"bench: schedule {b.get_schedule(0)}")
     return b, f, Q, (t1 - t0), prof
 
 
@@ -95,17 +96,19 @@ def sampled_error(E, b, Q, cells, cell_ids, oplan, efm, npts=64):
 
 
 def roofline(prof, flops_cell, peak):
+    """Dominant kernel of the timed region: algorithmic flops it performed
+    over its summed duration (HIP events on the launch stream)."""
     ms, launches, cells = prof
-    avg = [ms[k] / max(1, launches[k]) for k in range(3)]
-    k = max(range(3), key=lambda i: ms[i])
-    cells_per_launch = cells / max(1, launches[k])
-    achieved = flops_cell[k] * cells_per_launch / (avg[k] * 1e-3) / 1e12
+    k = max(range(len(ms)), key=lambda i: ms[i])
+    fl = sum(flops_cell) if KNAMES[k] == "k_pipe" else flops_cell[k]
+    achieved = fl * cells / (ms[k] * 1e-3) / 1e12
     return {
         "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4), "traffic": None, "kernel": KNAMES[k],
-        "avg_launch_ms": round(avg[k], 4), "cells_per_launch": cells_per_launch,
-        "flops_per_launch": flops_cell[k] * cells_per_launch,
-        "kernel_ms_per_step": {KNAMES[i]: round(ms[i], 3) for i in range(3)},
+        "avg_launch_ms": round(ms[k] / max(1, launches[k]), 5),
+        "launches": int(launches[k]), "cells_per_launch": cells / max(1, launches[k]),
+        "flops_per_launch": fl * cells / max(1, launches[k]),
+        "kernel_ms_total": {KNAMES[i]: round(float(ms[i]), 3) for i in range(len(ms))},
     }
 
 
@@ -130,6 +133,8 @@ def main():
     ap.add_argument("--cells", type=int, default=1024)
     ap.add_argument("--skip-cpu", action="store_true", help="omit the oracle timing")
     ap.add_argument("--skip-parity", action="store_true")
+    ap.add_argument("--skip-fp32", action="store_true", help="omit the FP32 side (profiling runs)")
+    ap.add_argument("--skip-single", action="store_true", help="omit single-cell latency")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): cells are independent, "
@@ -154,16 +159,20 @@ def main():
                                               args.warmup, True)
     ev64 = args.cells * args.steps / t64
     log(f"bench: FP64 {ev64:.4g} evals/s")
-    log("bench: FP32 timed region")
-    b32, f32, Q32, t32, prof32 = time_collide(E, torch, plan, cells, E.EC_FP32, args.steps,
-                                              args.warmup, True)
-    ev32 = args.cells * args.steps / t32
-    log(f"bench: FP32 {ev32:.4g} evals/s")
-    log("bench: single-cell latency")
-    one = cells[:1]
+    ev32 = t32 = prof32 = b32 = Q32 = None
+    if not args.skip_fp32:
+        log("bench: FP32 timed region")
+        b32, f32, Q32, t32, prof32 = time_collide(E, torch, plan, cells, E.EC_FP32, args.steps,
+                                                  args.warmup, True)
+        ev32 = args.cells * args.steps / t32
+        log(f"bench: FP32 {ev32:.4g} evals/s")
+    t1_64 = t1_32 = None
     reps = max(10, args.steps)
-    _, _, _, t1_64, _ = time_collide(E, torch, plan, one, E.EC_FP64, reps, 2, False)
-    _, _, _, t1_32, _ = time_collide(E, torch, plan, one, E.EC_FP32, reps, 2, False)
+    if not args.skip_single:
+        log("bench: single-cell latency")
+        one = cells[:1]
+        _, _, _, t1_64, _ = time_collide(E, torch, plan, one, E.EC_FP64, reps, 2, False)
+        _, _, _, t1_32, _ = time_collide(E, torch, plan, one, E.EC_FP32, reps, 2, False)
 
     out = {
         "metric": METRIC, "value": ev64, "unit": "evals/s", "n_gpus": 1,
@@ -175,10 +184,12 @@ def main():
                    "d": D, "N": N, "M": M, "L": L, "R": R, "cells": args.cells,
                    "kernel": "hard_sphere", "flops_per_eval": flops_eval},
         "roofline": roofline(prof64, flops, PEAK_FP64),
-        "fp32": {"value": ev32, "ms_per_step": t32 / args.steps * 1e3,
-                 "roofline": roofline(prof32, flops, PEAK_FP32)},
-        "single_cell": {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6},
     }
+    if ev32 is not None:
+        out["fp32"] = {"value": ev32, "ms_per_step": t32 / args.steps * 1e3,
+                       "roofline": roofline(prof32, flops, PEAK_FP32)}
+    if t1_64 is not None:
+        out["single_cell"] = {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6}
     if not args.skip_parity or not args.skip_cpu:
         from oracle import efm
         log("bench: oracle tables (quadrature)")
@@ -188,8 +199,10 @@ def main():
             out["parity"] = {
                 "metric": "max_r |Q - Q_oracle| / max_r |Q+_oracle| on 64 sampled points x 2 cells",
                 "fp64": sampled_error(E, b64, Q64, cells, [0, args.cells - 1], oplan, efm),
-                "fp32": sampled_error(E, b32, Q32, cells, [0, args.cells - 1], oplan, efm),
             }
+            if b32 is not None:
+                out["parity"]["fp32"] = sampled_error(E, b32, Q32, cells, [0, args.cells - 1],
+                                                      oplan, efm)
         if not args.skip_cpu:
             log("bench: CPU baseline (oracle)")
             out["cpu_baseline"] = cpu_baseline(cells, efm, oplan)

@@ -131,7 +131,25 @@ int ec_batch_destroy(ec_batch* batch);
 int ec_batch_size(const ec_batch* batch, int64_t* n_cells, int64_t* n_elems);
 /* offsets[c] = element offset of cell c (host array of n_cells). */
 int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
-/* Cells per pass of the slab/pencil pipeline (autotuned; 0 = default). */
+/*
+ * Execution schedule of the 3D groups (2D groups always use the two-pass
+ * schedule).  EC_SCHED_PIPELINE: one software-pipelined launch per chunk of
+ * cells_per_pass cells, whose four roles (forward transform, x pass, slab
+ * pass split into term_groups groups of terms, combine) work on four
+ * consecutive chunks, so the per-term intermediates of a chunk stay in the
+ * last-level cache.  EC_SCHED_TWO_PASS: three launches per chunk with the
+ * intermediates of the whole chunk in memory.  0 for cells_per_pass or
+ * term_groups selects the default (chosen from the cache size); the
+ * autotuner picks measured values.  Reallocates the workspace (synchronises
+ * the device); call it outside graph capture.
+ */
+#define EC_SCHED_PIPELINE 0
+#define EC_SCHED_TWO_PASS 1
+int ec_batch_set_schedule(ec_batch* batch, int group, int mode, int cells_per_pass,
+                          int term_groups);
+int ec_batch_get_schedule(const ec_batch* batch, int group, int* mode, int* cells_per_pass,
+                          int* term_groups);
+/* Shorthand: change only cells_per_pass of a group. */
 int ec_batch_set_chunk(ec_batch* batch, int group, int cells_per_pass);
 
 /*
@@ -178,14 +196,15 @@ int ec_step(ec_batch* batch, double* f, double dt, int n_steps,
             double* monitors, void* hip_stream);
 
 /*
- * Profiling of ec_collide (tracing).  While enabled, every pass of ec_collide
- * records HIP events on its stream around its three kernels (forward slab
- * transform, x-pencil pass, slab pass).  ec_profile_read waits for them and
- * returns, per group g of the batch, ms[3g + k] = summed duration of kernel k
- * and launches[3g + k] = number of launches, and cells[g] = cells processed;
- * then it forgets the records.  Host arrays of 3 * n_groups (cells: n_groups).
- * In 2D the x-pencil pass is empty (its duration is ~0).
+ * Profiling of ec_collide (tracing).  While enabled, ec_collide records HIP
+ * events on its stream around its kernels.  ec_profile_read waits for them and
+ * returns, per group g of the batch and kernel k (EC_PROF_KERNELS per group:
+ * 0 forward slab transform, 1 x-pencil pass, 2 slab pass of the two-pass
+ * schedule, 3 the pipelined kernel), ms[4g + k] = summed duration and
+ * launches[4g + k] = number of launches, and cells[g] = cells processed; then
+ * it forgets the records.  Host arrays of 4 * n_groups (cells: n_groups).
  */
+#define EC_PROF_KERNELS 4
 int ec_profile(ec_batch* batch, int enable);
 int ec_profile_read(ec_batch* batch, double* ms, int64_t* launches, int64_t* cells);
 

@@ -20,6 +20,9 @@ EC_ERR_ARG, EC_ERR_DEVICE, EC_ERR_OOM, EC_ERR_UNSUPPORTED, EC_ERR_DOMAIN = -1, -
 EC_KERNEL_MAXWELL, EC_KERNEL_HARD_SPHERE, EC_KERNEL_VHS = 0, 1, 2
 EC_FP64, EC_FP32 = 0, 1
 EC_NMON = 7
+EC_SCHED_PIPELINE, EC_SCHED_TWO_PASS = 0, 1
+EC_PROF_KERNELS = 4
+PROF_KERNEL_NAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe"]
 MON_NAMES = ["mass", "sumQ", "entropy_prod", "eta", "minF", "eps_pos", "sumabsQ"]
 
 _c_int, _c_double, _c_i64, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_void_p
@@ -54,6 +57,9 @@ _SIGS = {
     "ec_entropy_prod": ([_vp, _vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_monitors": ([_vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_step": ([_vp, _vp, _c_double, _c_int, _vp, _vp], _c_int),
+    "ec_batch_set_schedule": ([_vp, _c_int, _c_int, _c_int, _c_int], _c_int),
+    "ec_batch_get_schedule": ([_vp, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
+                               ctypes.POINTER(_c_int)], _c_int),
     "ec_profile": ([_vp, _c_int], _c_int),
     "ec_profile_read": ([_vp, ctypes.POINTER(_c_double), ctypes.POINTER(_c_i64),
                          ctypes.POINTER(_c_i64)], _c_int),
@@ -209,11 +215,22 @@ def ec_profile(batch, enable=True):
     return _check(lib().ec_profile(batch, 1 if enable else 0))
 
 
+def ec_batch_set_schedule(batch, group, mode, cells_per_pass=0, term_groups=0):
+    return _check(lib().ec_batch_set_schedule(batch, group, mode, cells_per_pass, term_groups))
+
+
+def ec_batch_get_schedule(batch, group):
+    m, c, g = _c_int(), _c_int(), _c_int()
+    _check(lib().ec_batch_get_schedule(batch, group, ctypes.byref(m), ctypes.byref(c),
+                                       ctypes.byref(g)))
+    return m.value, c.value, g.value
+
+
 def ec_profile_read(batch, n_groups):
-    ms = np.zeros(3 * n_groups)
-    la = np.zeros(3 * n_groups, dtype=np.int64)
+    ms = np.zeros(EC_PROF_KERNELS * n_groups)
+    la = np.zeros(EC_PROF_KERNELS * n_groups, dtype=np.int64)
     ce = np.zeros(n_groups, dtype=np.int64)
     _check(lib().ec_profile_read(batch, ms.ctypes.data_as(ctypes.POINTER(_c_double)),
                                  la.ctypes.data_as(ctypes.POINTER(_c_i64)),
                                  ce.ctypes.data_as(ctypes.POINTER(_c_i64))))
-    return ms.reshape(n_groups, 3), la.reshape(n_groups, 3), ce
+    return ms.reshape(n_groups, EC_PROF_KERNELS), la.reshape(n_groups, EC_PROF_KERNELS), ce

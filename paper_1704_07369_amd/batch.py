@@ -58,6 +58,12 @@ class Batch:
     def set_chunk(self, group, cells):
         B.ec_batch_set_chunk(self.handle, group, cells)
 
+    def set_schedule(self, group, mode, cells=0, term_groups=0):
+        B.ec_batch_set_schedule(self.handle, group, mode, cells, term_groups)
+
+    def get_schedule(self, group):
+        return B.ec_batch_get_schedule(self.handle, group)
+
     def collide(self, f, Q, stream=None):
         B.ec_collide(self.handle, f, Q, stream)
 

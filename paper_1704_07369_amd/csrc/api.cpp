@@ -11,6 +11,7 @@
 
 #include "../../include/ec.h"
 #include "kernels.h"
+#include "pipe.h"
 #include "plan.h"
 
 using namespace efm;
@@ -57,7 +58,9 @@ struct BatchGroup {
   const ec_plan* plan = nullptr;
   int64_t count = 0;
   int64_t first = 0;   // first batch cell of the group
-  int chunk = 0;       // cells per pass
+  int mode = 0;        // EC_SCHED_PIPELINE or EC_SCHED_TWO_PASS (3D); 2D is always two-pass
+  int chunk = 0;       // cells per pass / per pipeline chunk
+  int G = 1;           // term groups (pipeline)
 };
 
 struct StepGraph {
@@ -71,6 +74,7 @@ struct StepGraph {
 struct ProfRec {
   int group;
   int ncells;
+  int kind;            // 0: two-pass chunk (3 kernels), 1: one pipeline launch
   hipEvent_t ev[4];
 };
 
@@ -86,39 +90,63 @@ struct ec_batch {
   int64_t* d_off = nullptr;
   int* d_n = nullptr;
   double* d_hd = nullptr;
-  void* d_W = nullptr;
-  void* d_Z = nullptr;
-  size_t W_bytes = 0, Z_bytes = 0;
+  void* d_ws = nullptr;     // workspace shared by the groups (one at a time)
+  size_t ws_bytes = 0;
   int* d_step = nullptr;
   StepGraph graph;
 };
 
 namespace {
 
-int default_chunk(const HostTables& T, int64_t count) {
-  // aim for about 2048 waves in the slab pass (N0 * N threads per cell)
-  const int64_t threads_per_cell = (int64_t)T.n0 * T.n1;
-  int64_t c = (2048 * 64 + threads_per_cell - 1) / threads_per_cell;
-  c = std::max<int64_t>(1, std::min<int64_t>(c, count));
-  return (int)c;
+size_t csize(int precision) { return precision == EC_FP32 ? 8 : 16; }
+
+void default_schedule(BatchGroup& g, int precision) {
+  const HostTables& T = g.plan->host;
+  const int64_t count = std::max<int64_t>(1, g.count);
+  if (T.d == 3 && g.mode == EC_SCHED_PIPELINE) {
+    // keep one slot of the per-term intermediates under ~96 MB (the MALL holds
+    // the slot being written and the slot being read), then split the terms so
+    // the slab role has about 1024 blocks
+    const double per_cell = (double)T.J * T.n * csize(precision);
+    int64_t c = (int64_t)std::max(1.0, std::floor(96.0 * 1048576.0 / per_cell));
+    g.chunk = (int)std::min<int64_t>(c, count);
+    const int spb = (T.N == 24 || T.N == 12 ? 96 : 64) / T.N;
+    const int64_t slab_blocks = ((int64_t)g.chunk * T.N + spb - 1) / spb;
+    int G = (int)std::max<int64_t>(1, (1024 + slab_blocks - 1) / slab_blocks);
+    g.G = std::min(G, std::min(T.J, 16));
+  } else {
+    // two-pass: aim for about 2048 waves in the slab pass (N0 * N threads per cell)
+    const int64_t threads_per_cell = (int64_t)T.n0 * T.n1;
+    int64_t c = (2048 * 64 + threads_per_cell - 1) / threads_per_cell;
+    g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, count));
+    g.G = 1;
+  }
+}
+
+bool use_pipe(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_PIPELINE; }
+
+size_t group_ws_bytes(const BatchGroup& g, int precision) {
+  const HostTables& T = g.plan->host;
+  const size_t cs = csize(precision);
+  const size_t n = (size_t)T.n;
+  if (use_pipe(g))
+    return 2 * ((size_t)g.chunk * n * cs + (size_t)g.chunk * T.J * n * cs +
+                (size_t)g.G * g.chunk * n * 8 + (size_t)g.chunk * n * 8) + 8 * 256;
+  size_t bytes = (size_t)g.chunk * n * cs + 256;
+  if (T.d == 3) bytes += (size_t)g.chunk * T.J * n * cs + 256;
+  return bytes;
 }
 
 int alloc_workspaces(ec_batch* b) {
-  const size_t cs = b->precision == EC_FP32 ? 8 : 16;
-  size_t wmax = 0, zmax = 0;
-  for (auto& g : b->groups) {
-    const HostTables& T = g.plan->host;
-    wmax = std::max(wmax, (size_t)g.chunk * T.n * cs);
-    if (T.d == 3) zmax = std::max(zmax, (size_t)g.chunk * T.J * T.n * cs);
-  }
-  if (b->d_W) { (void)hipFree(b->d_W); b->d_W = nullptr; }
-  if (b->d_Z) { (void)hipFree(b->d_Z); b->d_Z = nullptr; }
-  b->W_bytes = wmax;
-  b->Z_bytes = zmax;
-  if (wmax && hipMalloc(&b->d_W, wmax) != hipSuccess) return fail(EC_ERR_OOM, "workspace W");
-  if (zmax && hipMalloc(&b->d_Z, zmax) != hipSuccess) return fail(EC_ERR_OOM, "workspace Z");
+  size_t need = 0;
+  for (auto& g : b->groups) need = std::max(need, group_ws_bytes(g, b->precision));
+  if (b->d_ws) { (void)hipFree(b->d_ws); b->d_ws = nullptr; }
+  b->ws_bytes = need;
+  if (need && hipMalloc(&b->d_ws, need) != hipSuccess) return fail(EC_ERR_OOM, "workspace");
   return EC_OK;
 }
+
+char* align256(char* p) { return (char*)(((uintptr_t)p + 255) & ~(uintptr_t)255); }
 
 void release_prof(ec_batch* b) {
   for (auto& r : b->prof)
@@ -142,34 +170,89 @@ hipEvent_t take_event(ec_batch* b) {
   return e;
 }
 
+int take_events(ec_batch* b, ProfRec& rec) {
+  for (int k = 0; k < 4; ++k) {
+    rec.ev[k] = take_event(b);
+    if (!rec.ev[k]) return fail(EC_ERR_DEVICE, "hipEventCreate failed");
+  }
+  return EC_OK;
+}
+
+int run_group_two_pass(ec_batch* b, int gi, const double* f, double* Q, double dt,
+                       hipStream_t s, bool profile) {
+  const BatchGroup& g = b->groups[gi];
+  const HostTables& T = g.plan->host;
+  const size_t cs = csize(b->precision);
+  char* W = align256((char*)b->d_ws);
+  char* Z = align256(W + (size_t)g.chunk * T.n * cs);
+  for (int64_t c0 = 0; c0 < g.count; c0 += g.chunk) {
+    ChunkArgs a;
+    a.N = T.N; a.d = T.d; a.precision = b->precision; a.J = T.J;
+    a.gamma = b->precision == EC_FP32 ? g.plan->d_gamma32 : g.plan->d_gamma64;
+    a.W = W; a.Z = T.d == 3 ? Z : nullptr;
+    a.f = f; a.Q = Q; a.off = b->d_off;
+    a.cell0 = g.first + c0;
+    a.ncells = (int)std::min<int64_t>(g.chunk, g.count - c0);
+    a.dt = dt;
+    ProfRec rec{};
+    if (profile) {
+      rec.group = gi; rec.ncells = a.ncells; rec.kind = 0;
+      int rc = take_events(b, rec);
+      if (rc) return rc;
+      a.ev = rec.ev;
+    }
+    HIPCHK(launch_chunk(a, s));
+    if (profile) b->prof.push_back(rec);
+  }
+  return EC_OK;
+}
+
+int run_group_pipe(ec_batch* b, int gi, const double* f, double* Q, double dt, hipStream_t s,
+                   bool profile) {
+  const BatchGroup& g = b->groups[gi];
+  const HostTables& T = g.plan->host;
+  const size_t cs = csize(b->precision);
+  const size_t n = (size_t)T.n;
+  PipeArgs base;
+  base.gamma = b->precision == EC_FP32 ? g.plan->d_gamma32 : g.plan->d_gamma64;
+  base.J = T.J; base.G = g.G; base.chunk = g.chunk;
+  base.f = f; base.Q = Q; base.off = b->d_off; base.dt = dt;
+  char* p = (char*)b->d_ws;
+  for (int k = 0; k < 2; ++k) { p = align256(p); base.W[k] = p; p += (size_t)g.chunk * n * cs; }
+  for (int k = 0; k < 2; ++k) { p = align256(p); base.Z[k] = p; p += (size_t)g.chunk * T.J * n * cs; }
+  for (int k = 0; k < 2; ++k) { p = align256(p); base.Pg[k] = (double*)p; p += (size_t)g.G * g.chunk * n * 8; }
+  for (int k = 0; k < 2; ++k) { p = align256(p); base.Lr[k] = (double*)p; p += (size_t)g.chunk * n * 8; }
+  const int64_t nch = (g.count + g.chunk - 1) / g.chunk;
+  auto cells_of = [&](int64_t k) { return (int)std::min<int64_t>(g.chunk, g.count - k * g.chunk); };
+  for (int64_t i = 0; i < nch + 3; ++i) {
+    PipeArgs a = base;
+    if (i < nch) { a.f_cell0 = g.first + i * g.chunk; a.f_n = cells_of(i); a.f_slot = (int)(i & 1); }
+    if (i - 1 >= 0 && i - 1 < nch) { a.p_cell0 = g.first + (i - 1) * g.chunk; a.p_n = cells_of(i - 1); a.p_slot = (int)((i - 1) & 1); }
+    if (i - 2 >= 0 && i - 2 < nch) { a.s_cell0 = g.first + (i - 2) * g.chunk; a.s_n = cells_of(i - 2); a.s_slot = (int)((i - 2) & 1); }
+    if (i - 3 >= 0 && i - 3 < nch) { a.c_cell0 = g.first + (i - 3) * g.chunk; a.c_n = cells_of(i - 3); a.c_slot = (int)((i - 3) & 1); }
+    ProfRec rec{};
+    if (profile) {
+      rec.group = gi; rec.ncells = a.c_n; rec.kind = 1;
+      int rc = take_events(b, rec);
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(rec.ev[0], s));
+    }
+    HIPCHK(launch_pipe(a, T.N, b->precision, s));
+    if (profile) {
+      HIPCHK(hipEventRecord(rec.ev[3], s));
+      b->prof.push_back(rec);
+    }
+  }
+  return EC_OK;
+}
+
 int run_collide(ec_batch* b, const double* f, double* Q, double dt, hipStream_t s,
                 bool profile = false) {
-  int gi = -1;
-  for (auto& g : b->groups) {
-    ++gi;
-    const HostTables& T = g.plan->host;
-    for (int64_t c0 = 0; c0 < g.count; c0 += g.chunk) {
-      ChunkArgs a;
-      a.N = T.N; a.d = T.d; a.precision = b->precision; a.J = T.J;
-      a.gamma = b->precision == EC_FP32 ? g.plan->d_gamma32 : g.plan->d_gamma64;
-      a.W = b->d_W; a.Z = b->d_Z;
-      a.f = f; a.Q = Q; a.off = b->d_off;
-      a.cell0 = g.first + c0;
-      a.ncells = (int)std::min<int64_t>(g.chunk, g.count - c0);
-      a.dt = dt;
-      ProfRec rec{};
-      if (profile) {
-        rec.group = gi;
-        rec.ncells = a.ncells;
-        for (int k = 0; k < 4; ++k) {
-          rec.ev[k] = take_event(b);
-          if (!rec.ev[k]) return fail(EC_ERR_DEVICE, "hipEventCreate failed");
-        }
-        a.ev = rec.ev;
-      }
-      HIPCHK(launch_chunk(a, s));
-      if (profile) b->prof.push_back(rec);
-    }
+  for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
+    if (b->groups[gi].count == 0) continue;
+    int rc = use_pipe(b->groups[gi]) ? run_group_pipe(b, gi, f, Q, dt, s, profile)
+                                     : run_group_two_pass(b, gi, f, Q, dt, s, profile);
+    if (rc) return rc;
   }
   return EC_OK;
 }
@@ -266,7 +349,8 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
       bg.plan = plans[g];
       bg.count = counts[g];
       bg.first = cell;
-      bg.chunk = default_chunk(plans[g]->host, std::max<int64_t>(1, counts[g]));
+      bg.mode = EC_SCHED_PIPELINE;
+      default_schedule(bg, precision);
       const HostTables& T = plans[g]->host;
       const double hd = std::pow(2.0 * T.L / T.N, T.d);
       for (int64_t c = 0; c < counts[g]; ++c) {
@@ -310,8 +394,7 @@ int ec_batch_destroy(ec_batch* b) {
   if (b->d_off) (void)hipFree(b->d_off);
   if (b->d_n) (void)hipFree(b->d_n);
   if (b->d_hd) (void)hipFree(b->d_hd);
-  if (b->d_W) (void)hipFree(b->d_W);
-  if (b->d_Z) (void)hipFree(b->d_Z);
+  if (b->d_ws) (void)hipFree(b->d_ws);
   if (b->d_step) (void)hipFree(b->d_step);
   delete b;
   return EC_OK;
@@ -330,16 +413,35 @@ int ec_batch_offsets(const ec_batch* b, int64_t* offsets) {
   return EC_OK;
 }
 
-int ec_batch_set_chunk(ec_batch* b, int group, int cells_per_pass) {
+int ec_batch_set_schedule(ec_batch* b, int group, int mode, int cells_per_pass, int term_groups) {
   return guarded([&]() -> int {
     if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
+    if (mode != EC_SCHED_PIPELINE && mode != EC_SCHED_TWO_PASS) return fail(EC_ERR_ARG, "bad mode");
     BatchGroup& g = b->groups[group];
-    int c = cells_per_pass > 0 ? cells_per_pass : default_chunk(g.plan->host, std::max<int64_t>(1, g.count));
-    g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, std::max<int64_t>(1, g.count)));
+    g.mode = mode;
+    default_schedule(g, b->precision);
+    const int64_t count = std::max<int64_t>(1, g.count);
+    if (cells_per_pass > 0) g.chunk = (int)std::min<int64_t>(cells_per_pass, count);
+    if (term_groups > 0 && use_pipe(g)) g.G = std::min(term_groups, g.plan->host.J);
     drop_graph(b);
     HIPCHK(hipDeviceSynchronize());
     return alloc_workspaces(b);
   });
+}
+
+int ec_batch_set_chunk(ec_batch* b, int group, int cells_per_pass) {
+  if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
+  return ec_batch_set_schedule(b, group, b->groups[group].mode, cells_per_pass, 0);
+}
+
+int ec_batch_get_schedule(const ec_batch* b, int group, int* mode, int* cells_per_pass,
+                          int* term_groups) {
+  if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
+  const BatchGroup& g = b->groups[group];
+  if (mode) *mode = use_pipe(g) ? EC_SCHED_PIPELINE : EC_SCHED_TWO_PASS;
+  if (cells_per_pass) *cells_per_pass = g.chunk;
+  if (term_groups) *term_groups = g.G;
+  return EC_OK;
 }
 
 int ec_collide(ec_batch* b, const double* f, double* Q, void* stream) {
@@ -361,15 +463,22 @@ int ec_profile_read(ec_batch* b, double* ms, int64_t* launches, int64_t* cells) 
   return guarded([&]() -> int {
     if (!b || !ms || !launches || !cells) return fail(EC_ERR_ARG, "null argument");
     const int G = (int)b->groups.size();
-    for (int i = 0; i < 3 * G; ++i) { ms[i] = 0.0; launches[i] = 0; }
+    for (int i = 0; i < EC_PROF_KERNELS * G; ++i) { ms[i] = 0.0; launches[i] = 0; }
     for (int g = 0; g < G; ++g) cells[g] = 0;
     for (auto& r : b->prof) {
       HIPCHK(hipEventSynchronize(r.ev[3]));
-      for (int k = 0; k < 3; ++k) {
+      if (r.kind == 0) {
+        for (int k = 0; k < 3; ++k) {
+          float t = 0.f;
+          HIPCHK(hipEventElapsedTime(&t, r.ev[k], r.ev[k + 1]));
+          ms[EC_PROF_KERNELS * r.group + k] += t;
+          launches[EC_PROF_KERNELS * r.group + k] += 1;
+        }
+      } else {
         float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, r.ev[k], r.ev[k + 1]));
-        ms[3 * r.group + k] += t;
-        launches[3 * r.group + k] += 1;
+        HIPCHK(hipEventElapsedTime(&t, r.ev[0], r.ev[3]));
+        ms[EC_PROF_KERNELS * r.group + 3] += t;
+        launches[EC_PROF_KERNELS * r.group + 3] += 1;
       }
       cells[r.group] += r.ncells;
     }
