@@ -60,8 +60,13 @@ def make_cells(n_cells, seed0=2001):
     return [synth.sample_mixture(synth.mixture_anisotropic(seed0 + c, D), N, L) for c in range(n_cells)]
 
 
+SCHED = {"mode": None, "chunk": 0, "G": 0}
+
+
 def time_collide(E, torch, plan, cells, precision, steps, warmup, profile):
     b = E.Batch([plan], [len(cells)], precision)
+    if SCHED["mode"] is not None:
+        b.set_schedule(0, SCHED["mode"], SCHED["chunk"], SCHED["G"])
     f = torch.from_numpy(E.pack(b, cells)).to("cuda:0")
     Q = torch.zeros_like(f)
     for _ in range(warmup):
@@ -135,6 +140,11 @@ def main():
     ap.add_argument("--skip-parity", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true", help="omit the FP32 side (profiling runs)")
     ap.add_argument("--skip-single", action="store_true", help="omit single-cell latency")
+    ap.add_argument("--schedule", choices=["auto", "pipeline", "two_pass"], default="auto")
+    ap.add_argument("--chunk", type=int, default=0, help="cells per pass/chunk (0 = default)")
+    ap.add_argument("--term-groups", type=int, default=0)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run ec_copy on a buffer of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): cells are independent, "
@@ -147,6 +157,18 @@ def main():
     import paper_1704_07369_amd as E
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.schedule != "auto":
+        SCHED["mode"] = E.EC_SCHED_PIPELINE if args.schedule == "pipeline" else E.EC_SCHED_TWO_PASS
+        SCHED["chunk"], SCHED["G"] = args.chunk, args.term_groups
+    if args.copy_mb:
+        nc = args.copy_mb * 1048576 // 8
+        a = torch.ones(nc, dtype=torch.float64, device="cuda:0")
+        bb = torch.zeros_like(a)
+        for _ in range(3):
+            E.ec_copy(a, bb, nc)
+        torch.cuda.synchronize()
+        log(f"bench: ec_copy of {args.copy_mb} MiB x3 done (16 n bytes each)")
+        del a, bb
     log(f"bench: building {args.cells} cells of {N}^3")
     cells = make_cells(args.cells)
     plan = E.Plan(N, D, L, M, R=R)

@@ -208,6 +208,13 @@ int ec_step(ec_batch* batch, double* f, double dt, int n_steps,
 int ec_profile(ec_batch* batch, int enable);
 int ec_profile_read(ec_batch* batch, double* ms, int64_t* launches, int64_t* cells);
 
+/*
+ * ec_copy -- dst[i] = src[i], i < n, with a plain grid-stride copy kernel
+ * (k_copy).  Used to calibrate hardware byte counters: its algorithmic
+ * traffic is exactly 16 n bytes.  Device arrays, must not overlap.
+ */
+int ec_copy(const double* src, double* dst, int64_t n, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* ec_last_error(void);
 

@@ -60,6 +60,7 @@ _SIGS = {
     "ec_batch_set_schedule": ([_vp, _c_int, _c_int, _c_int, _c_int], _c_int),
     "ec_batch_get_schedule": ([_vp, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
                                ctypes.POINTER(_c_int)], _c_int),
+    "ec_copy": ([_vp, _vp, _c_i64, _vp], _c_int),
     "ec_profile": ([_vp, _c_int], _c_int),
     "ec_profile_read": ([_vp, ctypes.POINTER(_c_double), ctypes.POINTER(_c_i64),
                          ctypes.POINTER(_c_i64)], _c_int),
@@ -234,3 +235,7 @@ def ec_profile_read(batch, n_groups):
                                  la.ctypes.data_as(ctypes.POINTER(_c_i64)),
                                  ce.ctypes.data_as(ctypes.POINTER(_c_i64))))
     return ms.reshape(n_groups, EC_PROF_KERNELS), la.reshape(n_groups, EC_PROF_KERNELS), ce
+
+
+def ec_copy(src, dst, n, stream=None):
+    return _check(lib().ec_copy(_ptr(src), _ptr(dst), n, _stream(stream)))

@@ -453,6 +453,12 @@ int ec_collide(ec_batch* b, const double* f, double* Q, void* stream) {
   });
 }
 
+int ec_copy(const double* src, double* dst, int64_t n, void* stream) {
+  if (!src || !dst || n < 0) return fail(EC_ERR_ARG, "bad copy arguments");
+  HIPCHK(launch_copy(src, dst, n, (hipStream_t)stream));
+  return EC_OK;
+}
+
 int ec_profile(ec_batch* b, int enable) {
   if (!b) return fail(EC_ERR_ARG, "batch is null");
   b->profiling = enable != 0;

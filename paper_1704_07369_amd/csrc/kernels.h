@@ -41,6 +41,7 @@ hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
                            int32_t* n_nonpos, const int* step, double* step_mon,
                            int64_t step_stride, int step_cap, hipStream_t s);
 
+hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 hipError_t launch_inc_int(int* p, hipStream_t s);
 

@@ -296,6 +296,19 @@ hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_copy(const double* __restrict__ a, double* __restrict__ b,
+                                              int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) b[i] = a[i];
+}
+
+hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(8192), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
 __global__ void k_set_int(int* p, int v) { *p = v; }
 __global__ void k_inc_int(int* p) { *p += 1; }
 
