@@ -61,6 +61,7 @@ def make_cells(n_cells, seed0=2001):
 
 
 SCHED = {"mode": None, "chunk": 0, "G": 0}
+TUNE_CACHE = os.path.join(ROOT, "paper_1704_07369_amd", "tune_cache.txt")
 
 
 def time_collide(E, torch, plan, cells, precision, steps, warmup, profile):
@@ -69,6 +70,8 @@ def time_collide(E, torch, plan, cells, precision, steps, warmup, profile):
         b.set_schedule(0, SCHED["mode"], SCHED["chunk"], SCHED["G"])
     f = torch.from_numpy(E.pack(b, cells)).to("cuda:0")
     Q = torch.zeros_like(f)
+    if SCHED["mode"] is None and len(cells) > 1:
+        b.autotune(f, Q, TUNE_CACHE)
     for _ in range(warmup):
         b.collide(f, Q)
     torch.cuda.synchronize()
@@ -117,6 +120,43 @@ def roofline(prof, flops_cell, peak):
     }
 
 
+def relaxation_leg(E, torch, steps=200, dt=0.01, n_cells=4096, seed=3000):
+    """Batched space-homogeneous relaxation: n_cells cells with grids mixed
+    16^3/24^3/32^3 (40/35/25 %, seeded permutation), hard spheres, M = 32,
+    FP64, `steps` forward-Euler steps replayed from one captured HIP graph,
+    per-cell (mass, eta) after every step."""
+    import numpy as np
+    import synth
+    sizes = synth.batch_mixed_sizes(seed, n_cells)
+    groups = [16, 24, 32]
+    plans = [E.Plan(Ng, D, L, M, R=R) for Ng in groups]
+    counts = [int((sizes == Ng).sum()) for Ng in groups]
+    order = [c for Ng in groups for c in np.nonzero(sizes == Ng)[0]]
+    cells = [synth.sample_mixture(synth.mixture_anisotropic(3001 + int(c), D), int(sizes[c]), L)
+             for c in order]
+    b = E.Batch(plans, counts, E.EC_FP64)
+    f = torch.from_numpy(E.pack(b, cells)).to("cuda:0")
+    Q = torch.zeros_like(f)
+    b.autotune(f, Q, TUNE_CACHE)
+    mon = torch.zeros(steps * n_cells * 2, dtype=torch.float64, device="cuda:0")
+    b.step(f, dt, 1, mon)          # graph capture + warm-up
+    f.copy_(torch.from_numpy(E.pack(b, cells)).to("cuda:0"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(f, dt, steps, mon)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    m = mon.view(steps, n_cells, 2).cpu().numpy()
+    mass_drift = float(np.max(np.abs(m[-1, :, 0] - m[0, :, 0]) / m[0, :, 0]))
+    deta = np.diff(m[:, :, 1], axis=0)
+    fmin = float(f.min().item())
+    return {"workload": f"{n_cells} cells mixed 16^3/24^3/32^3 ({counts}), hard sphere, M=32, "
+                        f"FP64, {steps} forward-Euler steps dt={dt} in one HIP graph",
+            "seconds": t, "cell_evals_per_s": n_cells * steps / t, "ms_per_step": t / steps * 1e3,
+            "max_rel_mass_drift": mass_drift, "max_eta_increase": float(deta.max()),
+            "min_F": fmin}
+
+
 def cpu_baseline(cells, efm, oplan):
     """The oracle (plain double sum over modes, OpenMP) on one cell of the
     workload; evals/s = 1 / time of one full evaluation."""
@@ -143,6 +183,7 @@ def main():
     ap.add_argument("--schedule", choices=["auto", "pipeline", "two_pass"], default="auto")
     ap.add_argument("--chunk", type=int, default=0, help="cells per pass/chunk (0 = default)")
     ap.add_argument("--term-groups", type=int, default=0)
+    ap.add_argument("--skip-relax", action="store_true", help="omit the mixed-N relaxation leg")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run ec_copy on a buffer of this size (counter calibration)")
     args = ap.parse_args()
@@ -212,6 +253,9 @@ def main():
                        "roofline": roofline(prof32, flops, PEAK_FP32)}
     if t1_64 is not None:
         out["single_cell"] = {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6}
+    if not args.skip_relax:
+        log("bench: mixed-N relaxation leg (200 graph-replayed FE steps)")
+        out["relaxation"] = relaxation_leg(E, torch)
     if not args.skip_parity or not args.skip_cpu:
         from oracle import efm
         log("bench: oracle tables (quadrature)")

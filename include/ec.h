@@ -149,6 +149,19 @@ int ec_batch_set_schedule(ec_batch* batch, int group, int mode, int cells_per_pa
                           int term_groups);
 int ec_batch_get_schedule(const ec_batch* batch, int group, int* mode, int* cells_per_pass,
                           int* term_groups);
+/*
+ * ec_autotune -- measure candidate schedules of every group on the device
+ * (two-pass with several chunk sizes; for 3D also the pipelined schedule over
+ * chunk sizes and term groups), keep the fastest, and append it to the text
+ * cache at cache_path (one line per key "arch|d|N|M|kind|L|R|precision|cells";
+ * NULL or "" = no cache).  A cached key is applied without measuring unless
+ * flags has EC_TUNE_REMEASURE.  f should hold representative cells; Q is
+ * overwritten.  Synchronises the stream; not capturable.
+ */
+#define EC_TUNE_REMEASURE 1
+int ec_autotune(ec_batch* batch, const double* f, double* Q, const char* cache_path, int flags,
+                void* hip_stream);
+
 /* Shorthand: change only cells_per_pass of a group. */
 int ec_batch_set_chunk(ec_batch* batch, int group, int cells_per_pass);
 

@@ -22,6 +22,7 @@ EC_FP64, EC_FP32 = 0, 1
 EC_NMON = 7
 EC_SCHED_PIPELINE, EC_SCHED_TWO_PASS = 0, 1
 EC_PROF_KERNELS = 4
+EC_TUNE_REMEASURE = 1
 PROF_KERNEL_NAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe"]
 MON_NAMES = ["mass", "sumQ", "entropy_prod", "eta", "minF", "eps_pos", "sumabsQ"]
 
@@ -61,6 +62,7 @@ _SIGS = {
     "ec_batch_get_schedule": ([_vp, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
                                ctypes.POINTER(_c_int)], _c_int),
     "ec_copy": ([_vp, _vp, _c_i64, _vp], _c_int),
+    "ec_autotune": ([_vp, _vp, _vp, ctypes.c_char_p, _c_int, _vp], _c_int),
     "ec_profile": ([_vp, _c_int], _c_int),
     "ec_profile_read": ([_vp, ctypes.POINTER(_c_double), ctypes.POINTER(_c_i64),
                          ctypes.POINTER(_c_i64)], _c_int),
@@ -239,3 +241,8 @@ def ec_profile_read(batch, n_groups):
 
 def ec_copy(src, dst, n, stream=None):
     return _check(lib().ec_copy(_ptr(src), _ptr(dst), n, _stream(stream)))
+
+
+def ec_autotune(batch, f, Q, cache_path=None, flags=0, stream=None):
+    cp = cache_path.encode() if cache_path else None
+    return _check(lib().ec_autotune(batch, _ptr(f), _ptr(Q), cp, flags, _stream(stream)))

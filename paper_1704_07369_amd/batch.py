@@ -61,6 +61,10 @@ class Batch:
     def set_schedule(self, group, mode, cells=0, term_groups=0):
         B.ec_batch_set_schedule(self.handle, group, mode, cells, term_groups)
 
+    def autotune(self, f, Q, cache_path=None, remeasure=False, stream=None):
+        B.ec_autotune(self.handle, f, Q, cache_path, B.EC_TUNE_REMEASURE if remeasure else 0,
+                      stream)
+
     def get_schedule(self, group):
         return B.ec_batch_get_schedule(self.handle, group)
 

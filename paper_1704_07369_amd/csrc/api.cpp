@@ -3,7 +3,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <exception>
 #include <new>
 #include <string>
@@ -68,7 +71,6 @@ struct StepGraph {
   double* f = nullptr;
   double dt = 0.0;
   double* mon = nullptr;
-  int cap = 0;
 };
 
 struct ProfRec {
@@ -378,7 +380,7 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
         return fail(EC_ERR_DEVICE, "upload of batch metadata failed");
       }
     }
-    if (hipMalloc(&b->d_step, sizeof(int)) != hipSuccess) { ec_batch_destroy(b); return fail(EC_ERR_OOM, "step counter"); }
+    if (hipMalloc(&b->d_step, 2 * sizeof(int)) != hipSuccess) { ec_batch_destroy(b); return fail(EC_ERR_OOM, "step counter"); }
     int rc = alloc_workspaces(b);
     if (rc) { ec_batch_destroy(b); return rc; }
     *out = b;
@@ -453,6 +455,132 @@ int ec_collide(ec_batch* b, const double* f, double* Q, void* stream) {
   });
 }
 
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Sched {
+  int mode, chunk, G;
+};
+
+std::string tune_key(int dev, const HostTables& T, int precision, int64_t count) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|d%d|N%d|M%d|kind%d|L%.6g|R%.6g|prec%d|cells%lld", arch.c_str(),
+                T.d, T.N, T.M, T.kind, T.L, T.R, precision, (long long)count);
+  return buf;
+}
+
+// cache format: one line per key, "<key> <mode> <chunk> <G> <ms>"
+bool cache_lookup(const char* path, const std::string& key, Sched& out) {
+  if (!path || !*path) return false;
+  std::ifstream in(path);
+  if (!in) return false;
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string k;
+    Sched s{};
+    double ms;
+    if (ls >> k >> s.mode >> s.chunk >> s.G >> ms && k == key) { out = s; found = true; }
+  }
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const Sched& s, double ms) {
+  if (!path || !*path) return;
+  std::ofstream outf(path, std::ios::app);
+  if (outf) outf << key << ' ' << s.mode << ' ' << s.chunk << ' ' << s.G << ' ' << ms << '\n';
+}
+
+int apply_sched(ec_batch* b, int gi, const Sched& s) {
+  BatchGroup& g = b->groups[gi];
+  g.mode = s.mode;
+  default_schedule(g, b->precision);
+  const int64_t count = std::max<int64_t>(1, g.count);
+  if (s.chunk > 0) g.chunk = (int)std::min<int64_t>(s.chunk, count);
+  if (s.G > 0 && use_pipe(g)) g.G = std::min(s.G, g.plan->host.J);
+  return alloc_workspaces(b);
+}
+
+int time_group(ec_batch* b, int gi, const double* f, double* Q, hipStream_t st, double& best_ms) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  best_ms = 1e30;
+  int rc = EC_OK;
+  for (int r = 0; r < 4 && rc == EC_OK; ++r) {
+    (void)hipEventRecord(e0, st);
+    rc = use_pipe(b->groups[gi]) ? run_group_pipe(b, gi, f, Q, 0.0, st, false)
+                                 : run_group_two_pass(b, gi, f, Q, 0.0, st, false);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) rc = fail(EC_ERR_DEVICE, "autotune run failed");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (r > 0) best_ms = std::min(best_ms, (double)ms);   // first run is a warm-up
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+}  // namespace
+
+int ec_autotune(ec_batch* b, const double* f, double* Q, const char* cache_path, int flags,
+                void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_batch_ptrs(b, f, Q);
+    if (rc) return rc;
+    if (!Q) return fail(EC_ERR_ARG, "Q is null");
+    hipStream_t st = (hipStream_t)stream;
+    drop_graph(b);
+    for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
+      BatchGroup& g = b->groups[gi];
+      if (g.count == 0) continue;
+      const HostTables& T = g.plan->host;
+      const std::string key = tune_key(b->device, T, b->precision, g.count);
+      Sched best{};
+      if (!(flags & EC_TUNE_REMEASURE) && cache_lookup(cache_path, key, best)) {
+        rc = apply_sched(b, gi, best);
+        if (rc) return rc;
+        continue;
+      }
+      std::vector<Sched> cand;
+      const int64_t count = g.count;
+      for (int c : {16, 32, 64, 128, 256, 1024, 4096}) {
+        Sched s{EC_SCHED_TWO_PASS, (int)std::min<int64_t>(c, count), 0};
+        bool dup = false;
+        for (auto& x : cand) dup |= (x.mode == s.mode && x.chunk == s.chunk);
+        if (!dup) cand.push_back(s);
+      }
+      if (T.d == 3) {
+        for (int c : {4, 6, 8, 12, 16, 24})
+          for (int G : {1, 2, 4, 8}) {
+            if (c > count && c != 4) continue;
+            cand.push_back(Sched{EC_SCHED_PIPELINE, (int)std::min<int64_t>(c, count), G});
+          }
+      }
+      double best_ms = 1e30;
+      for (auto& s : cand) {
+        rc = apply_sched(b, gi, s);
+        if (rc) return rc;
+        double ms;
+        rc = time_group(b, gi, f, Q, st, ms);
+        if (rc) return rc;
+        if (ms < best_ms) { best_ms = ms; best = s; }
+      }
+      rc = apply_sched(b, gi, best);
+      if (rc) return rc;
+      cache_store(cache_path, key, best, best_ms);
+    }
+    return EC_OK;
+  });
+}
+
 int ec_copy(const double* src, double* dst, int64_t n, void* stream) {
   if (!src || !dst || n < 0) return fail(EC_ERR_ARG, "bad copy arguments");
   HIPCHK(launch_copy(src, dst, n, (hipStream_t)stream));
@@ -500,7 +628,7 @@ int ec_entropy_prod(ec_batch* b, const double* f, const double* Q, double* out,
     if (rc) return rc;
     if (!Q || !out) return fail(EC_ERR_ARG, "Q or out is null");
     HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, nullptr, out,
-                           n_nonpos, nullptr, nullptr, 0, 0, (hipStream_t)stream));
+                           n_nonpos, nullptr, nullptr, 0, nullptr, (hipStream_t)stream));
     return EC_OK;
   });
 }
@@ -511,7 +639,7 @@ int ec_monitors(ec_batch* b, const double* f, const double* Q, double* out, void
     if (rc) return rc;
     if (!out) return fail(EC_ERR_ARG, "out is null");
     HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, out, nullptr,
-                           nullptr, nullptr, nullptr, 0, 0, (hipStream_t)stream));
+                           nullptr, nullptr, nullptr, 0, nullptr, (hipStream_t)stream));
     return EC_OK;
   });
 }
@@ -523,9 +651,7 @@ int ec_step(ec_batch* b, double* f, double dt, int n_steps, double* monitors, vo
     if (n_steps < 0 || !(dt > 0.0)) return fail(EC_ERR_ARG, "need dt > 0 and n_steps >= 0");
     hipStream_t s = (hipStream_t)stream;
     if (n_steps == 0) return EC_OK;
-    const int cap = monitors ? n_steps : 0;
-    if (!(b->graph.exec && b->graph.f == f && b->graph.dt == dt && b->graph.mon == monitors &&
-          b->graph.cap == cap)) {
+    if (!(b->graph.exec && b->graph.f == f && b->graph.dt == dt && b->graph.mon == monitors)) {
       drop_graph(b);
       // capture one step; replays advance the device step counter
       hipStream_t cap_stream;
@@ -538,7 +664,7 @@ int ec_step(ec_batch* b, double* f, double dt, int n_steps, double* monitors, vo
         if (rc2 == EC_OK && monitors) {
           hipError_t e2 = launch_monitors(f, nullptr, b->d_off, b->d_n, b->d_hd, 0, b->n_cells,
                                           nullptr, nullptr, nullptr, b->d_step, monitors,
-                                          b->n_cells, n_steps, cap_stream);
+                                          b->n_cells, b->d_step + 1, cap_stream);
           if (e2 == hipSuccess) e2 = launch_inc_int(b->d_step, cap_stream);
           if (e2 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e2));
         }
@@ -557,9 +683,10 @@ int ec_step(ec_batch* b, double* f, double dt, int n_steps, double* monitors, vo
       b->graph.f = f;
       b->graph.dt = dt;
       b->graph.mon = monitors;
-      b->graph.cap = cap;
     }
+    // step counter and the capacity of the monitor buffer (in steps)
     HIPCHK(launch_set_int(b->d_step, 0, s));
+    HIPCHK(launch_set_int(b->d_step + 1, monitors ? n_steps : 0, s));
     for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(b->graph.exec, s));
     return EC_OK;
   });

@@ -33,13 +33,14 @@ hipError_t launch_chunk(const ChunkArgs& a, hipStream_t s);
 // Per-cell reductions (fixed order, deterministic).  Any output may be null.
 //   full:    [cell][EC_NMON]
 //   entprod: [cell]      n_nonpos: [cell]
-//   step_mon: (mass, eta) at [(*step) * step_stride + cell][2], step read on
-//             device; nothing is written once *step >= step_cap
+//   step_mon: (mass, eta) at [(*step) * step_stride + cell][2]; step and the
+//             capacity step_cap are read on device; nothing is written once
+//             *step >= *step_cap
 hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
                            const int* cell_n, const double* cell_hd, int64_t cell0,
                            int64_t ncells, double* full, double* entprod,
                            int32_t* n_nonpos, const int* step, double* step_mon,
-                           int64_t step_stride, int step_cap, hipStream_t s);
+                           int64_t step_stride, const int* step_cap, hipStream_t s);
 
 hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);

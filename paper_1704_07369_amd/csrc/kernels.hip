@@ -221,7 +221,7 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
     const int64_t* __restrict__ off, const int* __restrict__ cell_n,
     const double* __restrict__ cell_hd, int64_t cell0, double* full,
     double* entprod, int32_t* n_nonpos, const int* step, double* step_mon,
-    int64_t step_stride, int step_cap) {
+    int64_t step_stride, const int* step_cap) {
   __shared__ double red[MON_Q][MON_BS];
   const int64_t c = cell0 + blockIdx.x;
   const double* fc = f + off[c];
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
     }
     if (entprod) entprod[lc] = ep;
     if (n_nonpos) n_nonpos[lc] = (int32_t)red[7][0];
-    if (step_mon && *step >= 0 && *step < step_cap) {
+    if (step_mon && *step >= 0 && *step < step_cap[0]) {
       double* o = step_mon + ((int64_t)(*step) * step_stride + lc) * 2;
       o[0] = mass;
       o[1] = eta;
@@ -288,7 +288,7 @@ hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
                            const int* cell_n, const double* cell_hd, int64_t cell0,
                            int64_t ncells, double* full, double* entprod,
                            int32_t* n_nonpos, const int* step, double* step_mon,
-                           int64_t step_stride, int step_cap, hipStream_t s) {
+                           int64_t step_stride, const int* step_cap, hipStream_t s) {
   if (ncells <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_monitors, dim3((unsigned)ncells), dim3(MON_BS), 0, s, f, Q, off,
                      cell_n, cell_hd, cell0, full, entprod, n_nonpos, step, step_mon,
