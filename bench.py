@@ -229,6 +229,13 @@ def main():
                                                   args.warmup, True)
         ev32 = args.cells * args.steps / t32
         log(f"bench: FP32 {ev32:.4g} evals/s")
+    evb = tb = profb = bb = Qb = None
+    if not args.skip_fp32:
+        log("bench: split-BF16 MFMA x pass timed region")
+        bb, fb, Qb, tb, profb = time_collide(E, torch, plan, cells, E.EC_BF16X3, args.steps,
+                                             args.warmup, True)
+        evb = args.cells * args.steps / tb
+        log(f"bench: BF16x3 {evb:.4g} evals/s")
     t1_64 = t1_32 = None
     reps = max(10, args.steps)
     if not args.skip_single:
@@ -251,6 +258,9 @@ def main():
     if ev32 is not None:
         out["fp32"] = {"value": ev32, "ms_per_step": t32 / args.steps * 1e3,
                        "roofline": roofline(prof32, flops, PEAK_FP32)}
+    if evb is not None:
+        out["bf16x3"] = {"value": evb, "ms_per_step": tb / args.steps * 1e3,
+                         "roofline": roofline(profb, flops, PEAK_FP32)}
     if t1_64 is not None:
         out["single_cell"] = {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6}
     if not args.skip_relax:
@@ -269,6 +279,9 @@ def main():
             if b32 is not None:
                 out["parity"]["fp32"] = sampled_error(E, b32, Q32, cells, [0, args.cells - 1],
                                                       oplan, efm)
+            if bb is not None:
+                out["parity"]["bf16x3"] = sampled_error(E, bb, Qb, cells, [0, args.cells - 1],
+                                                        oplan, efm)
         if not args.skip_cpu:
             log("bench: CPU baseline (oracle)")
             out["cpu_baseline"] = cpu_baseline(cells, efm, oplan)

@@ -69,6 +69,10 @@ typedef struct ec_kernel {
 #define EC_FP64   0   /* transforms, products and sums in FP64              */
 #define EC_FP32   1   /* transforms and products in FP32, sum over terms,
                          loss combine and reductions in FP64                */
+#define EC_BF16X3 2   /* as EC_FP32, but the inverse DFT along x of every term
+                         runs on MFMA as a real (2N x 2N) DFT-matrix product
+                         with split-BF16 operands (hi*hi + hi*lo + lo*hi, FP32
+                         accumulate); 3D cells with N = 16 or 32 only        */
 
 typedef struct ec_plan ec_plan;
 typedef struct ec_batch ec_batch;
@@ -118,7 +122,7 @@ int ec_host_tables(int N, int d, double L, const ec_kernel* kernel, int M,
  * ec_batch_create -- a packed batch of cells grouped by plan.
  *   plans[g], counts[g]: group g holds counts[g] cells of plans[g] (the plans
  *   must stay alive while the batch exists).
- *   precision: EC_FP64 or EC_FP32.
+ *   precision: EC_FP64, EC_FP32 or EC_BF16X3.
  * Layout of f and Q for every call on the batch: cells in group order, each
  * cell N_g^d contiguous FP64 values starting at a 256-byte aligned element
  * offset (ec_batch_offsets).  Workspaces for all later calls are allocated

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libefm.so")
 EC_OK = 0
 EC_ERR_ARG, EC_ERR_DEVICE, EC_ERR_OOM, EC_ERR_UNSUPPORTED, EC_ERR_DOMAIN = -1, -2, -3, -4, -5
 EC_KERNEL_MAXWELL, EC_KERNEL_HARD_SPHERE, EC_KERNEL_VHS = 0, 1, 2
-EC_FP64, EC_FP32 = 0, 1
+EC_FP64, EC_FP32, EC_BF16X3 = 0, 1, 2
 EC_NMON = 7
 EC_SCHED_PIPELINE, EC_SCHED_TWO_PASS = 0, 1
 EC_PROF_KERNELS = 4

@@ -100,11 +100,12 @@ struct ec_batch {
 
 namespace {
 
-size_t csize(int precision) { return precision == EC_FP32 ? 8 : 16; }
+size_t csize(int precision) { return precision == EC_FP64 ? 16 : 8; }
 
 void default_schedule(BatchGroup& g, int precision) {
   const HostTables& T = g.plan->host;
   const int64_t count = std::max<int64_t>(1, g.count);
+  if (precision == EC_BF16X3) g.mode = EC_SCHED_TWO_PASS;   // the MFMA x pass is a separate kernel
   if (T.d == 3 && g.mode == EC_SCHED_PIPELINE) {
     // keep one slot of the per-term intermediates under ~96 MB (the MALL holds
     // the slot being written and the slot being read), then split the terms so
@@ -126,6 +127,7 @@ void default_schedule(BatchGroup& g, int precision) {
 }
 
 bool use_pipe(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_PIPELINE; }
+bool fp32_tables(int precision) { return precision != EC_FP64; }
 
 size_t group_ws_bytes(const BatchGroup& g, int precision) {
   const HostTables& T = g.plan->host;
@@ -190,7 +192,7 @@ int run_group_two_pass(ec_batch* b, int gi, const double* f, double* Q, double d
   for (int64_t c0 = 0; c0 < g.count; c0 += g.chunk) {
     ChunkArgs a;
     a.N = T.N; a.d = T.d; a.precision = b->precision; a.J = T.J;
-    a.gamma = b->precision == EC_FP32 ? g.plan->d_gamma32 : g.plan->d_gamma64;
+    a.gamma = fp32_tables(b->precision) ? g.plan->d_gamma32 : g.plan->d_gamma64;
     a.W = W; a.Z = T.d == 3 ? Z : nullptr;
     a.f = f; a.Q = Q; a.off = b->d_off;
     a.cell0 = g.first + c0;
@@ -216,7 +218,7 @@ int run_group_pipe(ec_batch* b, int gi, const double* f, double* Q, double dt, h
   const size_t cs = csize(b->precision);
   const size_t n = (size_t)T.n;
   PipeArgs base;
-  base.gamma = b->precision == EC_FP32 ? g.plan->d_gamma32 : g.plan->d_gamma64;
+  base.gamma = fp32_tables(b->precision) ? g.plan->d_gamma32 : g.plan->d_gamma64;
   base.J = T.J; base.G = g.G; base.chunk = g.chunk;
   base.f = f; base.Q = Q; base.off = b->d_off; base.dt = dt;
   char* p = (char*)b->d_ws;
@@ -337,7 +339,13 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
                     int precision, ec_batch** out) {
   return guarded([&]() -> int {
     if (!plans || !counts || !out || n_groups < 1) return fail(EC_ERR_ARG, "null argument or no groups");
-    if (precision != EC_FP64 && precision != EC_FP32) return fail(EC_ERR_ARG, "precision");
+    if (precision != EC_FP64 && precision != EC_FP32 && precision != EC_BF16X3)
+      return fail(EC_ERR_ARG, "precision");
+    if (precision == EC_BF16X3)
+      for (int g = 0; g < n_groups; ++g)
+        if (plans[g] && counts[g] > 0 &&
+            !(plans[g]->host.d == 3 && (plans[g]->host.N == 16 || plans[g]->host.N == 32)))
+          return fail(EC_ERR_UNSUPPORTED, "split-BF16 transforms need 3D cells with N = 16 or 32");
     *out = nullptr;
     auto* b = new ec_batch();
     b->precision = precision;

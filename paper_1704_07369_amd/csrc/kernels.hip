@@ -22,6 +22,7 @@
 #include "kernels.h"
 
 #include "fft.h"
+#include "mfma.h"
 
 namespace efm {
 
@@ -172,10 +173,15 @@ static hipError_t launch_chunk_t(const ChunkArgs& a, hipStream_t st) {
                      a.f, a.off, a.cell0, a.ncells, W);
   if (a.ev) (void)hipEventRecord(a.ev[1], st);
   if constexpr (N0 > 1) {
-    const int64_t pencils = (int64_t)a.ncells * N * N;
-    const int pblocks = (int)((pencils + PENCIL_BS - 1) / PENCIL_BS);
-    hipLaunchKernelGGL((k_pencil<R, N0, N>), dim3(pblocks), dim3(PENCIL_BS), 0, st,
-                       W, G, a.J, a.ncells, Z);
+    if (a.precision == 2) {
+      hipError_t e = launch_pencil_bf16(W, G, a.J, a.ncells, Z, N, st);
+      if (e != hipSuccess) return e;
+    } else {
+      const int64_t pencils = (int64_t)a.ncells * N * N;
+      const int pblocks = (int)((pencils + PENCIL_BS - 1) / PENCIL_BS);
+      hipLaunchKernelGGL((k_pencil<R, N0, N>), dim3(pblocks), dim3(PENCIL_BS), 0, st,
+                         W, G, a.J, a.ncells, Z);
+    }
     if (a.ev) (void)hipEventRecord(a.ev[2], st);
     hipLaunchKernelGGL((k_slab<R, N0, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
                        Z, G, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
@@ -207,7 +213,7 @@ static hipError_t launch_chunk_r(const ChunkArgs& a, hipStream_t st) {
 
 hipError_t launch_chunk(const ChunkArgs& a, hipStream_t st) {
   if (a.ncells <= 0) return hipSuccess;
-  return a.precision == 1 ? launch_chunk_r<float>(a, st) : launch_chunk_r<double>(a, st);
+  return a.precision != 0 ? launch_chunk_r<float>(a, st) : launch_chunk_r<double>(a, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -108,6 +108,39 @@ def test_fp32_parity():
             assert err <= TOL32
 
 
+TOLBF = 5e-4
+
+
+def test_bf16x3_parity():
+    """Split-BF16 MFMA x pass: 16^3 full grid and 32^3 sampled points."""
+    say("case bf16x3")
+    for (N, ncell) in [(16, 2), (32, 2)]:
+        L = 8.0
+        p = E.Plan(N, 3, L, 32, R=R)
+        cells = mixtures(3, N, L, ncell, 9000 + N)
+        out, _ = run_collide(E, [p], [ncell], cells, E.EC_BF16X3)
+        op = oplan(N, 3, L, 32)
+        for c in range(ncell):
+            if N == 16:
+                ref = efm.collide_modes(op, cells[c])
+                err = rel_err(out[c], ref.Q, ref.Qplus)
+            else:
+                idx = np.random.default_rng(c).choice(N ** 3, 48, replace=False)
+                q, qp, _, _ = efm.collide_points(op, cells[c], idx)
+                err = np.abs(out[c].ravel()[idx] - q).max() / np.abs(qp).max()
+            say(f"  N={N} cell {c}: rel err {err:.3e}")
+            assert err <= TOLBF
+
+
+def test_bf16x3_rejects_unsupported_sizes():
+    say("case bf16x3 unsupported")
+    for (N, d) in [(24, 3), (16, 2)]:
+        p = E.Plan(N, d, 8.0, 8, R=R)
+        with pytest.raises(E.EcError) as ei:
+            E.Batch([p], [1], E.EC_BF16X3)
+        assert ei.value.code == E.EC_ERR_UNSUPPORTED
+
+
 def test_mixed_batch_parity():
     """Groups of 16^3, 24^3 and 32^3 cells in one batch (and an empty group)."""
     say("case mixed batch 16/24/32 + empty group")
