@@ -232,6 +232,50 @@ int ec_profile_read(ec_batch* batch, double* ms, int64_t* launches, int64_t* cel
  */
 int ec_copy(const double* src, double* dst, int64_t n, void* hip_stream);
 
+/* ---- learned surrogate ---------------------------------------------------
+ * A Fourier neural operator that predicts Q / mass^2 from F / mass on the
+ * N^3 grid (Q is quadratic in F): lift 1 -> C channels, `layers` layers
+ * u <- GELU(W u + b + S(u)) (no GELU after the last), projection C -> 1;
+ * S keeps the modes kx, ky in [-modes, modes), kz in [0, modes) with complex
+ * C x C weights per mode.  FP32 parameters, trained by the library's own
+ * forward, backward and Adam kernels on (F, Q) pairs of the exact operator.
+ * Supported (N, modes, channels): (32, 12, 16), (16, 6, 8), (8, 2, 4).
+ */
+typedef struct ec_surrogate ec_surrogate;
+int ec_surrogate_create(int N, int modes, int channels, int layers, uint64_t seed, int max_batch,
+                        ec_surrogate** out);
+int ec_surrogate_destroy(ec_surrogate* s);
+int ec_surrogate_num_params(const ec_surrogate* s, int64_t* n);
+/* Host copies of the flat FP32 parameter / last-gradient vector (num_params
+ * floats; layout: Wl[C], bl[C], then per layer W[C][C], b[C], R[modes][C][C]
+ * as (re, im) pairs, then Wp[C], bp).  set_params resets the Adam state. */
+int ec_surrogate_get_params(const ec_surrogate* s, float* host);
+int ec_surrogate_set_params(ec_surrogate* s, const float* host);
+int ec_surrogate_get_grads(const ec_surrogate* s, float* host);
+/* Normalised training inputs of cells cell0 .. cell0+B-1 of a batch (one
+ * group of 3D cells of the surrogate's N): Fin = F / mass and, if Q and
+ * target are not NULL, target = Q / mass^2 (device [B][N^3] FP32). */
+int ec_surrogate_prepare(ec_surrogate* s, const ec_batch* batch, const double* f, const double* Q,
+                         int64_t cell0, int B, float* Fin, float* target, void* hip_stream);
+/* y = network(Fin), device [B][N^3] FP32, B <= max_batch. */
+int ec_surrogate_forward(ec_surrogate* s, const float* Fin, float* y, int B, void* hip_stream);
+/* One forward + backward (per-sample relative squared error, averaged) and,
+ * if update != 0, one Adam step (lr, beta 0.9/0.999).  If loss != NULL the
+ * mean loss is returned (synchronises the stream). */
+int ec_surrogate_train_step(ec_surrogate* s, const float* Fin, const float* target, int B,
+                            float lr, int update, double* loss, void* hip_stream);
+/* Screened inference on a batch (one group of 3D cells of the surrogate's N):
+ * Q = mass^2 network(F / mass); a cell passes the screen when its discrete
+ * H-functional h^3 sum_{F>0} Q ln F <= 0 (Theorem 1), |sum Q| <= tau_m
+ * sum |Q| and the momentum and energy residuals |sum Q v| / (L sum|Q|),
+ * |sum Q |v|^2| / (3 L^2 sum|Q|) are <= tau_e.  Every failing cell is
+ * recomputed with the exact operator (ec_collide on a compacted batch).
+ * Optional device outputs: fell_back[c] (0/1), screen[c*4 + {P, mass, mom,
+ * energy residual}]; host output n_fallback.  Synchronises the stream. */
+int ec_surrogate_collide(ec_surrogate* s, ec_batch* batch, const double* f, double* Q,
+                         double tau_m, double tau_e, int32_t* fell_back, double* screen,
+                         int64_t* n_fallback, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* ec_last_error(void);
 

@@ -63,6 +63,19 @@ _SIGS = {
                                ctypes.POINTER(_c_int)], _c_int),
     "ec_copy": ([_vp, _vp, _c_i64, _vp], _c_int),
     "ec_autotune": ([_vp, _vp, _vp, ctypes.c_char_p, _c_int, _vp], _c_int),
+    "ec_surrogate_create": ([_c_int, _c_int, _c_int, _c_int, ctypes.c_uint64, _c_int,
+                             ctypes.POINTER(_vp)], _c_int),
+    "ec_surrogate_destroy": ([_vp], _c_int),
+    "ec_surrogate_num_params": ([_vp, ctypes.POINTER(_c_i64)], _c_int),
+    "ec_surrogate_get_params": ([_vp, _vp], _c_int),
+    "ec_surrogate_set_params": ([_vp, _vp], _c_int),
+    "ec_surrogate_get_grads": ([_vp, _vp], _c_int),
+    "ec_surrogate_prepare": ([_vp, _vp, _vp, _vp, _c_i64, _c_int, _vp, _vp, _vp], _c_int),
+    "ec_surrogate_forward": ([_vp, _vp, _vp, _c_int, _vp], _c_int),
+    "ec_surrogate_train_step": ([_vp, _vp, _vp, _c_int, ctypes.c_float, _c_int,
+                                 ctypes.POINTER(_c_double), _vp], _c_int),
+    "ec_surrogate_collide": ([_vp, _vp, _vp, _vp, _c_double, _c_double, _vp, _vp,
+                              ctypes.POINTER(_c_i64), _vp], _c_int),
     "ec_profile": ([_vp, _c_int], _c_int),
     "ec_profile_read": ([_vp, ctypes.POINTER(_c_double), ctypes.POINTER(_c_i64),
                          ctypes.POINTER(_c_i64)], _c_int),
@@ -246,3 +259,61 @@ def ec_copy(src, dst, n, stream=None):
 def ec_autotune(batch, f, Q, cache_path=None, flags=0, stream=None):
     cp = cache_path.encode() if cache_path else None
     return _check(lib().ec_autotune(batch, _ptr(f), _ptr(Q), cp, flags, _stream(stream)))
+
+
+def ec_surrogate_create(N, modes, channels, layers, seed, max_batch):
+    h = _vp()
+    _check(lib().ec_surrogate_create(N, modes, channels, layers, seed, max_batch, ctypes.byref(h)))
+    return h.value
+
+
+def ec_surrogate_destroy(s):
+    return _check(lib().ec_surrogate_destroy(s))
+
+
+def ec_surrogate_num_params(s):
+    n = _c_i64()
+    _check(lib().ec_surrogate_num_params(s, ctypes.byref(n)))
+    return n.value
+
+
+def ec_surrogate_get_params(s):
+    out = np.empty(ec_surrogate_num_params(s), dtype=np.float32)
+    _check(lib().ec_surrogate_get_params(s, out.ctypes.data))
+    return out
+
+
+def ec_surrogate_set_params(s, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == ec_surrogate_num_params(s)
+    return _check(lib().ec_surrogate_set_params(s, p.ctypes.data))
+
+
+def ec_surrogate_get_grads(s):
+    out = np.empty(ec_surrogate_num_params(s), dtype=np.float32)
+    _check(lib().ec_surrogate_get_grads(s, out.ctypes.data))
+    return out
+
+
+def ec_surrogate_prepare(s, batch, f, Q, cell0, B, Fin, target, stream=None):
+    return _check(lib().ec_surrogate_prepare(s, batch, _ptr(f), _ptr(Q), cell0, B, _ptr(Fin),
+                                             _ptr(target), _stream(stream)))
+
+
+def ec_surrogate_forward(s, Fin, y, B, stream=None):
+    return _check(lib().ec_surrogate_forward(s, _ptr(Fin), _ptr(y), B, _stream(stream)))
+
+
+def ec_surrogate_train_step(s, Fin, target, B, lr, update=True, want_loss=True, stream=None):
+    loss = _c_double(float("nan"))
+    _check(lib().ec_surrogate_train_step(s, _ptr(Fin), _ptr(target), B, lr, 1 if update else 0,
+                                         ctypes.byref(loss) if want_loss else None,
+                                         _stream(stream)))
+    return loss.value
+
+
+def ec_surrogate_collide(s, batch, f, Q, tau_m, tau_e, fell_back=None, screen=None, stream=None):
+    nf = _c_i64()
+    _check(lib().ec_surrogate_collide(s, batch, _ptr(f), _ptr(Q), tau_m, tau_e, _ptr(fell_back),
+                                      _ptr(screen), ctypes.byref(nf), _stream(stream)))
+    return nf.value

@@ -22,14 +22,14 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function"]
-SOURCES = ["kernels.hip", "pipe.hip", "mfma.hip", "api.cpp", "plan.cpp"]
+SOURCES = ["kernels.hip", "pipe.hip", "mfma.hip", "fno.hip", "api.cpp", "surrogate.cpp", "plan.cpp"]
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
-        cmd[1:1] = ["-x", "hip"] if src == "api.cpp" else []
+        cmd[1:1] = ["-x", "hip"] if src in ("api.cpp", "surrogate.cpp") else []
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

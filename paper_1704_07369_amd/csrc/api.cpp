@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/ec.h"
+#include "internal.h"
 #include "kernels.h"
 #include "pipe.h"
 #include "plan.h"
@@ -49,6 +50,10 @@ int guarded(F&& fn) {
 }
 
 }  // namespace
+
+namespace efm {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace efm
 
 struct ec_plan {
   HostTables host;
@@ -269,6 +274,29 @@ int check_batch_ptrs(ec_batch* b, const void* f, const void* Q) {
 }
 
 }  // namespace
+
+namespace efm {
+const int64_t* batch_offsets_dev(const ec_batch* b) { return b->d_off; }
+int64_t batch_cells(const ec_batch* b) { return b->n_cells; }
+int64_t batch_elems(const ec_batch* b) { return b->n_elems; }
+int batch_groups(const ec_batch* b) { return (int)b->groups.size(); }
+const ec_plan* batch_group_plan(const ec_batch* b, int g) { return b->groups[g].plan; }
+int64_t batch_group_count(const ec_batch* b, int g) { return b->groups[g].count; }
+int plan_N(const ec_plan* p) { return p->host.N; }
+int plan_d(const ec_plan* p) { return p->host.d; }
+double plan_L(const ec_plan* p) { return p->host.L; }
+
+int collide_prefix(ec_batch* b, int64_t n_active, const double* f, double* Q, hipStream_t s) {
+  if (n_active <= 0) return EC_OK;
+  BatchGroup& g = b->groups[0];
+  const int64_t saved = g.count;
+  g.count = std::min(saved, n_active);
+  int rc = use_pipe(g) ? run_group_pipe(b, 0, f, Q, 0.0, s, false)
+                       : run_group_two_pass(b, 0, f, Q, 0.0, s, false);
+  g.count = saved;
+  return rc;
+}
+}  // namespace efm
 
 extern "C" {
 
