@@ -157,6 +157,105 @@ def relaxation_leg(E, torch, steps=200, dt=0.01, n_cells=4096, seed=3000):
             "min_F": fmin}
 
 
+def surrogate_leg(E, torch, seconds=40.0, n_traj=500, n_steps=100, n_test=1024, dt=0.01, log_fn=None):
+    """Learned surrogate at the headline size: (F, Q) pairs from n_traj
+    forward-Euler trajectories of the exact FP64 operator (seeds 5001 + i,
+    n_steps steps each), training by the library's own kernels for `seconds`,
+    then n_test fresh cells (seeds 6001 + i): relative L2 error of the raw
+    network and of the screened result against the FP64 operator, fallback
+    count, and evals/s of the screened path (network, screen and fallback
+    inside the timed region) beside the exact operator's."""
+    import numpy as np
+    import synth
+    from paper_1704_07369_amd.surrogate import DEFAULT, Surrogate, generate_pairs, train
+    plan = E.Plan(N, D, L, M, R=R)
+    sur = Surrogate(N, seed=1234, max_batch=64, **DEFAULT)
+    t0 = time.perf_counter()
+    cells = [synth.sample_mixture(synth.mixture_anisotropic(5001 + i, D), N, L) for i in range(n_traj)]
+    Fin, Tgt = generate_pairs(torch, plan, cells, n_steps, dt, sur)
+    t_gen = time.perf_counter() - t0
+    del cells
+    hist, steps = train(torch, sur, Fin, Tgt, seconds=seconds, batch=16, lr=2e-3, log=log_fn)
+    npairs = int(Fin.shape[0])
+    del Fin, Tgt
+    torch.cuda.empty_cache()
+    test = [synth.sample_mixture(synth.mixture_anisotropic(6001 + i, D), N, L) for i in range(n_test)]
+    b = E.Batch([plan], [n_test], E.EC_FP64)
+    f = torch.from_numpy(E.pack(b, test)).to("cuda:0")
+    Qe = torch.zeros_like(f)
+    b.autotune(f, Qe, TUNE_CACHE)
+    b.collide(f, Qe)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        b.collide(f, Qe)
+    torch.cuda.synchronize()
+    t_exact = (time.perf_counter() - t0) / 3
+    # raw network output (no screen), per-cell relative L2 error
+    n = N ** D
+    mb = sur.max_batch
+    xin = torch.empty((mb, n), dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(xin)
+    Qr = torch.empty((n_test, n), dtype=torch.float64, device="cuda:0")
+    h3 = (2 * L / N) ** 3
+    c0 = (2 * math.pi) ** 1.5
+    fv = f.view(n_test, n)
+    for c in range(0, n_test, mb):
+        k = min(mb, n_test - c)
+        sur.prepare(b, f, None, c, k, xin[:k], None)
+        sur.forward(xin[:k], y[:k], k)
+        mass = h3 * fv[c:c + k].sum(1, keepdim=True)
+        Qr[c:c + k] = y[:k].double() * mass ** 2 / c0 ** 2
+    Qev = Qe.view(n_test, n)
+    raw = ((Qr - Qev).norm(dim=1) / Qev.norm(dim=1)).cpu().numpy()
+    Qs = torch.zeros_like(f)
+    fell = torch.zeros(n_test, dtype=torch.int32, device="cuda:0")
+    sur.collide(b, f, Qs, tau_m=-1.0, fell_back=fell)       # screen off: projected network
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        sur.collide(b, f, Qs, tau_m=-1.0, fell_back=fell)
+    torch.cuda.synchronize()
+    t_net = (time.perf_counter() - t0) / 3
+    proj = ((Qs.view(n_test, n) - Qev).norm(dim=1) / Qev.norm(dim=1)).cpu().numpy()
+    scr_d = torch.zeros(n_test * 4, dtype=torch.float64, device="cuda:0")
+    sur.collide(b, f, Qs, tau_m=-1.0, fell_back=fell, screen=scr_d)
+    scr_h = scr_d.view(n_test, 4).cpu().numpy()
+    sweep = []
+    for tm, te in [(1e-3, 1e-2), (1e-2, 1e-2), (1e-2, 5e-2), (5e-2, 5e-2), (1.0, 1.0)]:
+        ok = (scr_h[:, 0] <= 0) & (scr_h[:, 1] <= tm) & (scr_h[:, 2] <= te) & (scr_h[:, 3] <= te)
+        sweep.append({"tau_m": tm, "tau_e": te, "accepted": int(ok.sum()),
+                      "accepted_rel_l2_max": float(proj[ok].max()) if ok.any() else None})
+    nf = sur.collide(b, f, Qs, fell_back=fell)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        nf = sur.collide(b, f, Qs, fell_back=fell)
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / 3
+    scr = ((Qs.view(n_test, n) - Qev).norm(dim=1) / Qev.norm(dim=1)).cpu().numpy()
+    acc = fell.cpu().numpy() == 0
+    return {
+        "workload": f"FNO {DEFAULT['layers']} layers x {DEFAULT['channels']} channels x "
+                    f"{DEFAULT['modes']} modes, FP32, trained {seconds:.0f} s on {npairs} pairs "
+                    f"({n_traj} FE trajectories x {n_steps} steps of the FP64 operator), "
+                    f"tested on {n_test} fresh cells",
+        "train_steps": steps, "train_batch": 16, "data_gen_s": round(t_gen, 2),
+        "final_train_loss": hist[-1][2] if hist else None,
+        "raw_rel_l2_median": float(np.median(raw)), "raw_rel_l2_max": float(raw.max()),
+        "projected_rel_l2_median": float(np.median(proj)), "projected_rel_l2_max": float(proj.max()),
+        "projected_evals_per_s": n_test / t_net,
+        "screen_sweep": sweep,
+        "raw_residual_median": [float(np.median(scr_h[:, i])) for i in (1, 2, 3)],
+        "fallback_cells": int(nf),
+        "accepted_rel_l2_median": float(np.median(scr[acc])) if acc.any() else None,
+        "accepted_rel_l2_max": float(scr[acc].max()) if acc.any() else None,
+        "screened_rel_l2_max": float(scr.max()),
+        "screened_evals_per_s": n_test / t_sur, "exact_fp64_evals_per_s": n_test / t_exact,
+        "gain_vs_exact_fp64": t_exact / t_sur,
+    }
+
+
 def cpu_baseline(cells, efm, oplan):
     """The oracle (plain double sum over modes, OpenMP) on one cell of the
     workload; evals/s = 1 / time of one full evaluation."""
@@ -184,6 +283,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="cells per pass/chunk (0 = default)")
     ap.add_argument("--term-groups", type=int, default=0)
     ap.add_argument("--skip-relax", action="store_true", help="omit the mixed-N relaxation leg")
+    ap.add_argument("--skip-surrogate", action="store_true", help="omit the learned-surrogate leg")
+    ap.add_argument("--surrogate-seconds", type=float, default=40.0, help="surrogate training budget")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run ec_copy on a buffer of this size (counter calibration)")
     args = ap.parse_args()
@@ -266,6 +367,10 @@ def main():
     if not args.skip_relax:
         log("bench: mixed-N relaxation leg (200 graph-replayed FE steps)")
         out["relaxation"] = relaxation_leg(E, torch)
+    if not args.skip_surrogate:
+        log("bench: learned surrogate (data, training, screened inference)")
+        out["surrogate"] = surrogate_leg(E, torch, seconds=args.surrogate_seconds, log_fn=log)
+        log(f"bench: surrogate {out['surrogate']}")
     if not args.skip_parity or not args.skip_cpu:
         from oracle import efm
         log("bench: oracle tables (quadrature)")

@@ -233,11 +233,13 @@ int ec_profile_read(ec_batch* batch, double* ms, int64_t* launches, int64_t* cel
 int ec_copy(const double* src, double* dst, int64_t n, void* hip_stream);
 
 /* ---- learned surrogate ---------------------------------------------------
- * A Fourier neural operator that predicts Q / mass^2 from F / mass on the
- * N^3 grid (Q is quadratic in F): lift 1 -> C channels, `layers` layers
+ * A Fourier neural operator that predicts c0^2 Q / mass^2 from c0 F / mass
+ * on the N^3 grid (Q is quadratic in F; c0 = (2 pi)^{3/2} puts the peak of a
+ * unit-temperature Maxwellian at 1): lift 1 -> C channels, `layers` layers
  * u <- GELU(W u + b + S(u)) (no GELU after the last), projection C -> 1;
  * S keeps the modes kx, ky in [-modes, modes), kz in [0, modes) with complex
- * C x C weights per mode.  FP32 parameters, trained by the library's own
+ * C x C weights per mode, between a forward DFT and a normalised (1/n)
+ * inverse DFT.  FP32 parameters, trained by the library's own
  * forward, backward and Adam kernels on (F, Q) pairs of the exact operator.
  * Supported (N, modes, channels): (32, 12, 16), (16, 6, 8), (8, 2, 4).
  */
@@ -253,8 +255,8 @@ int ec_surrogate_get_params(const ec_surrogate* s, float* host);
 int ec_surrogate_set_params(ec_surrogate* s, const float* host);
 int ec_surrogate_get_grads(const ec_surrogate* s, float* host);
 /* Normalised training inputs of cells cell0 .. cell0+B-1 of a batch (one
- * group of 3D cells of the surrogate's N): Fin = F / mass and, if Q and
- * target are not NULL, target = Q / mass^2 (device [B][N^3] FP32). */
+ * group of 3D cells of the surrogate's N): Fin = c0 F / mass and, if Q and
+ * target are not NULL, target = c0^2 Q / mass^2 (device [B][N^3] FP32). */
 int ec_surrogate_prepare(ec_surrogate* s, const ec_batch* batch, const double* f, const double* Q,
                          int64_t cell0, int B, float* Fin, float* target, void* hip_stream);
 /* y = network(Fin), device [B][N^3] FP32, B <= max_batch. */
@@ -265,11 +267,17 @@ int ec_surrogate_forward(ec_surrogate* s, const float* Fin, float* y, int B, voi
 int ec_surrogate_train_step(ec_surrogate* s, const float* Fin, const float* target, int B,
                             float lr, int update, double* loss, void* hip_stream);
 /* Screened inference on a batch (one group of 3D cells of the surrogate's N):
- * Q = mass^2 network(F / mass); a cell passes the screen when its discrete
- * H-functional h^3 sum_{F>0} Q ln F <= 0 (Theorem 1), |sum Q| <= tau_m
- * sum |Q| and the momentum and energy residuals |sum Q v| / (L sum|Q|),
- * |sum Q |v|^2| / (3 L^2 sum|Q|) are <= tau_e.  Every failing cell is
+ * Q = mass^2 network(c0 F / mass) / c0^2, then projected orthogonally onto
+ * zero discrete mass (Q - mean Q; the exact operator conserves mass exactly,
+ * so the projection cannot move Q farther from it in the 2-norm).  A cell
+ * passes the
+ * screen when the discrete H-functional of the projected Q,
+ * h^3 sum_{F>0} Q ln F, is <= 0 (Theorem 1), and the raw prediction's
+ * residuals |sum Q| <= tau_m sum |Q|, |sum Q v| / (L sum|Q|) <= tau_e and
+ * |sum Q |v|^2| / (3 L^2 sum|Q|) <= tau_e.  Every failing cell is
  * recomputed with the exact operator (ec_collide on a compacted batch).
+ * tau_m < 0 disables the screen: every cell keeps the projected prediction
+ * (the screen values are still written).
  * Optional device outputs: fell_back[c] (0/1), screen[c*4 + {P, mass, mom,
  * energy residual}]; host output n_fallback.  Synchronises the stream. */
 int ec_surrogate_collide(ec_surrogate* s, ec_batch* batch, const double* f, double* Q,

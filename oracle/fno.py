@@ -9,7 +9,8 @@ differences of this forward pass).
 Network (n = N^3 grid points, C channels, kept modes kx, ky in [-K, K),
 kz in [0, K)):
     u0[c] = Wl[c] x + bl[c]
-    h_l   = W_l u + b_l + Re IDFT(scatter(R_l . DFT(u)|kept))   (unnormalised DFTs)
+    h_l   = W_l u + b_l + Re IDFT(scatter(R_l . DFT(u)|kept))
+            (forward DFT unnormalised, inverse DFT normalised by 1/N^3)
     u     = GELU(h_l) for l < L-1, u = h_{L-1} for the last layer
     y     = sum_c Wp[c] u[c] + bp
 Flat parameter layout: Wl[C], bl[C], per layer W[C][C] (out, in), b[C],
@@ -67,7 +68,7 @@ def spectral(u, R, N, K):
     S = np.zeros((C, N, N, N), dtype=np.complex128)
     Vb = V.T.reshape(C, 2 * K, 2 * K, K)
     S[np.ix_(np.arange(C), kx, ky, kz)] = Vb
-    return np.real(np.fft.ifftn(S, axes=(1, 2, 3)) * N ** 3)  # unnormalised inverse
+    return np.real(np.fft.ifftn(S, axes=(1, 2, 3)))           # normalised inverse
 
 
 def forward(p, x, N, K, C, L):
@@ -122,3 +123,10 @@ def param_blocks(N, K, C, L):
     for name, size in [("Wp", C), ("bp", 1)]:
         out.append((name, o, size)); o += size
     return out
+
+
+def mass_projection(Q):
+    """Q - mean(Q): the orthogonal projection of Q onto grid functions whose
+    discrete mass vanishes."""
+    Q = np.asarray(Q, dtype=np.float64)
+    return Q - Q.mean()

@@ -3,14 +3,19 @@
 //
 // Network (per cell, n = N^3 points, C channels, modes kx, ky in [-K, K),
 // kz in [0, K) -- NM = 4 K^3 modes):
-//   u0 = lift(F~)             u0[c] = Wl[c] F~ + bl[c]           (F~ = F / mass)
+//   u0 = lift(F~)             u0[c] = Wl[c] F~ + bl[c]      (F~ = c0 F / mass)
 //   for l < L:  h = W_l u + b_l + S_l(u);  u <- GELU(h)  (no GELU after the last layer)
-//   y  = proj(u)              y = sum_c Wp[c] u[c] + bp           (prediction of Q / mass^2)
-// Spectral convolution S(u)[o] = Re IDFT( scatter_m( sum_i R[m][i][o] Uh[m][i] ) ),
-// Uh[m][i] = DFT(u[i]) at the kept modes (unnormalised transforms; the scale
-// lives in R).  Its adjoint in u is the same pair of transforms with conj(R)
-// transposed, and dR[m][i][o] = sum_b Gv[b][m][o] conj(Uh[b][m][i]) where Gv is
-// the truncated DFT of the output gradient.  Every truncated transform is a
+//   y  = proj(u)              y = sum_c Wp[c] u[c] + bp      (prediction of c0^2 Q / mass^2)
+// with c0 = (2 pi)^{3/2}, which puts a unit-temperature Maxwellian's peak at 1
+// (Q is quadratic in F, so the target scales with the square of the input).
+// Spectral convolution S(u)[o] = Re IDFT( scatter_m( sum_i R[m][i][o] Uh[m][i] ) ) / n,
+// Uh[m][i] = DFT(u[i]) at the kept modes: unnormalised kernels, with the 1/n of
+// the normalised inverse applied in the mode mixing, so R is O(1/C) like the
+// dense weights (Adam's steps are of one size for all parameters; an R that
+// carries the 1/n itself makes every step 1/n too coarse).  Its adjoint in u is
+// the same pair of transforms with conj(R) transposed and the same 1/n, and
+// dR[m][i][o] = sum_b Gv[b][m][o] conj(Uh[b][m][i]) / n where Gv is the
+// truncated DFT of the output gradient.  Every truncated transform is a
 // pruned 3D FFT: forward = z lines of the slab (keep kz < K) -> y lines of the
 // kept kz (keep 2K ky) -> x lines of the 2K x K kept (ky, kz) pencils (keep
 // 2K kx); inverse = the same passes backwards with zero padding.
@@ -141,14 +146,15 @@ __global__ __launch_bounds__(N) void k_fno_inv_slab(const cx<float>* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// mode mixing.  forward: Y[b][m][o] = sum_i R[m][i][o] X[b][m][i]
-// adjoint:              Y[b][m][i] = sum_o conj(R[m][i][o]) X[b][m][o]
+// mode mixing.  forward: Y[b][m][o] = scale sum_i R[m][i][o] X[b][m][i]
+// adjoint:              Y[b][m][i] = scale sum_o conj(R[m][i][o]) X[b][m][o]
 // one thread per (b, m, output channel)
 // ---------------------------------------------------------------------------
 template <int C>
 __global__ __launch_bounds__(256) void k_fno_mix2(const cx<float>* __restrict__ R,
                                                   const cx<float>* __restrict__ X, int B, int NM,
-                                                  int adjoint, cx<float>* __restrict__ Y) {
+                                                  int adjoint, float scale,
+                                                  cx<float>* __restrict__ Y) {
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (gid >= (int64_t)B * NM * C) return;
   const int o = (int)(gid % C);
@@ -167,14 +173,14 @@ __global__ __launch_bounds__(256) void k_fno_mix2(const cx<float>* __restrict__ 
       acc = cadd(acc, cmul({r.x, -r.y}, x[oo]));
     }
   }
-  Y[gid] = acc;
+  Y[gid] = {scale * acc.x, scale * acc.y};
 }
 
-// dR[m][i][o] (+)= sum_b G[b][m][o] conj(U[b][m][i]); one thread per (m, i, o)
+// dR[m][i][o] = scale sum_b G[b][m][o] conj(U[b][m][i]); one thread per (m, i, o)
 template <int C>
 __global__ __launch_bounds__(256) void k_fno_dR(const cx<float>* __restrict__ G,
                                                 const cx<float>* __restrict__ U, int B, int NM,
-                                                cx<float>* __restrict__ dR) {
+                                                float scale, cx<float>* __restrict__ dR) {
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (gid >= (int64_t)NM * C * C) return;
   const int o = (int)(gid % C);
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(256) void k_fno_dR(const cx<float>* __restrict__ G,
     const cx<float> uu = U[((int64_t)b * NM + m) * C + i];
     acc = cadd(acc, cmul(g, {uu.x, -uu.y}));
   }
-  dR[gid] = acc;
+  dR[gid] = {scale * acc.x, scale * acc.y};
 }
 
 // ---------------------------------------------------------------------------
@@ -396,7 +402,10 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// F~ = F / mass (FP64 cell in the batch layout -> FP32), mass[b] = h^3 sum F
+// input scale c0 = (2 pi)^{3/2}
+constexpr double kInputScale = 15.749609945653303;
+
+// F~ = c0 F / mass (FP64 cell in the batch layout -> FP32), mass[b] = h^3 sum F
 __global__ __launch_bounds__(256) void k_fno_normalize(const double* __restrict__ f,
                                                        const int64_t* __restrict__ off,
                                                        int64_t cell0, int n, double hd,
@@ -415,11 +424,11 @@ __global__ __launch_bounds__(256) void k_fno_normalize(const double* __restrict_
   }
   const double ms = hd * red[0];
   if (threadIdx.x == 0) mass[b] = ms;
-  const double inv = ms > 0.0 ? 1.0 / ms : 0.0;
+  const double inv = ms > 0.0 ? kInputScale / ms : 0.0;
   for (int r = threadIdx.x; r < n; r += 256) Fin[(int64_t)b * n + r] = (float)(fc[r] * inv);
 }
 
-// target = Q / mass^2 (FP64 cell in the batch layout -> FP32)
+// target = c0^2 Q / mass^2 (FP64 cell in the batch layout -> FP32)
 __global__ __launch_bounds__(256) void k_fno_target(const double* __restrict__ Q,
                                                     const int64_t* __restrict__ off, int64_t cell0,
                                                     int n, int B, const double* __restrict__ mass,
@@ -428,10 +437,10 @@ __global__ __launch_bounds__(256) void k_fno_target(const double* __restrict__ Q
   if (gid >= (int64_t)B * n) return;
   const int b = (int)(gid / n), r = (int)(gid % n);
   const double m = mass[b];
-  t[gid] = m > 0.0 ? (float)(Q[off[cell0 + b] + r] / (m * m)) : 0.f;
+  t[gid] = m > 0.0 ? (float)(Q[off[cell0 + b] + r] * (kInputScale * kInputScale) / (m * m)) : 0.f;
 }
 
-// Q = mass^2 y (FP32 -> FP64 cell in the batch layout)
+// Q = mass^2 y / c0^2 (FP32 -> FP64 cell in the batch layout)
 __global__ __launch_bounds__(256) void k_fno_denormalize(const float* __restrict__ y,
                                                          const double* __restrict__ mass,
                                                          const int64_t* __restrict__ off,
@@ -440,7 +449,7 @@ __global__ __launch_bounds__(256) void k_fno_denormalize(const float* __restrict
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (gid >= (int64_t)B * n) return;
   const int b = (int)(gid / n), r = (int)(gid % n);
-  Q[off[cell0 + b] + r] = mass[b] * mass[b] * (double)y[gid];
+  Q[off[cell0 + b] + r] = mass[b] * mass[b] * (double)y[gid] / (kInputScale * kInputScale);
 }
 
 // ---------------------------------------------------------------------------
@@ -481,7 +490,7 @@ static hipError_t fno_forward_t(const FnoArgs& a, hipStream_t st) {
     if (e != hipSuccess) return e;
     const int64_t nbmc = (int64_t)B * D::NM * C;
     hipLaunchKernelGGL((k_fno_mix2<C>), dim3((unsigned)((nbmc + 255) / 256)), dim3(256), 0, st,
-                       a.R[l], a.Uh[l], B, D::NM, 0, a.V);
+                       a.R[l], a.Uh[l], B, D::NM, 0, 1.f / (float)n, a.V);
     e = O::inv_transform(a.V, B * C, a.T, a.s, 0, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fno_pointwise<C>), dim3(gb), dim3(256), 0, st, a.u[l], a.s, B, n,
@@ -530,10 +539,10 @@ static hipError_t fno_backward_t(const FnoArgs& args, hipStream_t st) {
     if (e != hipSuccess) return e;
     const int64_t nmcc = (int64_t)D::NM * C * C;
     hipLaunchKernelGGL((k_fno_dR<C>), dim3((unsigned)((nmcc + 255) / 256)), dim3(256), 0, st, a.V,
-                       a.Uh[l], B, D::NM, a.gR[l]);
+                       a.Uh[l], B, D::NM, 1.f / (float)n, a.gR[l]);
     const int64_t nbmc = (int64_t)B * D::NM * C;
     hipLaunchKernelGGL((k_fno_mix2<C>), dim3((unsigned)((nbmc + 255) / 256)), dim3(256), 0, st,
-                       a.R[l], a.V, B, D::NM, 1, a.V2);
+                       a.R[l], a.V, B, D::NM, 1, 1.f / (float)n, a.V2);
     // du_in = pointwise part + Re IDFT(scatter(Gu))
     e = O::inv_transform(a.V2, B * C, a.T, a.du2, 1, st);
     if (e != hipSuccess) return e;

@@ -57,7 +57,7 @@ struct ec_surrogate {
   FnoArgs a;
   float* d_Fin = nullptr;
   double* d_mass = nullptr;
-  double* d_screen = nullptr;   // [maxB or batch][6]
+  double* d_screen = nullptr;   // [cells][4]: P, mass, momentum, energy residual
   int32_t* d_flag = nullptr;
   double* d_fc = nullptr;       // compact fallback cells (owned batch layout)
   double* d_qc = nullptr;
@@ -77,57 +77,92 @@ hipError_t dalloc(ec_surrogate* s, void** p, size_t bytes) {
 }
 
 // ---- screening kernels -------------------------------------------------------
-// per cell: P = h^d sum_{F>0} Q ln F, sum Q, sum |Q|, sum Q v_i, sum Q |v|^2
+// per cell: P = h^d sum_{F>0} Q ln F of the projected Q; the raw prediction's
+// moment residuals were written to out[c*4 + 1..3] by the projection
 __global__ __launch_bounds__(256) void k_screen(const double* __restrict__ f,
                                                 const double* __restrict__ Q,
                                                 const int64_t* __restrict__ off, int N, double L,
                                                 double tau_m, double tau_e, double* __restrict__ out,
                                                 int32_t* __restrict__ flag) {
-  __shared__ double red[7][256];
+  __shared__ double red[256];
   const int c = blockIdx.x;
   const double* fc = f + off[c];
   const double* qc = Q + off[c];
   const int n = N * N * N;
   const double h = 2.0 * L / N;
-  double a[7] = {0, 0, 0, 0, 0, 0, 0};
+  double a = 0.0;
   for (int r = threadIdx.x; r < n; r += 256) {
-    const double fv = fc[r], qv = qc[r];
-    const int ix = r / (N * N), iy = (r / N) % N, iz = r % N;
-    const double vx = -L + ix * h, vy = -L + iy * h, vz = -L + iz * h;
-    if (fv > 0.0) a[0] += qv * log(fv);
-    a[1] += qv;
-    a[2] += fabs(qv);
-    a[3] += qv * vx;
-    a[4] += qv * vy;
-    a[5] += qv * vz;
-    a[6] += qv * (vx * vx + vy * vy + vz * vz);
+    const double fv = fc[r];
+    if (fv > 0.0) a += qc[r] * log(fv);
   }
-#pragma unroll
-  for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = a[k];
+  red[threadIdx.x] = a;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-#pragma unroll
-      for (int k = 0; k < 7; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double hd = h * h * h;
-    const double P = hd * red[0][0];
-    const double sabs = red[2][0] > 0.0 ? red[2][0] : 1e-300;
-    const double mass_res = fabs(red[1][0]) / sabs;
-    const double mom_res =
-        sqrt(red[3][0] * red[3][0] + red[4][0] * red[4][0] + red[5][0] * red[5][0]) / (sabs * L);
-    const double en_res = fabs(red[6][0]) / (sabs * 3.0 * L * L);
     double* o = out + (int64_t)c * 4;
+    const double P = h * h * h * red[0];
     o[0] = P;
-    o[1] = mass_res;
-    o[2] = mom_res;
-    o[3] = en_res;
-    const bool ok = (P <= 0.0) && (mass_res <= tau_m) && (mom_res <= tau_e) && (en_res <= tau_e) &&
-                    isfinite(P) && isfinite(mass_res);
+    const double mass_res = o[1], mom_res = o[2], en_res = o[3];
+    const bool ok = tau_m < 0.0 ||     // screen disabled: every cell keeps the prediction
+                    ((P <= 0.0) && (mass_res <= tau_m) && (mom_res <= tau_e) &&
+                     (en_res <= tau_e) && isfinite(P) && isfinite(mass_res));
     flag[c] = ok ? 0 : 1;
   }
+}
+
+// ---- mass projection -------------------------------------------------------
+// Q <- Q - (sum_r Q) / n: the orthogonal (Euclidean) projection onto grid
+// functions with zero discrete mass.  The exact operator conserves mass
+// exactly (momentum and energy only to spectral accuracy), so this projection
+// never moves the prediction farther from it in the 2-norm.  Before
+// projecting, the raw prediction's residuals |sum Q| / sum|Q|,
+// |sum Q v| / (L sum|Q|) and |sum Q |v|^2| / (3 L^2 sum|Q|) go to
+// out[c*4 + 1..3] for the screen.  One block per cell of cells
+// cell0 .. cell0 + gridDim.x - 1.
+__global__ __launch_bounds__(256) void k_project(double* __restrict__ Q,
+                                                 const int64_t* __restrict__ off, int64_t cell0,
+                                                 int N, double L, double* __restrict__ out) {
+  __shared__ double red[6][256];
+  __shared__ double mean;
+  const int64_t c = cell0 + blockIdx.x;
+  double* qc = Q + off[c];
+  const int n = N * N * N;
+  const double h = 2.0 * L / N;
+  double a[6] = {0, 0, 0, 0, 0, 0};
+  for (int r = threadIdx.x; r < n; r += 256) {
+    const int ix = r / (N * N), iy = (r / N) % N, iz = r % N;
+    const double vx = -L + ix * h, vy = -L + iy * h, vz = -L + iz * h;
+    const double q = qc[r];
+    a[0] += q;
+    a[1] += q * vx;
+    a[2] += q * vy;
+    a[3] += q * vz;
+    a[4] += q * (vx * vx + vy * vy + vz * vz);
+    a[5] += fabs(q);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double sabs = red[5][0] > 0.0 ? red[5][0] : 1e-300;
+    double* o = out + c * 4;
+    o[1] = fabs(red[0][0]) / sabs;
+    o[2] = sqrt(red[1][0] * red[1][0] + red[2][0] * red[2][0] + red[3][0] * red[3][0]) / (sabs * L);
+    o[3] = fabs(red[4][0]) / (3.0 * L * L * sabs);
+    mean = red[0][0] / n;
+  }
+  __syncthreads();
+  const double m = mean;
+  for (int r = threadIdx.x; r < n; r += 256) qc[r] -= m;
 }
 
 // gather cells idx[j] of (f, off) into the compact layout (cell j at j * n)
@@ -170,7 +205,8 @@ void bind_params(ec_surrogate* s) {
   a.gWp = s->d_g + s->oWp;
 }
 
-// forward of B cells of one batch (cells cell0 .. cell0+B-1) into Q
+// forward of B cells of one batch (cells cell0 .. cell0+B-1) into Q, then the
+// conservative projection
 int forward_batch_cells(ec_surrogate* s, const ec_batch* batch, const double* f, double* Q,
                         int64_t cell0, int B, hipStream_t st) {
   const double L = plan_L(batch_group_plan(batch, 0));
@@ -182,6 +218,9 @@ int forward_batch_cells(ec_surrogate* s, const ec_batch* batch, const double* f,
   a.Fin = s->d_Fin;
   SCHK(fno_forward(a, st));
   SCHK(fno_denormalize(a.y, s->d_mass, batch_offsets_dev(batch), cell0, (int)s->n, B, Q, st));
+  hipLaunchKernelGGL(k_project, dim3((unsigned)B), dim3(256), 0, st, Q, batch_offsets_dev(batch),
+                     cell0, s->N, L, s->d_screen);
+  SCHK(hipGetLastError());
   return EC_OK;
 }
 
@@ -227,8 +266,8 @@ int ec_surrogate_create(int N, int modes, int channels, int layers, uint64_t see
     for (int l = 0; l < layers; ++l) {
       fill(s->oW[l], (int64_t)C * C, 1.0 / std::sqrt((double)C));
       fill(s->ob[l], C, 0.0);
-      // spectral weights: the unnormalised transform pair scales by n
-      fill(s->oR[l], 2 * s->NM * C * C, 1.0 / ((double)C * C * (double)s->n));
+      // spectral weights (the 1/n of the inverse transform is applied in the mixing)
+      fill(s->oR[l], 2 * s->NM * C * C, 1.0 / ((double)C * C));
     }
     fill(s->oWp, C, 1.0 / std::sqrt((double)C));
     fill(s->obp, 1, 0.0);
@@ -397,12 +436,7 @@ int ec_surrogate_collide(ec_surrogate* s, ec_batch* batch, const double* f, doub
       return set_error(EC_ERR_ARG, "the batch must be one group of 3D cells of the surrogate's N");
     hipStream_t st = (hipStream_t)stream;
     const int64_t ncell = batch_cells(batch);
-    for (int64_t c0 = 0; c0 < ncell; c0 += s->maxB) {
-      const int B = (int)std::min<int64_t>(s->maxB, ncell - c0);
-      int rc = forward_batch_cells(s, batch, f, Q, c0, B, st);
-      if (rc) return rc;
-    }
-    // screen
+    // screen buffers (the projection writes the residuals of every cell)
     if (!s->d_flag || s->scap < ncell) {
       if (s->d_flag) (void)hipFree(s->d_flag);
       if (s->d_screen) (void)hipFree(s->d_screen);
@@ -413,6 +447,12 @@ int ec_surrogate_collide(ec_surrogate* s, ec_batch* batch, const double* f, doub
       SCHK(hipMalloc(&s->d_idx, ncell * sizeof(int64_t)));
       s->scap = ncell;
     }
+    for (int64_t c0 = 0; c0 < ncell; c0 += s->maxB) {
+      const int B = (int)std::min<int64_t>(s->maxB, ncell - c0);
+      int rc = forward_batch_cells(s, batch, f, Q, c0, B, st);
+      if (rc) return rc;
+    }
+    // screen
     const double L = plan_L(batch_group_plan(batch, 0));
     hipLaunchKernelGGL(k_screen, dim3((unsigned)ncell), dim3(256), 0, st, f, Q,
                        batch_offsets_dev(batch), s->N, L, tau_m, tau_e, s->d_screen, s->d_flag);

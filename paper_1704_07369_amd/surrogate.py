@@ -60,7 +60,7 @@ class Surrogate:
 
 
 def generate_pairs(torch, plan: Plan, cells, n_steps, dt, sur: Surrogate):
-    """(F/mass, Q/mass^2) pairs along forward-Euler trajectories of the exact
+    """(c0 F/mass, c0^2 Q/mass^2) pairs along forward-Euler trajectories of the exact
     operator (ec_collide + ec_step), stored on the device as FP32 tensors of
     shape [len(cells) * n_steps, N^3]."""
     nc = len(cells)

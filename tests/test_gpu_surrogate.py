@@ -120,7 +120,79 @@ def test_training_on_operator_trajectories_lowers_loss():
     Fin, Tgt = generate_pairs(torch, plan, cells, 8, 0.01, sur)
     assert Fin.shape == (128, N ** 3) and torch.isfinite(Tgt).all()
     l0 = sur.train_step(Fin[:8], Tgt[:8], 8, 0.0, update=False, want_loss=True)
+    p0 = sur.params()
     hist, steps = train(torch, sur, Fin, Tgt, seconds=8.0, batch=8, lr=2e-3)
     l1 = sur.train_step(Fin[:8], Tgt[:8], 8, 0.0, update=False, want_loss=True)
     say(f"  steps {steps}: loss {l0:.3e} -> {l1:.3e}")
     assert l1 < 0.5 * l0
+    # held-out cells (fresh seeds): projected prediction against the exact
+    # operator, trained network against its own initialisation
+    test = [synth.sample_mixture(synth.mixture_anisotropic(6001 + i, 3), N, L) for i in range(8)]
+    b = E.Batch([plan], [8])
+    f = to_dev(E.pack(b, test))
+    Qe = torch.zeros_like(f)
+    b.collide(f, Qe)
+    Qs = torch.zeros_like(f)
+
+    def held_out_error():
+        sur.collide(b, f, Qs, tau_m=-1.0)
+        torch.cuda.synchronize()
+        d = (Qs - Qe).view(8, -1).norm(dim=1) / Qe.view(8, -1).norm(dim=1)
+        return float(d.median())
+
+    e1 = held_out_error()
+    trained = sur.params()
+    sur.set_params(p0)
+    e0 = held_out_error()
+    sur.set_params(trained)
+    say(f"  held-out median rel L2 error: initial {e0:.3e}, trained {e1:.3e}")
+    assert e1 < 0.3 and e1 < 0.2 * e0
+
+
+def test_mass_projection_matches_reference():
+    """Screen disabled: the library's Q is the FP64 mass projection of its own
+    network output (reference: oracle/fno.py on the same FP32 prediction),
+    its mass vanishes, and the residuals it reports are those of the
+    unprojected prediction."""
+    import torch
+    say("case surrogate projection")
+    N, L, M = 16, 8.0, 32
+    plan = E.Plan(N, 3, L, M, R=6.0)
+    nc = 5
+    cells = [synth.sample_mixture(synth.mixture_anisotropic(700 + i, 3), N, L) for i in range(nc)]
+    b = E.Batch([plan], [nc])
+    f = to_dev(E.pack(b, cells))
+    sur = Surrogate(N, 6, 8, 2, seed=5, max_batch=2)
+    xin = torch.empty((nc, N ** 3), dtype=torch.float32, device="cuda")
+    y = torch.empty_like(xin)
+    for c in range(0, nc, 2):
+        k = min(2, nc - c)
+        sur.prepare(b, f, None, c, k, xin[c:c + k], None)
+        sur.forward(xin[c:c + k], y[c:c + k], k)
+    Qs = torch.zeros_like(f)
+    fell = torch.ones(nc, dtype=torch.int32, device="cuda")
+    scr = torch.zeros(nc * 4, dtype=torch.float64, device="cuda")
+    nf = sur.collide(b, f, Qs, tau_m=-1.0, fell_back=fell, screen=scr)
+    torch.cuda.synchronize()
+    assert nf == 0 and fell.cpu().numpy().tolist() == [0] * nc
+    h3 = (2 * L / N) ** 3
+    c0 = (2 * np.pi) ** 1.5
+    yh = y.cpu().numpy().astype(np.float64)
+    qs = E.unpack(b, Qs.cpu().numpy())
+    v = -L + np.arange(N) * (2 * L / N)
+    vx, vy, vz = np.meshgrid(v, v, v, indexing="ij")
+    for c in range(nc):
+        mass = h3 * cells[c].sum()
+        raw = (yh[c] * mass ** 2 / c0 ** 2).reshape(N, N, N)
+        ref = fno.mass_projection(raw)
+        err = np.abs(qs[c] - ref).max() / np.abs(ref).max()
+        say(f"  cell {c}: projection rel err {err:.2e}")
+        assert err < 1e-10
+        q = qs[c]
+        assert abs(q.sum()) < 1e-12 * np.abs(q).sum()
+        ra = np.abs(raw).sum()
+        res = [abs(raw.sum()) / ra,
+               np.sqrt((raw * vx).sum() ** 2 + (raw * vy).sum() ** 2 + (raw * vz).sum() ** 2) / (L * ra),
+               abs((raw * (vx**2 + vy**2 + vz**2)).sum()) / (3 * L * L * ra)]
+        got = scr.cpu().numpy()[c * 4 + 1:c * 4 + 4]
+        assert np.allclose(got, res, rtol=1e-8, atol=1e-14), (got, res)

@@ -22,12 +22,12 @@ def test_spectral_conv_single_mode_is_a_plane_wave():
     mx, my, mz = m // (2 * K * K), (m // K) % (2 * K), m % K
     R[m, 1, 0] = 0.3 - 0.7j
     s = fno.spectral(u, R, N, K)
-    # explicit: Uh = sum_r u[1](r) e^{-2 pi i k.r/N}; s[0](r) = Re(R Uh e^{+2 pi i k.r/N})
+    # explicit: Uh = sum_r u[1](r) e^{-2 pi i k.r/N}; s[0](r) = Re(R Uh e^{+2 pi i k.r/N}) / N^3
     k = np.array([kx[mx], ky[my], kz[mz]])
     r = np.stack(np.meshgrid(*([np.arange(N)] * 3), indexing="ij"), axis=-1)
     ph = np.exp(2j * math.pi * (r @ k) / N)
     uh = np.sum(u[1] * np.conj(ph))
-    ref = np.real(R[m, 1, 0] * uh * ph)
+    ref = np.real(R[m, 1, 0] * uh * ph) / N ** 3
     assert np.abs(s[0] - ref).max() < 1e-12 * np.abs(ref).max()
     assert np.abs(s[1]).max() < 1e-12
 
@@ -79,3 +79,22 @@ def test_fd_gradient_matches_linear_layer_closed_form():
     ref = np.mean(2 * np.sum(y - t, axis=1) / np.sum(t ** 2, axis=1))
     g = fno.fd_grad(p, x, t, N, K, C, L, [p.size - 1])
     assert abs(g[0] - ref) < 1e-7 * max(1.0, abs(ref))
+
+
+def test_mass_projection_is_the_least_norm_correction():
+    """The projection zeroes the mass, is idempotent, equals Q minus the
+    minimum-norm correction with Q's mass (scipy's least squares), and never
+    increases the distance to a target of zero mass."""
+    from scipy.linalg import lstsq
+    N = 6
+    rng = np.random.default_rng(4)
+    Q = rng.standard_normal((N, N, N)) + 0.3
+    P = fno.mass_projection(Q)
+    assert abs(P.sum()) < 1e-12 * np.abs(Q).sum()
+    assert np.abs(fno.mass_projection(P) - P).max() < 1e-15
+    A = np.ones((1, N ** 3))
+    c = lstsq(A, A @ Q.ravel())[0]
+    assert np.abs((Q.ravel() - c) - P.ravel()).max() < 1e-12 * np.abs(Q).max()
+    for _ in range(5):
+        target = fno.mass_projection(rng.standard_normal((N, N, N)))
+        assert np.linalg.norm(P - target) <= np.linalg.norm(Q - target) + 1e-12
