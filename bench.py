@@ -29,7 +29,7 @@ METRIC = "collision evals/sec at N=32^3,M=32: FP64 vs mixed vs surrogate at stat
 PEAK_FP64 = 78.6    # TFLOP/s, MI355X vector FP64
 PEAK_FP32 = 157.3   # TFLOP/s, MI355X vector FP32
 N, D, L, M, R = 32, 3, 8.0, 32, 6.0
-KNAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe"]
+KNAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe", "k_fwdx", "k_fused"]
 
 
 def log(msg):
@@ -52,7 +52,10 @@ def kernel_flops(n_side: int, d: int, terms: int) -> list:
         fwd = 2.5 * n * lg
         pencil = 0.0
         slab = terms * 5.0 * n * lg + 2.5 * n * lg + terms * 8.0 * n + 4.0 * n
-    return [fwd, pencil, slab]
+    total = fwd + pencil + slab
+    # the fused schedule: k_fwd, then the x forward pass, then everything else
+    fwdx = (1.0 / 3.0) * 2.5 * n * lg if d == 3 else 0.0
+    return [fwd, pencil, slab, total, fwdx, total - fwd - fwdx]
 
 
 def make_cells(n_cells, seed0=2001):
@@ -108,7 +111,7 @@ def roofline(prof, flops_cell, peak):
     over its summed duration (HIP events on the launch stream)."""
     ms, launches, cells = prof
     k = max(range(len(ms)), key=lambda i: ms[i])
-    fl = sum(flops_cell) if KNAMES[k] == "k_pipe" else flops_cell[k]
+    fl = flops_cell[k]
     achieved = fl * cells / (ms[k] * 1e-3) / 1e12
     return {
         "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
@@ -279,7 +282,7 @@ def main():
     ap.add_argument("--skip-parity", action="store_true")
     ap.add_argument("--skip-fp32", action="store_true", help="omit the FP32 side (profiling runs)")
     ap.add_argument("--skip-single", action="store_true", help="omit single-cell latency")
-    ap.add_argument("--schedule", choices=["auto", "pipeline", "two_pass"], default="auto")
+    ap.add_argument("--schedule", choices=["auto", "pipeline", "two_pass", "fused"], default="auto")
     ap.add_argument("--chunk", type=int, default=0, help="cells per pass/chunk (0 = default)")
     ap.add_argument("--term-groups", type=int, default=0)
     ap.add_argument("--skip-relax", action="store_true", help="omit the mixed-N relaxation leg")
@@ -300,7 +303,8 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     if args.schedule != "auto":
-        SCHED["mode"] = E.EC_SCHED_PIPELINE if args.schedule == "pipeline" else E.EC_SCHED_TWO_PASS
+        SCHED["mode"] = {"pipeline": E.EC_SCHED_PIPELINE, "two_pass": E.EC_SCHED_TWO_PASS,
+                         "fused": E.EC_SCHED_FUSED}[args.schedule]
         SCHED["chunk"], SCHED["G"] = args.chunk, args.term_groups
     if args.copy_mb:
         nc = args.copy_mb * 1048576 // 8
@@ -316,7 +320,7 @@ def main():
     plan = E.Plan(N, D, L, M, R=R)
     terms = plan.terms()
     flops = kernel_flops(N, D, terms)
-    flops_eval = sum(flops)
+    flops_eval = flops[3]
 
     log("bench: FP64 timed region")
     b64, f64, Q64, t64, prof64 = time_collide(E, torch, plan, cells, E.EC_FP64, args.steps,

@@ -142,13 +142,19 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
  * pass split into term_groups groups of terms, combine) work on four
  * consecutive chunks, so the per-term intermediates of a chunk stay in the
  * last-level cache.  EC_SCHED_TWO_PASS: three launches per chunk with the
- * intermediates of the whole chunk in memory.  0 for cells_per_pass or
- * term_groups selects the default (chosen from the cache size); the
- * autotuner picks measured values.  Reallocates the workspace (synchronises
+ * intermediates of the whole chunk in memory.  EC_SCHED_FUSED (3D, N = 16,
+ * 24, 32; FP64 and FP32): forward transform, then one kernel that runs every
+ * term's inverse transform on chip (the x axis split by decimation in
+ * frequency into term_groups residue classes, one workgroup per class) and
+ * accumulates the gain in FP64 registers, so no per-term intermediate touches
+ * device memory; splits: N = 16: 1, 2; N = 24: 2, 3; N = 32: 4 (FP32 also 2).
+ * 0 for cells_per_pass or term_groups selects the default (chosen from the
+ * cache size); the autotuner picks measured values.  Reallocates the workspace (synchronises
  * the device); call it outside graph capture.
  */
 #define EC_SCHED_PIPELINE 0
 #define EC_SCHED_TWO_PASS 1
+#define EC_SCHED_FUSED 2
 int ec_batch_set_schedule(ec_batch* batch, int group, int mode, int cells_per_pass,
                           int term_groups);
 int ec_batch_get_schedule(const ec_batch* batch, int group, int* mode, int* cells_per_pass,
@@ -217,11 +223,12 @@ int ec_step(ec_batch* batch, double* f, double dt, int n_steps,
  * events on its stream around its kernels.  ec_profile_read waits for them and
  * returns, per group g of the batch and kernel k (EC_PROF_KERNELS per group:
  * 0 forward slab transform, 1 x-pencil pass, 2 slab pass of the two-pass
- * schedule, 3 the pipelined kernel), ms[4g + k] = summed duration and
- * launches[4g + k] = number of launches, and cells[g] = cells processed; then
- * it forgets the records.  Host arrays of 4 * n_groups (cells: n_groups).
+ * schedule, 3 the pipelined kernel, 4 forward x transform and 5 fused kernel
+ * of the fused schedule), ms[6g + k] = summed duration and launches[6g + k] =
+ * number of launches, and cells[g] = cells processed; then it forgets the
+ * records.  Host arrays of 6 * n_groups (cells: n_groups).
  */
-#define EC_PROF_KERNELS 4
+#define EC_PROF_KERNELS 6
 int ec_profile(ec_batch* batch, int enable);
 int ec_profile_read(ec_batch* batch, double* ms, int64_t* launches, int64_t* cells);
 

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/ec.h"
+#include "fused.h"
 #include "internal.h"
 #include "kernels.h"
 #include "pipe.h"
@@ -66,9 +67,9 @@ struct BatchGroup {
   const ec_plan* plan = nullptr;
   int64_t count = 0;
   int64_t first = 0;   // first batch cell of the group
-  int mode = 0;        // EC_SCHED_PIPELINE or EC_SCHED_TWO_PASS (3D); 2D is always two-pass
+  int mode = 0;        // EC_SCHED_* (3D); 2D is always two-pass
   int chunk = 0;       // cells per pass / per pipeline chunk
-  int G = 1;           // term groups (pipeline)
+  int G = 1;           // term groups (pipeline) or x split (fused)
 };
 
 struct StepGraph {
@@ -81,7 +82,7 @@ struct StepGraph {
 struct ProfRec {
   int group;
   int ncells;
-  int kind;            // 0: two-pass chunk (3 kernels), 1: one pipeline launch
+  int kind;            // 0: two-pass chunk (3 kernels), 1: one pipeline launch, 2: fused chunk
   hipEvent_t ev[4];
 };
 
@@ -111,7 +112,13 @@ void default_schedule(BatchGroup& g, int precision) {
   const HostTables& T = g.plan->host;
   const int64_t count = std::max<int64_t>(1, g.count);
   if (precision == EC_BF16X3) g.mode = EC_SCHED_TWO_PASS;   // the MFMA x pass is a separate kernel
-  if (T.d == 3 && g.mode == EC_SCHED_PIPELINE) {
+  if (g.mode == EC_SCHED_FUSED && (T.d != 3 || fused_default_split(T.N, precision) == 0))
+    g.mode = EC_SCHED_TWO_PASS;
+  if (T.d == 3 && g.mode == EC_SCHED_FUSED) {
+    // one spectrum per cell of workspace; 2048 cells keep >= 2048 workgroups busy
+    g.chunk = (int)std::min<int64_t>(2048, count);
+    g.G = fused_default_split(T.N, precision);
+  } else if (T.d == 3 && g.mode == EC_SCHED_PIPELINE) {
     // keep one slot of the per-term intermediates under ~96 MB (the MALL holds
     // the slot being written and the slot being read), then split the terms so
     // the slab role has about 1024 blocks
@@ -132,12 +139,14 @@ void default_schedule(BatchGroup& g, int precision) {
 }
 
 bool use_pipe(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_PIPELINE; }
+bool use_fused(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_FUSED; }
 bool fp32_tables(int precision) { return precision != EC_FP64; }
 
 size_t group_ws_bytes(const BatchGroup& g, int precision) {
   const HostTables& T = g.plan->host;
   const size_t cs = csize(precision);
   const size_t n = (size_t)T.n;
+  if (use_fused(g)) return (size_t)g.chunk * n * cs + 256;
   if (use_pipe(g))
     return 2 * ((size_t)g.chunk * n * cs + (size_t)g.chunk * T.J * n * cs +
                 (size_t)g.G * g.chunk * n * 8 + (size_t)g.chunk * n * 8) + 8 * 256;
@@ -255,12 +264,46 @@ int run_group_pipe(ec_batch* b, int gi, const double* f, double* Q, double dt, h
   return EC_OK;
 }
 
+int run_group_fused(ec_batch* b, int gi, const double* f, double* Q, double dt, hipStream_t s,
+                    bool profile) {
+  const BatchGroup& g = b->groups[gi];
+  const HostTables& T = g.plan->host;
+  char* W = align256((char*)b->d_ws);
+  for (int64_t c0 = 0; c0 < g.count; c0 += g.chunk) {
+    ChunkArgs a;
+    a.N = T.N; a.d = T.d; a.precision = b->precision; a.J = T.J;
+    a.gamma = fp32_tables(b->precision) ? g.plan->d_gamma32 : g.plan->d_gamma64;
+    a.W = W;
+    a.f = f; a.Q = Q; a.off = b->d_off;
+    a.cell0 = g.first + c0;
+    a.ncells = (int)std::min<int64_t>(g.chunk, g.count - c0);
+    a.dt = dt;
+    ProfRec rec{};
+    if (profile) {
+      rec.group = gi; rec.ncells = a.ncells; rec.kind = 2;
+      int rc = take_events(b, rec);
+      if (rc) return rc;
+      a.ev = rec.ev;
+    }
+    HIPCHK(launch_fused(a, g.G, s));
+    if (profile) b->prof.push_back(rec);
+  }
+  return EC_OK;
+}
+
+int run_group(ec_batch* b, int gi, const double* f, double* Q, double dt, hipStream_t s,
+              bool profile) {
+  const BatchGroup& g = b->groups[gi];
+  if (use_fused(g)) return run_group_fused(b, gi, f, Q, dt, s, profile);
+  if (use_pipe(g)) return run_group_pipe(b, gi, f, Q, dt, s, profile);
+  return run_group_two_pass(b, gi, f, Q, dt, s, profile);
+}
+
 int run_collide(ec_batch* b, const double* f, double* Q, double dt, hipStream_t s,
                 bool profile = false) {
   for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
     if (b->groups[gi].count == 0) continue;
-    int rc = use_pipe(b->groups[gi]) ? run_group_pipe(b, gi, f, Q, dt, s, profile)
-                                     : run_group_two_pass(b, gi, f, Q, dt, s, profile);
+    int rc = run_group(b, gi, f, Q, dt, s, profile);
     if (rc) return rc;
   }
   return EC_OK;
@@ -291,8 +334,7 @@ int collide_prefix(ec_batch* b, int64_t n_active, const double* f, double* Q, hi
   BatchGroup& g = b->groups[0];
   const int64_t saved = g.count;
   g.count = std::min(saved, n_active);
-  int rc = use_pipe(g) ? run_group_pipe(b, 0, f, Q, 0.0, s, false)
-                       : run_group_two_pass(b, 0, f, Q, 0.0, s, false);
+  int rc = run_group(b, 0, f, Q, 0.0, s, false);
   g.count = saved;
   return rc;
 }
@@ -454,13 +496,19 @@ int ec_batch_offsets(const ec_batch* b, int64_t* offsets) {
 int ec_batch_set_schedule(ec_batch* b, int group, int mode, int cells_per_pass, int term_groups) {
   return guarded([&]() -> int {
     if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
-    if (mode != EC_SCHED_PIPELINE && mode != EC_SCHED_TWO_PASS) return fail(EC_ERR_ARG, "bad mode");
+    if (mode != EC_SCHED_PIPELINE && mode != EC_SCHED_TWO_PASS && mode != EC_SCHED_FUSED)
+      return fail(EC_ERR_ARG, "bad mode");
     BatchGroup& g = b->groups[group];
     g.mode = mode;
     default_schedule(g, b->precision);
     const int64_t count = std::max<int64_t>(1, g.count);
     if (cells_per_pass > 0) g.chunk = (int)std::min<int64_t>(cells_per_pass, count);
     if (term_groups > 0 && use_pipe(g)) g.G = std::min(term_groups, g.plan->host.J);
+    if (term_groups > 0 && use_fused(g)) {
+      if (!fused_supported(g.plan->host.N, b->precision, term_groups))
+        return fail(EC_ERR_UNSUPPORTED, "unsupported x split for the fused schedule");
+      g.G = term_groups;
+    }
     drop_graph(b);
     HIPCHK(hipDeviceSynchronize());
     return alloc_workspaces(b);
@@ -476,7 +524,7 @@ int ec_batch_get_schedule(const ec_batch* b, int group, int* mode, int* cells_pe
                           int* term_groups) {
   if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
   const BatchGroup& g = b->groups[group];
-  if (mode) *mode = use_pipe(g) ? EC_SCHED_PIPELINE : EC_SCHED_TWO_PASS;
+  if (mode) *mode = use_fused(g) ? EC_SCHED_FUSED : (use_pipe(g) ? EC_SCHED_PIPELINE : EC_SCHED_TWO_PASS);
   if (cells_per_pass) *cells_per_pass = g.chunk;
   if (term_groups) *term_groups = g.G;
   return EC_OK;
@@ -540,6 +588,7 @@ int apply_sched(ec_batch* b, int gi, const Sched& s) {
   const int64_t count = std::max<int64_t>(1, g.count);
   if (s.chunk > 0) g.chunk = (int)std::min<int64_t>(s.chunk, count);
   if (s.G > 0 && use_pipe(g)) g.G = std::min(s.G, g.plan->host.J);
+  if (s.G > 0 && use_fused(g) && fused_supported(g.plan->host.N, b->precision, s.G)) g.G = s.G;
   return alloc_workspaces(b);
 }
 
@@ -551,8 +600,7 @@ int time_group(ec_batch* b, int gi, const double* f, double* Q, hipStream_t st, 
   int rc = EC_OK;
   for (int r = 0; r < 4 && rc == EC_OK; ++r) {
     (void)hipEventRecord(e0, st);
-    rc = use_pipe(b->groups[gi]) ? run_group_pipe(b, gi, f, Q, 0.0, st, false)
-                                 : run_group_two_pass(b, gi, f, Q, 0.0, st, false);
+    rc = run_group(b, gi, f, Q, 0.0, st, false);
     (void)hipEventRecord(e1, st);
     if (hipEventSynchronize(e1) != hipSuccess) rc = fail(EC_ERR_DEVICE, "autotune run failed");
     float ms = 0.f;
@@ -592,6 +640,14 @@ int ec_autotune(ec_batch* b, const double* f, double* Q, const char* cache_path,
         bool dup = false;
         for (auto& x : cand) dup |= (x.mode == s.mode && x.chunk == s.chunk);
         if (!dup) cand.push_back(s);
+      }
+      if (T.d == 3 && fused_default_split(T.N, b->precision) > 0) {
+        for (int P : {1, 2, 3, 4})
+          if (fused_supported(T.N, b->precision, P))
+            for (int c : {256, 2048}) {
+              if (c > count && c != 256) continue;
+              cand.push_back(Sched{EC_SCHED_FUSED, (int)std::min<int64_t>(c, count), P});
+            }
       }
       if (T.d == 3) {
         for (int c : {4, 6, 8, 12, 16, 24})
@@ -643,6 +699,14 @@ int ec_profile_read(ec_batch* b, double* ms, int64_t* launches, int64_t* cells) 
           HIPCHK(hipEventElapsedTime(&t, r.ev[k], r.ev[k + 1]));
           ms[EC_PROF_KERNELS * r.group + k] += t;
           launches[EC_PROF_KERNELS * r.group + k] += 1;
+        }
+      } else if (r.kind == 2) {
+        const int slot[3] = {0, 4, 5};   // k_fwd, k_fwdx, k_fused
+        for (int k = 0; k < 3; ++k) {
+          float t = 0.f;
+          HIPCHK(hipEventElapsedTime(&t, r.ev[k], r.ev[k + 1]));
+          ms[EC_PROF_KERNELS * r.group + slot[k]] += t;
+          launches[EC_PROF_KERNELS * r.group + slot[k]] += 1;
         }
       } else {
         float t = 0.f;

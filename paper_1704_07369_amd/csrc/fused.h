@@ -1,0 +1,21 @@
+// Fused schedule of the 3D operator: forward transform, then one kernel that
+// runs every term's inverse transform on chip and accumulates the gain in
+// FP64 registers (no per-term intermediates in device memory).
+#pragma once
+
+#include "kernels.h"
+
+namespace efm {
+
+// x split P of the fused kernel (each cell is handled by P workgroups, one per
+// residue class of the output x index mod P): the default for (N, precision),
+// or 0 when the fused schedule has no instantiation for N.
+int fused_default_split(int N, int precision);
+bool fused_supported(int N, int precision, int split);
+
+// k_fwd (2D transform of every x slab into a.W), k_fwdx (x transform in place:
+// a.W then holds the unnormalised 3D spectrum), k_fused.  Events a.ev, when
+// set: before k_fwd, after k_fwd, after k_fwdx, after k_fused.
+hipError_t launch_fused(const ChunkArgs& a, int split, hipStream_t st);
+
+}  // namespace efm

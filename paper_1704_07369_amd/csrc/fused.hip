@@ -1,0 +1,258 @@
+// Fused per-term kernel of the 3D operator for gfx950.
+//
+// The gain is sum_t Re c_t Im c_t with c_t = IDFT[gamma_t Fh] (section 4.1,
+// eq. fastAlg; gamma_t = alpha_t + i beta_t carries N^-d, the weights and the
+// filter), the loss l = Re IDFT[D Fh] (section 3.1.2).  A 3D FP64 volume of
+// one term (N^3 complex, 512 KB at N = 32) does not fit in a CU's LDS, so the
+// inverse transform along x is split by decimation in frequency with radix P:
+// for the output rows x = P q + s,
+//   c(Pq+s, y, z) = sum_{k'<N/P} e^{2 pi i k' q/(N/P)} G_s(k', y, z),
+//   G_s(k', .) = e^{2 pi i k' s/N} sum_{j<P} e^{2 pi i j s/P} Zh(k' + jN/P, .),
+// where Zh = gamma_t Fh is transformed along y and z first.  One workgroup
+// owns one (cell, s): for every term it forms G_s straight from Fh and the
+// term's table (both read from L2: Fh is reused by the cell's P workgroups
+// and by every term, the table by every cell), runs the inverse transforms
+// along z, y (register lines, LDS transposes) and x (length N/P), and adds
+// Re c Im c into FP64 registers that cover its N^3/P output points.  The loss
+// term goes first, so the accumulator starts at -F l.
+//
+// Block -> (cell, s): blocks b, b+8, ... land on one XCD, so the P workgroups
+// of a cell share that XCD's L2 (cell = (b / 8P) * 8 + b % 8, s = (b / 8) % P).
+#include "fused.h"
+
+#include "fft.h"
+
+namespace efm {
+
+// exp(2 pi i m / N) for a runtime m in [0, N): a select over the exact table
+template <int N, typename R>
+__device__ __forceinline__ cx<R> unit_root(int m) {
+  cx<R> w = {(R)1, (R)0};
+  if constexpr (N > 1) {
+#pragma unroll
+    for (int k = 1; k < N; ++k)
+      if (m == k) w = {(R)Tw<N>::c[k], (R)Tw<N>::s[k]};
+  }
+  return w;
+}
+
+// forward DFT along x of every (cell, k2, k1) pencil of W[cell][x][k2][k1], in place
+template <typename R, int N>
+__global__ __launch_bounds__(64) void k_fwdx(cx<R>* __restrict__ W, int ncells) {
+  constexpr int P2 = N * N;
+  const int64_t gid = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (gid >= (int64_t)ncells * P2) return;
+  const int64_t cc = gid / P2;
+  const int p = (int)(gid % P2);
+  cx<R>* Wc = W + cc * N * P2 + p;
+  cx<R> v[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = Wc[(int64_t)k * P2];
+  fft_line<N, -1>(v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) Wc[(int64_t)k * P2] = v[k];
+}
+
+template <int N, int P>
+constexpr int fused_threads() { return N / P * N; }
+
+// v exp(2 pi i M / P) for a compile-time M (free for P = 2, 4)
+template <int P, int M, typename R>
+__device__ __forceinline__ cx<R> root_mul(cx<R> v) {
+  if constexpr (M % P == 0) return v;
+  else return twiddle<P, +1>(v, M % P);
+}
+
+// G_s over the volume of one term, staged in LDS at vol[k'][k2][k1] (tables
+// are [k0][k2][k1]).  Only the half space k2 < N/2 is read: gamma = alpha +
+// i beta is real-pair and even in k and Fh of real F is Hermitian, so with
+// A = alpha Fh, B = beta Fh at the inputs k_j = (a + NP j, k2, bq),
+//   sum_j r^j Zh(k_j)  = SA + i SB,          SA = sum_j r^j A_j, SB likewise,
+//   sum_j r^-j Zh(-k_j) = conj(SA) + i conj(SB),
+// where r = exp(2 pi i S / P).  The mirrored inputs -k_j are the inputs of
+// G_s(am, N - k2, bm) in the order that gives roots conj(r^j) and twiddle
+// conj(tw) (am = -a mod NP, bm = -bq mod N).  The plane k2 = N/2 vanishes
+// (sigma(N/2) = 0).
+// SA += sum_j r^j alpha_j Fh_j, SB += sum_j r^j beta_j Fh_j, r = exp(2 pi i S / P),
+// over j = JJ .. P-1 (compile-time recursion, so every root is a constant)
+template <int P, int S, int JJ = 0, typename R>
+__device__ __forceinline__ void accum_roots(const cx<R> (&g)[P], const cx<R> (&fv)[P], cx<R>& SA,
+                                            cx<R>& SB) {
+  if constexpr (JJ < P) {
+    const R al = g[JJ].x, be = g[JJ].y;
+    SA = cadd(SA, root_mul<P, JJ * S>(cx<R>{al * fv[JJ].x, al * fv[JJ].y}));
+    SB = cadd(SB, root_mul<P, JJ * S>(cx<R>{be * fv[JJ].x, be * fv[JJ].y}));
+    accum_roots<P, S, JJ + 1>(g, fv, SA, SB);
+  }
+}
+
+template <typename R, int N, int P, int S>
+__device__ __forceinline__ void gather_term(const cx<R>* __restrict__ Gt,
+                                            const cx<R>* __restrict__ Fc, int a, int bq,
+                                            int am, int bm, cx<R> tw, cx<R>* vol) {
+  constexpr int NP = N / P, LD = N + 1;
+  static_assert((N / 2) % 4 == 0, "half-space planes come in groups of 4");
+  const cx<R> twc = {tw.x, -tw.y};
+#pragma unroll 1
+  for (int k2 = 0; k2 < N / 2; k2 += 4) {
+    cx<R> gl[4][P], fl[4][P];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int idx = ((a + NP * j) * N + k2 + u) * N + bq;
+        gl[u][j] = Gt[idx];
+        fl[u][j] = Fc[idx];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k2 + u;
+      cx<R> SA = {(R)0, (R)0}, SB = {(R)0, (R)0};
+      accum_roots<P, S>(gl[u], fl[u], SA, SB);
+      vol[(a * N + kk) * LD + bq] = cmul(tw, cx<R>{SA.x - SB.y, SA.y + SB.x});
+      if (kk > 0) vol[(am * N + (N - kk)) * LD + bm] = cmul(twc, cx<R>{SA.x + SB.y, SB.x - SA.y});
+    }
+  }
+  vol[(a * N + N / 2) * LD + bq] = {(R)0, (R)0};
+}
+
+template <typename R, int N, int P, int S = 0>
+__device__ __forceinline__ void gather_term_s(int s, const cx<R>* __restrict__ Gt,
+                                              const cx<R>* __restrict__ Fc, int a, int bq,
+                                              int am, int bm, cx<R> tw, cx<R>* vol) {
+  if (s == S) gather_term<R, N, P, S>(Gt, Fc, a, bq, am, bm, tw, vol);
+  else if constexpr (S + 1 < P) gather_term_s<R, N, P, S + 1>(s, Gt, Fc, a, bq, am, bm, tw, vol);
+}
+
+template <typename R, int N, int P>
+__global__ __launch_bounds__(N / P * N) void k_fused(
+    const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int J,
+    const double* f, const int64_t* __restrict__ off, int64_t cell0, int ncells,
+    double* Q, double dt) {
+  constexpr int NP = N / P;             // x rows per workgroup
+  constexpr int T = NP * N;             // threads
+  constexpr int LD = N + 1;             // padded LDS row
+  constexpr int n = N * N * N;
+  __shared__ cx<R> vol[NP * N * LD];
+  const int blk = blockIdx.x;
+  const int s = (blk / 8) % P;
+  const int cc = (blk / (8 * P)) * 8 + blk % 8;
+  if (cc >= ncells) return;             // whole workgroup
+  const int th = threadIdx.x;
+  const int a = th / N;                 // k' (z and y passes)
+  const int bq = th % N;                // k1 (z pass), z (y pass)
+  const cx<R> tw = unit_root<N, R>((a * s) % N);
+  const int am = (NP - a) % NP, bm = (N - bq) % N;   // mirror of (a, bq)
+
+  const cx<R>* Fc = Fh + (int64_t)cc * n;
+  const int64_t base = off[cell0 + cc];
+  const double* fc = f + base;
+  double acc[P][NP];
+  cx<R> v[N];
+  for (int it = 0; it < J; ++it) {
+    const int term = it == 0 ? J - 1 : it - 1;      // loss first
+    const cx<R>* Gt = G + (int64_t)term * n;
+    __syncthreads();                    // the previous term's x pass is done with vol
+    gather_term_s<R, N, P>(s, Gt, Fc, a, bq, am, bm, tw, vol);
+    __syncthreads();                    // mirrored entries land in other threads' columns
+#pragma unroll
+    for (int k2 = 0; k2 < N; ++k2) v[k2] = vol[(a * N + k2) * LD + bq];
+    fft_line<N, +1>(v);                 // along z: (k', k1 = bq, z), same column
+#pragma unroll
+    for (int z = 0; z < N; ++z) vol[(a * N + z) * LD + bq] = v[z];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < N; ++k1) v[k1] = vol[(a * N + bq) * LD + k1];
+    fft_line<N, +1>(v);                 // along y: (k', y, z = bq)
+    __syncthreads();
+#pragma unroll
+    for (int y = 0; y < N; ++y) vol[(a * N + y) * LD + bq] = v[y];
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int line = th + T * p;      // (y, z) of this x line
+      const int y = line / N, z = line % N;
+      cx<R> u[NP];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) u[q] = vol[(q * N + y) * LD + z];
+      fft_line<NP, +1>(u);              // x = P q + s
+      if (it == 0) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q)
+          acc[p][q] = -fc[((P * q + s) * N + y) * N + z] * (double)u[q].x;
+      } else {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) acc[p][q] += (double)u[q].x * (double)u[q].y;
+      }
+    }
+  }
+  double* qc = Q + base;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int line = th + T * p;
+    const int y = line / N, z = line % N;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int idx = ((P * q + s) * N + y) * N + z;
+      qc[idx] = dt == 0.0 ? acc[p][q] : fc[idx] + dt * acc[p][q];
+    }
+  }
+}
+
+template <typename R, int N, int P>
+static hipError_t launch_fused_t(const ChunkArgs& a, hipStream_t st) {
+  cx<R>* W = (cx<R>*)a.W;
+  hipError_t e = launch_fwd(a, st);
+  if (e != hipSuccess) return e;
+  if (a.ev) (void)hipEventRecord(a.ev[1], st);
+  const int64_t pencils = (int64_t)a.ncells * N * N;
+  hipLaunchKernelGGL((k_fwdx<R, N>), dim3((unsigned)((pencils + 63) / 64)), dim3(64), 0, st, W,
+                     a.ncells);
+  if (a.ev) (void)hipEventRecord(a.ev[2], st);
+  const int64_t groups8 = (a.ncells + 7) / 8;
+  hipLaunchKernelGGL((k_fused<R, N, P>), dim3((unsigned)(groups8 * 8 * P)),
+                     dim3(fused_threads<N, P>()), 0, st, (const cx<R>*)W,
+                     (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
+  if (a.ev) (void)hipEventRecord(a.ev[3], st);
+  return hipGetLastError();
+}
+
+int fused_default_split(int N, int precision) {
+  if (precision == 2) return 0;         // split-BF16 keeps its MFMA x pass
+  switch (N) {
+    case 16: return 1;
+    case 24: return 2;
+    case 32: return precision == 0 ? 4 : 2;
+    default: return 0;
+  }
+}
+
+bool fused_supported(int N, int precision, int split) {
+  if (precision == 2) return false;
+  switch (N) {
+    case 16: return split == 1 || split == 2;
+    case 24: return split == 2 || split == 3;
+    case 32: return split == 2 ? precision != 0 : split == 4;
+    default: return false;
+  }
+}
+
+hipError_t launch_fused(const ChunkArgs& a, int split, hipStream_t st) {
+  if (a.ncells <= 0) return hipSuccess;
+  if (a.d != 3 || !fused_supported(a.N, a.precision, split)) return hipErrorInvalidValue;
+  if (a.precision == 0) {
+    if (a.N == 16) return split == 1 ? launch_fused_t<double, 16, 1>(a, st)
+                                     : launch_fused_t<double, 16, 2>(a, st);
+    if (a.N == 24) return split == 2 ? launch_fused_t<double, 24, 2>(a, st)
+                                     : launch_fused_t<double, 24, 3>(a, st);
+    return launch_fused_t<double, 32, 4>(a, st);
+  }
+  if (a.N == 16) return split == 1 ? launch_fused_t<float, 16, 1>(a, st)
+                                   : launch_fused_t<float, 16, 2>(a, st);
+  if (a.N == 24) return split == 2 ? launch_fused_t<float, 24, 2>(a, st)
+                                   : launch_fused_t<float, 24, 3>(a, st);
+  return split == 2 ? launch_fused_t<float, 32, 2>(a, st) : launch_fused_t<float, 32, 4>(a, st);
+}
+
+}  // namespace efm
