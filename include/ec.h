@@ -149,7 +149,9 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
  * accumulates the gain in FP64 registers, so no per-term intermediate touches
  * device memory; splits: N = 16: 1, 2; N = 24: 2, 3; N = 32: 4 (FP32 also 2).
  * 0 for cells_per_pass or term_groups selects the default (chosen from the
- * cache size); the autotuner picks measured values.  Reallocates the workspace (synchronises
+ * cache size); the autotuner picks measured values.  A new batch starts with
+ * the fused schedule where it exists and the group has at least 32 cells,
+ * and with the two-pass schedule otherwise.  Reallocates the workspace (synchronises
  * the device); call it outside graph capture.
  */
 #define EC_SCHED_PIPELINE 0
