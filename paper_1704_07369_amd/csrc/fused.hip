@@ -91,13 +91,17 @@ __device__ __forceinline__ void gather_term(const cx<R>* __restrict__ Gt,
                                             const cx<R>* __restrict__ Fc, int a, int bq,
                                             int am, int bm, cx<R> tw, cx<R>* vol) {
   constexpr int NP = N / P, LD = N + 1;
-  static_assert((N / 2) % 4 == 0, "half-space planes come in groups of 4");
+  // planes per group: all of a group's loads are in flight together (8-plane
+  // groups measured slower at 32^3: the gather is bound by L2-to-CU delivery,
+  // about 42 of 64 B/clk, not by latency)
+  constexpr int GP = 4;
+  static_assert((N / 2) % GP == 0, "half-space planes come in whole groups");
   const cx<R> twc = {tw.x, -tw.y};
 #pragma unroll 1
-  for (int k2 = 0; k2 < N / 2; k2 += 4) {
-    cx<R> gl[4][P], fl[4][P];
+  for (int k2 = 0; k2 < N / 2; k2 += GP) {
+    cx<R> gl[GP][P], fl[GP][P];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < GP; ++u) {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         const int idx = ((a + NP * j) * N + k2 + u) * N + bq;
@@ -106,7 +110,7 @@ __device__ __forceinline__ void gather_term(const cx<R>* __restrict__ Gt,
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < GP; ++u) {
       const int kk = k2 + u;
       cx<R> SA = {(R)0, (R)0}, SB = {(R)0, (R)0};
       accum_roots<P, S>(gl[u], fl[u], SA, SB);
