@@ -106,7 +106,18 @@ def sampled_error(E, b, Q, cells, cell_ids, oplan, efm, npts=64):
     return worst
 
 
-def roofline(prof, flops_cell, peak):
+# HBM bytes per launch of the dominant kernels, 2 FETCH_SIZE + WRITE_SIZE (factors
+# from the ec_copy calibration) of the run recorded in
+# profiles/collide_n32_m32_default_counters.md; keyed by (kernel, precision,
+# cells per launch) and valid for that code only (re-measure after changing it)
+MEASURED_TRAFFIC = {
+    ("k_fused", "f64", 256): (2 * 624075 + 65536) * 1024,
+    ("k_fused", "f32", 256): (2 * 257495 + 66560) * 1024,
+    ("k_pencil", "bf16x3", 1024): (2 * 239598 + 8650752) * 1024,
+}
+
+
+def roofline(prof, flops_cell, peak, prec="f64"):
     """Dominant kernel of the timed region: algorithmic flops it performed
     over its summed duration (HIP events on the launch stream)."""
     ms, launches, cells = prof
@@ -115,7 +126,9 @@ def roofline(prof, flops_cell, peak):
     achieved = fl * cells / (ms[k] * 1e-3) / 1e12
     return {
         "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-        "frac": round(achieved / peak, 4), "traffic": None, "kernel": KNAMES[k],
+        "frac": round(achieved / peak, 4),
+        "traffic": MEASURED_TRAFFIC.get((KNAMES[k], prec, round(cells / max(1, launches[k])))),
+        "kernel": KNAMES[k],
         "avg_launch_ms": round(ms[k] / max(1, launches[k]), 5),
         "launches": int(launches[k]), "cells_per_launch": cells / max(1, launches[k]),
         "flops_per_launch": fl * cells / max(1, launches[k]),
@@ -362,10 +375,10 @@ def main():
     }
     if ev32 is not None:
         out["fp32"] = {"value": ev32, "ms_per_step": t32 / args.steps * 1e3,
-                       "roofline": roofline(prof32, flops, PEAK_FP32)}
+                       "roofline": roofline(prof32, flops, PEAK_FP32, "f32")}
     if evb is not None:
         out["bf16x3"] = {"value": evb, "ms_per_step": tb / args.steps * 1e3,
-                         "roofline": roofline(profb, flops, PEAK_FP32)}
+                         "roofline": roofline(profb, flops, PEAK_FP32, "bf16x3")}
     if t1_64 is not None:
         out["single_cell"] = {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6}
     if not args.skip_relax:
