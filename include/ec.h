@@ -221,6 +221,19 @@ int ec_step(ec_batch* batch, double* f, double dt, int n_steps,
             double* monitors, void* hip_stream);
 
 /*
+ * ec_step_ssprk3 -- n_steps steps of the third-order strong-stability-
+ * preserving Runge-Kutta method (the time integrator of the paper's numerical
+ * experiments, section 4; Shu-Osher form: u1 = f + dt Q(f), u2 = 3/4 f +
+ * 1/4 (u1 + dt Q(u1)), f <- 1/3 f + 2/3 (u2 + dt Q(u2))), in place on f,
+ * with the same graph replay, monitors and arguments as ec_step.  Each step
+ * is a convex combination of forward-Euler steps, so the positivity condition
+ * of ec_step applies per stage.  The first call allocates two stage buffers
+ * of the batch's size (synchronises the device; call it outside capture).
+ */
+int ec_step_ssprk3(ec_batch* batch, double* f, double dt, int n_steps, double* monitors,
+                   void* hip_stream);
+
+/*
  * Profiling of ec_collide (tracing).  While enabled, ec_collide records HIP
  * events on its stream around its kernels.  ec_profile_read waits for them and
  * returns, per group g of the batch and kernel k (EC_PROF_KERNELS per group:

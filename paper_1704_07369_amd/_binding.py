@@ -58,6 +58,7 @@ _SIGS = {
     "ec_entropy_prod": ([_vp, _vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_monitors": ([_vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_step": ([_vp, _vp, _c_double, _c_int, _vp, _vp], _c_int),
+    "ec_step_ssprk3": ([_vp, _vp, _c_double, _c_int, _vp, _vp], _c_int),
     "ec_batch_set_schedule": ([_vp, _c_int, _c_int, _c_int, _c_int], _c_int),
     "ec_batch_get_schedule": ([_vp, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
                                ctypes.POINTER(_c_int)], _c_int),
@@ -225,6 +226,11 @@ def ec_monitors(batch, f, Q, out, stream=None):
 
 def ec_step(batch, f, dt, n_steps, monitors=None, stream=None):
     return _check(lib().ec_step(batch, _ptr(f), dt, n_steps, _ptr(monitors), _stream(stream)))
+
+
+def ec_step_ssprk3(batch, f, dt, n_steps, monitors=None, stream=None):
+    return _check(lib().ec_step_ssprk3(batch, _ptr(f), dt, n_steps, _ptr(monitors),
+                                       _stream(stream)))
 
 
 def ec_profile(batch, enable=True):

@@ -77,8 +77,15 @@ class Batch:
     def monitors(self, f, Q, out, stream=None):
         B.ec_monitors(self.handle, f, Q, out, stream)
 
-    def step(self, f, dt, n_steps, monitors=None, stream=None):
-        B.ec_step(self.handle, f, dt, n_steps, monitors, stream)
+    def step(self, f, dt, n_steps, monitors=None, stream=None, method="euler"):
+        """n_steps time steps in place on f: method "euler" (ec_step) or
+        "ssprk3" (ec_step_ssprk3)."""
+        if method == "euler":
+            B.ec_step(self.handle, f, dt, n_steps, monitors, stream)
+        elif method == "ssprk3":
+            B.ec_step_ssprk3(self.handle, f, dt, n_steps, monitors, stream)
+        else:
+            raise ValueError(f"unknown method {method!r}")
 
     def profile(self, enable=True):
         B.ec_profile(self.handle, enable)

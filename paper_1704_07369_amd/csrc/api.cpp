@@ -77,6 +77,7 @@ struct StepGraph {
   double* f = nullptr;
   double dt = 0.0;
   double* mon = nullptr;
+  int method = 0;      // 0 forward Euler, 1 SSP-RK3
 };
 
 struct ProfRec {
@@ -102,6 +103,7 @@ struct ec_batch {
   size_t ws_bytes = 0;
   int* d_step = nullptr;
   StepGraph graph;
+  double* d_rk = nullptr;   // SSP-RK3 stage states: 2 x n_elems (allocated on first use)
 };
 
 namespace {
@@ -478,6 +480,7 @@ int ec_batch_destroy(ec_batch* b) {
   if (b->d_hd) (void)hipFree(b->d_hd);
   if (b->d_ws) (void)hipFree(b->d_ws);
   if (b->d_step) (void)hipFree(b->d_step);
+  if (b->d_rk) (void)hipFree(b->d_rk);
   delete b;
   return EC_OK;
 }
@@ -746,51 +749,107 @@ int ec_monitors(ec_batch* b, const double* f, const double* Q, double* out, void
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// One time step of `method` on f in place, recorded on stream s (captured).
+int record_step(ec_batch* b, double* f, double dt, int method, double* monitors, hipStream_t s) {
+  int rc = EC_OK;
+  if (method == 0) {
+    rc = run_collide(b, f, f, dt, s);
+  } else {
+    // Shu-Osher form: u1 = f + dt Q(f); u2 = 3/4 f + 1/4 (u1 + dt Q(u1));
+    // f <- 1/3 f + 2/3 (u2 + dt Q(u2)).  u1 and u2 share a buffer.
+    double* u = b->d_rk;
+    double* w = b->d_rk + b->n_elems;
+    rc = run_collide(b, f, u, dt, s);
+    if (rc == EC_OK) rc = run_collide(b, u, w, dt, s);
+    if (rc == EC_OK) {
+      hipError_t e = launch_axpby_cells(f, w, u, 0.75, 0.25, b->d_off, b->d_n, b->n_cells, s);
+      if (e != hipSuccess) rc = fail(EC_ERR_DEVICE, hipGetErrorString(e));
+    }
+    if (rc == EC_OK) rc = run_collide(b, u, w, dt, s);
+    if (rc == EC_OK) {
+      hipError_t e = launch_axpby_cells(f, w, f, 1.0 / 3.0, 2.0 / 3.0, b->d_off, b->d_n,
+                                        b->n_cells, s);
+      if (e != hipSuccess) rc = fail(EC_ERR_DEVICE, hipGetErrorString(e));
+    }
+  }
+  if (rc == EC_OK && monitors) {
+    hipError_t e2 = launch_monitors(f, nullptr, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, nullptr,
+                                    nullptr, nullptr, b->d_step, monitors, b->n_cells,
+                                    b->d_step + 1, s);
+    if (e2 == hipSuccess) e2 = launch_inc_int(b->d_step, s);
+    if (e2 != hipSuccess) rc = fail(EC_ERR_DEVICE, hipGetErrorString(e2));
+  }
+  return rc;
+}
+
+int run_steps(ec_batch* b, double* f, double dt, int n_steps, double* monitors, int method,
+              hipStream_t s) {
+  if (n_steps < 0 || !(dt > 0.0)) return fail(EC_ERR_ARG, "need dt > 0 and n_steps >= 0");
+  if (n_steps == 0) return EC_OK;
+  if (method == 1 && !b->d_rk) {
+    HIPCHK(hipDeviceSynchronize());
+    void* p = nullptr;
+    if (hipMalloc(&p, 2 * (size_t)b->n_elems * sizeof(double)) != hipSuccess)
+      return fail(EC_ERR_OOM, "SSP-RK3 stage buffers");
+    b->d_rk = (double*)p;
+  }
+  if (!(b->graph.exec && b->graph.f == f && b->graph.dt == dt && b->graph.mon == monitors &&
+        b->graph.method == method)) {
+    drop_graph(b);
+    // capture one step; replays advance the device step counter
+    hipStream_t cap_stream;
+    HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+    int rc2 = EC_OK;
+    if (e == hipSuccess) {
+      rc2 = record_step(b, f, dt, method, monitors, cap_stream);
+      hipError_t e3 = hipStreamEndCapture(cap_stream, &graph);
+      if (rc2 == EC_OK && e3 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e3));
+    } else {
+      rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e));
+    }
+    if (rc2 == EC_OK) {
+      hipError_t e4 = hipGraphInstantiate(&b->graph.exec, graph, nullptr, nullptr, 0);
+      if (e4 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e4));
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap_stream);
+    if (rc2) { drop_graph(b); return rc2; }
+    b->graph.f = f;
+    b->graph.dt = dt;
+    b->graph.mon = monitors;
+    b->graph.method = method;
+  }
+  // step counter and the capacity of the monitor buffer (in steps)
+  HIPCHK(launch_set_int(b->d_step, 0, s));
+  HIPCHK(launch_set_int(b->d_step + 1, monitors ? n_steps : 0, s));
+  for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(b->graph.exec, s));
+  return EC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ec_step(ec_batch* b, double* f, double dt, int n_steps, double* monitors, void* stream) {
   return guarded([&]() -> int {
     int rc = check_batch_ptrs(b, f, nullptr);
     if (rc) return rc;
-    if (n_steps < 0 || !(dt > 0.0)) return fail(EC_ERR_ARG, "need dt > 0 and n_steps >= 0");
-    hipStream_t s = (hipStream_t)stream;
-    if (n_steps == 0) return EC_OK;
-    if (!(b->graph.exec && b->graph.f == f && b->graph.dt == dt && b->graph.mon == monitors)) {
-      drop_graph(b);
-      // capture one step; replays advance the device step counter
-      hipStream_t cap_stream;
-      HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-      hipGraph_t graph = nullptr;
-      hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-      int rc2 = EC_OK;
-      if (e == hipSuccess) {
-        rc2 = run_collide(b, f, f, dt, cap_stream);
-        if (rc2 == EC_OK && monitors) {
-          hipError_t e2 = launch_monitors(f, nullptr, b->d_off, b->d_n, b->d_hd, 0, b->n_cells,
-                                          nullptr, nullptr, nullptr, b->d_step, monitors,
-                                          b->n_cells, b->d_step + 1, cap_stream);
-          if (e2 == hipSuccess) e2 = launch_inc_int(b->d_step, cap_stream);
-          if (e2 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e2));
-        }
-        hipError_t e3 = hipStreamEndCapture(cap_stream, &graph);
-        if (rc2 == EC_OK && e3 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e3));
-      } else {
-        rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e));
-      }
-      if (rc2 == EC_OK) {
-        hipError_t e4 = hipGraphInstantiate(&b->graph.exec, graph, nullptr, nullptr, 0);
-        if (e4 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e4));
-      }
-      if (graph) (void)hipGraphDestroy(graph);
-      (void)hipStreamDestroy(cap_stream);
-      if (rc2) { drop_graph(b); return rc2; }
-      b->graph.f = f;
-      b->graph.dt = dt;
-      b->graph.mon = monitors;
-    }
-    // step counter and the capacity of the monitor buffer (in steps)
-    HIPCHK(launch_set_int(b->d_step, 0, s));
-    HIPCHK(launch_set_int(b->d_step + 1, monitors ? n_steps : 0, s));
-    for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(b->graph.exec, s));
-    return EC_OK;
+    return run_steps(b, f, dt, n_steps, monitors, 0, (hipStream_t)stream);
+  });
+}
+
+int ec_step_ssprk3(ec_batch* b, double* f, double dt, int n_steps, double* monitors,
+                   void* stream) {
+  return guarded([&]() -> int {
+    int rc = check_batch_ptrs(b, f, nullptr);
+    if (rc) return rc;
+    return run_steps(b, f, dt, n_steps, monitors, 1, (hipStream_t)stream);
   });
 }
 

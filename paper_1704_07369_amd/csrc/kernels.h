@@ -47,6 +47,10 @@ hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
                            int64_t step_stride, const int* step_cap, hipStream_t s);
 
 hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s);
+// out = a x + b y over the n points of each of the first ncells cells
+hipError_t launch_axpby_cells(const double* x, const double* y, double* out, double a, double b,
+                              const int64_t* off, const int* cell_n, int64_t ncells,
+                              hipStream_t s);
 hipError_t launch_set_int(int* p, int v, hipStream_t s);
 hipError_t launch_inc_int(int* p, hipStream_t s);
 

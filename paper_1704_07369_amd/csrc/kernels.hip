@@ -341,6 +341,26 @@ hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// out = a x + b y over the n points of every cell (one block per cell; out may
+// alias x or y: each point is read and written by one thread)
+__global__ __launch_bounds__(256) void k_axpby_cells(const double* x, const double* y, double* out,
+                                                     double a, double b,
+                                                     const int64_t* __restrict__ off,
+                                                     const int* __restrict__ cell_n) {
+  const int64_t o = off[blockIdx.x];
+  const int n = cell_n[blockIdx.x];
+  for (int r = threadIdx.x; r < n; r += 256) out[o + r] = a * x[o + r] + b * y[o + r];
+}
+
+hipError_t launch_axpby_cells(const double* x, const double* y, double* out, double a, double b,
+                              const int64_t* off, const int* cell_n, int64_t ncells,
+                              hipStream_t s) {
+  if (ncells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby_cells, dim3((unsigned)ncells), dim3(256), 0, s, x, y, out, a, b, off,
+                     cell_n);
+  return hipGetLastError();
+}
+
 __global__ void k_set_int(int* p, int v) { *p = v; }
 __global__ void k_inc_int(int* p) { *p += 1; }
 
