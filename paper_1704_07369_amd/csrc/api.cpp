@@ -14,6 +14,7 @@
 
 #include "../../include/ec.h"
 #include "fused.h"
+#include "large2d.h"
 #include "internal.h"
 #include "kernels.h"
 #include "pipe.h"
@@ -61,7 +62,12 @@ struct ec_plan {
   int device = 0;
   void* d_gamma64 = nullptr;   // [J][n] double pairs
   void* d_gamma32 = nullptr;   // [J][n] float pairs
+  void* d_tw = nullptr;        // 2D grids of N >= 64: exp(2 pi i j / N), j < N
 };
+
+namespace {
+bool is_large2d(const HostTables& T) { return T.d == 2 && large2d_supported(T.N); }
+}  // namespace
 
 struct BatchGroup {
   const ec_plan* plan = nullptr;
@@ -131,6 +137,13 @@ void default_schedule(BatchGroup& g, int precision) {
     const int64_t slab_blocks = ((int64_t)g.chunk * T.N + spb - 1) / spb;
     int G = (int)std::max<int64_t>(1, (1024 + slab_blocks - 1) / slab_blocks);
     g.G = std::min(G, std::min(T.J, 16));
+  } else if (is_large2d(T)) {
+    // per cell N^2 (spectrum) + J N^2 (per-term columns) complex FP64: keep a
+    // pass under ~2 GiB of workspace
+    const double per_cell = (double)(T.J + 1) * T.n * 16.0;
+    const int64_t c = (int64_t)std::max(1.0, std::floor(2.0 * 1073741824.0 / per_cell));
+    g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, count));
+    g.G = 1;
   } else {
     // two-pass: aim for about 2048 waves in the slab pass (N0 * N threads per cell)
     const int64_t threads_per_cell = (int64_t)T.n0 * T.n1;
@@ -153,7 +166,7 @@ size_t group_ws_bytes(const BatchGroup& g, int precision) {
     return 2 * ((size_t)g.chunk * n * cs + (size_t)g.chunk * T.J * n * cs +
                 (size_t)g.G * g.chunk * n * 8 + (size_t)g.chunk * n * 8) + 8 * 256;
   size_t bytes = (size_t)g.chunk * n * cs + 256;
-  if (T.d == 3) bytes += (size_t)g.chunk * T.J * n * cs + 256;
+  if (T.d == 3 || is_large2d(T)) bytes += (size_t)g.chunk * T.J * n * cs + 256;
   return bytes;
 }
 
@@ -209,11 +222,12 @@ int run_group_two_pass(ec_batch* b, int gi, const double* f, double* Q, double d
     ChunkArgs a;
     a.N = T.N; a.d = T.d; a.precision = b->precision; a.J = T.J;
     a.gamma = fp32_tables(b->precision) ? g.plan->d_gamma32 : g.plan->d_gamma64;
-    a.W = W; a.Z = T.d == 3 ? Z : nullptr;
+    a.W = W; a.Z = (T.d == 3 || is_large2d(T)) ? Z : nullptr;
     a.f = f; a.Q = Q; a.off = b->d_off;
     a.cell0 = g.first + c0;
     a.ncells = (int)std::min<int64_t>(g.chunk, g.count - c0);
     a.dt = dt;
+    a.tw = g.plan->d_tw;
     ProfRec rec{};
     if (profile) {
       rec.group = gi; rec.ncells = a.ncells; rec.kind = 0;
@@ -221,7 +235,11 @@ int run_group_two_pass(ec_batch* b, int gi, const double* f, double* Q, double d
       if (rc) return rc;
       a.ev = rec.ev;
     }
-    HIPCHK(launch_chunk(a, s));
+    if (is_large2d(T)) {
+      HIPCHK(launch_large2d(a, a.tw, s));
+    } else {
+      HIPCHK(launch_chunk(a, s));
+    }
     if (profile) b->prof.push_back(rec);
   }
   return EC_OK;
@@ -382,6 +400,17 @@ int ec_setup_kernel(int N, int d, double L, const ec_kernel* kernel, int M, ec_p
       ec_plan_destroy(p);
       return fail(EC_ERR_DEVICE, "upload of plan tables failed");
     }
+    if (is_large2d(p->host)) {
+      const std::vector<double> tw = twiddle_table(N);
+      if (hipMalloc(&p->d_tw, tw.size() * sizeof(double)) != hipSuccess) {
+        ec_plan_destroy(p);
+        return fail(EC_ERR_OOM, "twiddle table");
+      }
+      if (hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        ec_plan_destroy(p);
+        return fail(EC_ERR_DEVICE, "upload of the twiddle table failed");
+      }
+    }
     *out = p;
     return EC_OK;
   });
@@ -391,6 +420,7 @@ int ec_plan_destroy(ec_plan* p) {
   if (!p) return EC_OK;
   if (p->d_gamma64) (void)hipFree(p->d_gamma64);
   if (p->d_gamma32) (void)hipFree(p->d_gamma32);
+  if (p->d_tw) (void)hipFree(p->d_tw);
   delete p;
   return EC_OK;
 }
@@ -418,6 +448,10 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
         if (plans[g] && counts[g] > 0 &&
             !(plans[g]->host.d == 3 && (plans[g]->host.N == 16 || plans[g]->host.N == 32)))
           return fail(EC_ERR_UNSUPPORTED, "split-BF16 transforms need 3D cells with N = 16 or 32");
+    if (precision != EC_FP64)
+      for (int g = 0; g < n_groups; ++g)
+        if (plans[g] && counts[g] > 0 && is_large2d(plans[g]->host))
+          return fail(EC_ERR_UNSUPPORTED, "2D grids of N >= 64 are FP64 only");
     *out = nullptr;
     auto* b = new ec_batch();
     b->precision = precision;

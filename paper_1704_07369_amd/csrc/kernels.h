@@ -23,6 +23,7 @@ struct ChunkArgs {
   int64_t cell0 = 0;               // first batch cell of the pass
   int ncells = 0;
   double dt = 0.0;
+  const void* tw = nullptr;        // 2D grids of N >= 64: exp(2 pi i j / N) table
   // optional: 4 events recorded before k_fwd, after k_fwd, after the x pass
   // and after k_slab (profiling; all on the launch stream)
   hipEvent_t* ev = nullptr;

@@ -75,8 +75,26 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 }
 
 bool supported_size(int N, int d) {
-  (void)d;
-  return N == 8 || N == 12 || N == 16 || N == 24 || N == 32;
+  if (N == 8 || N == 12 || N == 16 || N == 24 || N == 32) return true;
+  return d == 2 && (N == 64 || N == 128 || N == 256 || N == 512);   // LDS line transforms
+}
+
+std::vector<double> twiddle_table(int N) {
+  // exp(2 pi i j / N) as (cos, sin) pairs: the quarter turns are exact and the
+  // remainder r < N/4 is evaluated in long double, then rotated
+  static const long double PIL = 3.141592653589793238462643383279502884L;
+  std::vector<double> t(2 * (size_t)N);
+  for (int j = 0; j < N; ++j) {
+    const int q = (4 * j) / N;
+    const int rr = 4 * j - q * N;                     // angle 2 pi rr / (4N), rr < N
+    const long double a = 2.0L * PIL * (long double)rr / (4.0L * N);
+    const double c = rr == 0 ? 1.0 : (double)cosl(a), sn = rr == 0 ? 0.0 : (double)sinl(a);
+    double x = c, y = sn;
+    for (int k = 0; k < q; ++k) { const double u = x; x = -y; y = u; }   // times i
+    t[2 * j] = x;
+    t[2 * j + 1] = y;
+  }
+  return t;
 }
 
 static double sinc(double x) {
@@ -114,7 +132,10 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
                  int M, HostTables& T, std::string& err) {
   if (d != 2 && d != 3) { err = "d must be 2 or 3"; return EC_ERR_ARG; }
   if (N < 4 || M < 1 || !(L > 0.0)) { err = "need N >= 4, M >= 1, L > 0"; return EC_ERR_ARG; }
-  if (!supported_size(N, d)) { err = "unsupported N (supported: 8, 12, 16, 24, 32)"; return EC_ERR_UNSUPPORTED; }
+  if (!supported_size(N, d)) {
+    err = "unsupported N (supported: 8, 12, 16, 24, 32; in 2D also 64, 128, 256, 512)";
+    return EC_ERR_UNSUPPORTED;
+  }
   if (R <= 0.0) R = 4.0 * L / (3.0 * std::sqrt(2.0) + 1.0);
   const bool separable = (d == 2 && kind == EC_KERNEL_MAXWELL) || (d == 3 && kind == EC_KERNEL_HARD_SPHERE);
   if (!separable) { err = "only 2D Maxwell and 3D hard-sphere kernels are implemented"; return EC_ERR_UNSUPPORTED; }

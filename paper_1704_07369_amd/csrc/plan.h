@@ -31,4 +31,7 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 
 bool supported_size(int N, int d);
 
+// exp(2 pi i j / N), j < N, as interleaved (cos, sin) FP64 pairs
+std::vector<double> twiddle_table(int N);
+
 }  // namespace efm
