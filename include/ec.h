@@ -52,9 +52,20 @@ extern "C" {
  * which is constant (= 1/pi) -- hence separable in the fast algorithm --
  * for Maxwell molecules in 2D (gamma = 0) and hard spheres in 3D (gamma = 1).
  */
-#define EC_KERNEL_MAXWELL     0   /* gamma = 0                              */
+#define EC_KERNEL_MAXWELL     0   /* gamma = 0 (3D: non-separable)          */
 #define EC_KERNEL_HARD_SPHERE 1   /* gamma = 1                              */
-#define EC_KERNEL_VHS         2   /* general gamma (non-separable; reserved)*/
+#define EC_KERNEL_VHS         2   /* 3D, -1 < gamma <= 1 (non-separable)    */
+/*
+ * Non-separable kernels (3D Maxwell, VHS): the fast algorithm needs products
+ * alpha_{l+m} beta_l gamma_m (section 4.1); here the radius of y is
+ * discretised by n_radial Gauss-Legendre nodes (rho_j, omega_j) on [0, R],
+ * which separates the Carleman weight into M' = M n_radial products
+ *   psi_{t,j}(k) = 2 omega_j rho_j cos(pi rho_j k.e_t / L),
+ *   phi_{t,j}(k) = 4 pi int_0^R (rho_j^2 + r^2)^{(gamma-1)/2} J_0(q r) r dr,
+ *                  q = pi |k_perp| / L (k_perp: the part of k orthogonal to e_t),
+ * with the hard-sphere direction weights; gamma = 1 reproduces the
+ * hard-sphere kernel as n_radial grows.
+ */
 
 typedef struct ec_kernel {
   int kind;          /* EC_KERNEL_*                                          */
@@ -62,7 +73,7 @@ typedef struct ec_kernel {
   double R;          /* truncation radius of the Carleman integrals (section
                         1.2, eq. approximated_collision); R <= 0 selects the
                         largest R allowed by T >= (3 sqrt 2 + 1) R / 4        */
-  int n_radial;      /* radial nodes of a non-separable kernel (reserved)    */
+  int n_radial;      /* radial nodes of a non-separable kernel (<= 0: 8)     */
 } ec_kernel;
 
 /* ---- precision of the transforms --------------------------------------- */
@@ -100,7 +111,8 @@ int ec_setup_kernel(int N, int d, double L, const ec_kernel* kernel, int M,
                     ec_plan** out);
 int ec_plan_destroy(ec_plan* plan);
 
-/* Number of gain products M' of the plan (= M for the separable kernels). */
+/* Number of gain products M' of the plan (M for the separable kernels,
+ * M n_radial for the non-separable ones). */
 int ec_plan_terms(const ec_plan* plan, int* n_terms);
 
 /*

@@ -50,6 +50,7 @@ _lib = None
 
 KIND_MAXWELL = "maxwell"          # B = C_d |g|^0
 KIND_HARD_SPHERE = "hard_sphere"  # B = C_d |g|^1
+KIND_VHS = "vhs"                  # B = C_d |g|^gamma (3D Maxwell is gamma = 0)
 
 # Section 4.2: B(g, w) = 1/(2 pi) in 2D and 1/(4 pi) in 3D for Maxwell
 # molecules; the hard-sphere kernel keeps the same constant times |g|.
@@ -280,6 +281,64 @@ def lowrank_3d_hard_sphere(N: int, L: float, R: float, M: int) -> LowRank:
     return LowRank(0.5 * bt * w, U, V)
 
 
+def hankel_disk(q: np.ndarray, rho: float, a: float, R: float) -> np.ndarray:
+    """2 int_{|x|<=R, x in a plane} (rho^2 + |x|^2)^a cos(q x_1) dx
+    = 4 pi int_0^R (rho^2 + r^2)^a J_0(q r) r dr (the angular integral of the
+    disk is 2 pi J_0), by Gauss-Legendre in r.  rho > 0 keeps the weight
+    smooth.  a = 0 gives the hard-sphere disk integral."""
+    from scipy.special import j0
+    qmax = float(np.max(np.abs(q))) if q.size else 0.0
+    n = int(math.ceil(0.75 * qmax * R)) + 64
+    # the weight varies on the scale rho near r = 0: split there
+    rs = min(R, 8.0 * rho)
+    r1, w1 = gauss_legendre(n, 0.0, rs)
+    parts = [(r1, w1)]
+    if rs < R:
+        parts.append(gauss_legendre(n, rs, R))
+    r = np.concatenate([x for x, _ in parts])
+    w = np.concatenate([y for _, y in parts])
+    wt = 4.0 * math.pi * w * r * (rho * rho + r * r) ** a
+    out = np.empty(q.shape)
+    flat_q, flat_o = q.ravel(), out.ravel()
+    for c0 in range(0, flat_q.size, 2048):
+        blk = flat_q[c0:c0 + 2048]
+        flat_o[c0:c0 + 2048] = j0(np.outer(blk, r)) @ wt
+    return out
+
+
+def lowrank_3d_vhs(N: int, L: float, R: float, M: int, gamma: float, n_radial: int) -> LowRank:
+    """Variable hard spheres B = C_3 |g|^gamma in 3D: Carleman weight
+    Bt(y, z) = 2^2 C_3 (|y|^2 + |z|^2)^a with a = (gamma - 1)/2 (section 1),
+    which does not factor in (|y|, |z|).  The polar form of the 3D kernel
+    (as for hard spheres) keeps the factor inside both radial integrals;
+    discretising the radius of y by Gauss-Legendre (rho_j, omega_j) on [0, R]
+    (the integrand is even in rho) separates them (the form
+    alpha_{l+m} beta_l gamma_m of section 4.1, here with M' = M n_radial
+    terms):
+        psi_{t,j}(l) = 2 omega_j rho_j cos(pi rho_j l.e_t / T),
+        phi_{t,j}(m) = 2 int_{disk perp e_t} (rho_j^2 + |x|^2)^a cos(pi m.x / T) dx,
+    with the hemisphere rule over e_t and the constant (Bt/2) w_t as for hard
+    spheres.  gamma = 1 reduces to the hard-sphere kernel as n_radial grows."""
+    kx, ky, kz = mode_grid(N, 3)
+    dirs, w = directions_3d(M)
+    bt = 4.0 * C_D[3]
+    a = 0.5 * (gamma - 1.0)
+    rho, om = gauss_legendre(n_radial, 0.0, R)
+    T = len(w)
+    U = np.empty((T * n_radial, kx.size)); V = np.empty((T * n_radial, kx.size))
+    c = np.empty(T * n_radial)
+    kap2 = (kx * kx + ky * ky + kz * kz) * (math.pi / L) ** 2
+    for t in range(T):
+        s = math.pi / L * (kx * dirs[t, 0] + ky * dirs[t, 1] + kz * dirs[t, 2])
+        qperp = np.sqrt(np.maximum(kap2 - s * s, 0.0))
+        for j in range(n_radial):
+            i = t * n_radial + j
+            U[i] = 2.0 * om[j] * rho[j] * np.cos(rho[j] * s)
+            V[i] = hankel_disk(qperp, rho[j], a, R)
+            c[i] = 0.5 * bt * w[t]
+    return LowRank(c, U, V)
+
+
 # ----------------------------------------------------------------------------
 # Plan
 # ----------------------------------------------------------------------------
@@ -305,13 +364,20 @@ class Plan:
 
 
 def make_plan(N: int, d: int, L: float, M: int, kind: str | None = None,
-              R: float = 6.0, filtered: bool = True) -> Plan:
+              R: float = 6.0, filtered: bool = True, gamma: float | None = None,
+              n_radial: int = 8) -> Plan:
+    """kind None: 2D Maxwell / 3D hard spheres.  In 3D, KIND_MAXWELL is the
+    variable-hard-sphere kernel with gamma = 0 and KIND_VHS takes gamma; both
+    use n_radial radial nodes (M' = M n_radial terms)."""
     if kind is None:
         kind = KIND_MAXWELL if d == 2 else KIND_HARD_SPHERE
     if d == 2 and kind == KIND_MAXWELL:
         lr = lowrank_2d_maxwell(N, L, R, M)
     elif d == 3 and kind == KIND_HARD_SPHERE:
         lr = lowrank_3d_hard_sphere(N, L, R, M)
+    elif d == 3 and kind in (KIND_MAXWELL, KIND_VHS):
+        g = 0.0 if kind == KIND_MAXWELL else float(gamma)
+        lr = lowrank_3d_vhs(N, L, R, M, g, n_radial)
     else:
         raise NotImplementedError(f"oracle kernel {kind} in {d}D")
     sig = sigma_nd(N, d) if filtered else np.ones(N ** d)

@@ -370,7 +370,7 @@ int ec_host_tables(int N, int d, double L, const ec_kernel* kernel, int M, int* 
     if (!kernel) return fail(EC_ERR_ARG, "kernel is null");
     HostTables T;
     std::string err;
-    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, M, T, err);
+    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial, M, T, err);
     if (rc) return fail(rc, err);
     if (n_terms) *n_terms = T.terms;
     if (gamma) std::memcpy(gamma, T.gamma.data(), T.gamma.size() * sizeof(double));
@@ -384,7 +384,7 @@ int ec_setup_kernel(int N, int d, double L, const ec_kernel* kernel, int M, ec_p
     *out = nullptr;
     auto* p = new ec_plan();
     std::string err;
-    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, M, p->host, err);
+    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial, M, p->host, err);
     if (rc) { delete p; return fail(rc, err); }
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(EC_ERR_DEVICE, "no HIP device"); }
     const size_t cnt = p->host.gamma.size();
@@ -594,7 +594,12 @@ std::string tune_key(int dev, const HostTables& T, int precision, int64_t count)
   char buf[256];
   std::snprintf(buf, sizeof buf, "%s|d%d|N%d|M%d|kind%d|L%.6g|R%.6g|prec%d|cells%lld", arch.c_str(),
                 T.d, T.N, T.M, T.kind, T.L, T.R, precision, (long long)count);
-  return buf;
+  std::string key = buf;
+  if (T.n_radial > 1) {   // non-separable kernels: exponent and radial nodes too
+    std::snprintf(buf, sizeof buf, "|g%.6g|nr%d", T.gamma_exp, T.n_radial);
+    key += buf;
+  }
+  return key;
 }
 
 // cache format: one line per key, "<key> <mode> <chunk> <G> <ms>"

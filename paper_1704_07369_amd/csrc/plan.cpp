@@ -24,7 +24,9 @@
 //                   B_fast = (Bt/2) sum_t w_t psi_3 Phi over a hemisphere rule.
 #include "plan.h"
 
+#include <algorithm>
 #include <cmath>
+#include <thread>
 
 #include "../../include/ec.h"
 
@@ -121,6 +123,70 @@ static double phi3(double q, double R) {
   return 4.0 * PI * R * R * j1x;
 }
 
+// ---- non-separable kernels (variable hard spheres, 3D Maxwell) ----------------
+// Bt(y, z) = (1/pi) (|y|^2 + |z|^2)^a, a = (gamma - 1)/2, does not factor in
+// (|y|, |z|).  With Gauss-Legendre radii (rho_j, omega_j) on [0, R] for y the
+// polar form separates into M n_radial products
+//   psi_{t,j}(k) = 2 omega_j rho_j cos(rho_j s),                 s = pi k.e_t / L,
+//   phi_{t,j}(k) = Phi_j(q) = 4 pi int_0^R (rho_j^2 + r^2)^a J_0(q r) r dr,
+//                                                                q = pi |k_perp| / L,
+// with the hard-sphere weights w_t (reduces to psi_3 Phi as n_radial grows
+// when gamma = 1).  Phi_j is an entire function of q; it is sampled at the
+// Chebyshev points of [0, q_max] (each sample by Gauss-Legendre panels in r,
+// graded at r ~ rho_j where the weight changes) and evaluated by Clenshaw.
+struct ChebFn {
+  double qmax = 0.0;
+  std::vector<double> c;   // Chebyshev coefficients on [0, qmax]
+  double operator()(double q) const {
+    const double x = qmax > 0.0 ? 2.0 * q / qmax - 1.0 : -1.0;
+    double b1 = 0.0, b2 = 0.0;
+    for (int k = (int)c.size() - 1; k >= 1; --k) {
+      const double b0 = 2.0 * x * b1 - b2 + c[k];
+      b2 = b1;
+      b1 = b0;
+    }
+    return x * b1 - b2 + c[0];
+  }
+};
+
+static ChebFn hankel_cheb(double rho, double a, double R, double qmax) {
+  const double PI_ = 3.14159265358979323846;
+  // r panels [0, 2 rho], [2 rho, 8 rho], [8 rho, R] (clipped to R)
+  std::vector<double> edges = {0.0};
+  for (double e : {2.0 * rho, 8.0 * rho})
+    if (e < R) edges.push_back(e);
+  edges.push_back(R);
+  std::vector<double> rr, ww;
+  for (size_t p = 0; p + 1 < edges.size(); ++p) {
+    const double lo = edges[p], hi = edges[p + 1];
+    const int n = (int)std::ceil(0.6 * qmax * (hi - lo)) + 40;
+    std::vector<double> x, w;
+    gauss_legendre(n, x, w);
+    for (int i = 0; i < n; ++i) {
+      const double r = 0.5 * (hi - lo) * (x[i] + 1.0) + lo;
+      rr.push_back(r);
+      ww.push_back(0.5 * (hi - lo) * w[i] * 4.0 * PI_ * r * std::pow(rho * rho + r * r, a));
+    }
+  }
+  const int D = (int)std::ceil(0.75 * qmax * R) + 64;
+  std::vector<double> fv(D);
+  for (int m = 0; m < D; ++m) {
+    const double q = 0.5 * qmax * (1.0 + std::cos(PI_ * (m + 0.5) / D));
+    double acc = 0.0;
+    for (size_t i = 0; i < rr.size(); ++i) acc += ww[i] * std::cyl_bessel_j(0.0, q * rr[i]);
+    fv[m] = acc;
+  }
+  ChebFn f;
+  f.qmax = qmax;
+  f.c.assign(D, 0.0);
+  for (int k = 0; k < D; ++k) {
+    double acc = 0.0;
+    for (int m = 0; m < D; ++m) acc += fv[m] * std::cos(PI_ * k * (m + 0.5) / D);
+    f.c[k] = (k == 0 ? 1.0 : 2.0) * acc / D;
+  }
+  return f;
+}
+
 static void hemisphere_split(int M, int& mm, int& mp) {
   mm = 1;
   for (int a = 1; a <= M; ++a)
@@ -129,7 +195,7 @@ static void hemisphere_split(int M, int& mm, int& mp) {
 }
 
 int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
-                 int M, HostTables& T, std::string& err) {
+                 int n_radial, int M, HostTables& T, std::string& err) {
   if (d != 2 && d != 3) { err = "d must be 2 or 3"; return EC_ERR_ARG; }
   if (N < 4 || M < 1 || !(L > 0.0)) { err = "need N >= 4, M >= 1, L > 0"; return EC_ERR_ARG; }
   if (!supported_size(N, d)) {
@@ -138,15 +204,24 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
   }
   if (R <= 0.0) R = 4.0 * L / (3.0 * std::sqrt(2.0) + 1.0);
   const bool separable = (d == 2 && kind == EC_KERNEL_MAXWELL) || (d == 3 && kind == EC_KERNEL_HARD_SPHERE);
-  if (!separable) { err = "only 2D Maxwell and 3D hard-sphere kernels are implemented"; return EC_ERR_UNSUPPORTED; }
+  const bool radial = d == 3 && (kind == EC_KERNEL_MAXWELL || kind == EC_KERNEL_VHS);
+  if (!separable && !radial) {
+    err = "kernels: 2D Maxwell; 3D hard spheres, Maxwell and variable hard spheres";
+    return EC_ERR_UNSUPPORTED;
+  }
+  const double gexp = kind == EC_KERNEL_MAXWELL ? 0.0 : (kind == EC_KERNEL_HARD_SPHERE ? 1.0 : gamma_exp);
+  if (radial && !(gexp > -1.0 && gexp <= 1.0)) { err = "VHS needs -1 < gamma <= 1"; return EC_ERR_ARG; }
+  const int nrad = radial ? (n_radial > 0 ? n_radial : 8) : 1;
 
   T.N = N; T.d = d; T.M = M; T.kind = kind; T.L = L; T.R = R; T.gamma_exp = gamma_exp;
+  T.n_radial = nrad;
   T.n0 = (d == 3) ? N : 1;
   T.n1 = N;
   T.n2 = N;
   T.n = (int64_t)T.n0 * T.n1 * T.n2;
-  T.terms = M;
-  T.J = M + 1;
+  T.terms = M * nrad;
+  T.J = T.terms + 1;
+  T.gamma_exp = gexp;
 
   // directions: e[t], partner (2D) and weights w[t] (Bt folded in)
   std::vector<double> ex(M), ey(M), ez(M, 0.0), px(M, 0.0), py(M, 0.0), wt(M);
@@ -183,7 +258,25 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
   for (int i = 0; i < N; ++i) sig1[i] = jackson(N, i < (N + 1) / 2 ? i : i - N);
   auto mode = [N](int i) { return i < (N + 1) / 2 ? i : i - N; };
 
-  for (int i0 = 0; i0 < T.n0; ++i0)
+  // radial factors of the non-separable kernels
+  std::vector<double> rho, om;
+  std::vector<ChebFn> hank;
+  if (radial) {
+    std::vector<double> x, w;
+    gauss_legendre(nrad, x, w);
+    rho.resize(nrad);
+    om.resize(nrad);
+    for (int j = 0; j < nrad; ++j) {
+      rho[j] = 0.5 * R * (x[j] + 1.0);
+      om[j] = 0.5 * R * w[j];
+    }
+    double kmax2 = 0.0;   // largest |k|^2 over the modes bounds |k_perp|
+    for (int i = 0; i < N; ++i) kmax2 = std::max(kmax2, (double)mode(i) * mode(i));
+    const double qmax = kf * std::sqrt(3.0 * kmax2) * 1.0001;
+    for (int j = 0; j < nrad; ++j) hank.push_back(hankel_cheb(rho[j], 0.5 * (gexp - 1.0), R, qmax));
+  }
+
+  auto fill_slab = [&](int i0) {
     for (int i2 = 0; i2 < T.n2; ++i2)
       for (int i1 = 0; i1 < T.n1; ++i1) {
         const int64_t idx = ((int64_t)i0 * T.n2 + i2) * T.n1 + i1;
@@ -199,6 +292,18 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
         double diag = 0.0;
         for (int t = 0; t < M; ++t) {
           const double kd = kx * ex[t] + ky * ey[t] + kz * ez[t];
+          if (radial) {
+            const double q = kf * std::sqrt(std::max(0.0, k2 - kd * kd));
+            for (int j = 0; j < nrad; ++j) {
+              const size_t term = (size_t)t * nrad + j;
+              const double ps = 2.0 * om[j] * rho[j] * std::cos(rho[j] * kf * kd);
+              const double ph = hank[j](q);
+              T.gamma[(term * T.n + idx) * 2 + 0] = scale * wt[t] * sig * ps;
+              T.gamma[(term * T.n + idx) * 2 + 1] = scale * sig * ph;
+              diag += wt[t] * ps * ph;
+            }
+            continue;
+          }
           double ps, ph;
           if (d == 2) {
             ps = psi2(kf * kd, R);
@@ -211,9 +316,22 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
           T.gamma[((size_t)t * T.n + idx) * 2 + 1] = scale * sig * ph;
           diag += wt[t] * ps * ph;
         }
-        T.gamma[((size_t)M * T.n + idx) * 2 + 0] = scale * sig * sig * diag;
-        T.gamma[((size_t)M * T.n + idx) * 2 + 1] = 0.0;
+        T.gamma[((size_t)T.terms * T.n + idx) * 2 + 0] = scale * sig * sig * diag;
+        T.gamma[((size_t)T.terms * T.n + idx) * 2 + 1] = 0.0;
       }
+  };
+  // slabs in parallel on the host threads (each writes its own entries)
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (T.n0 * (int64_t)T.J * T.n2 * T.n1 < 4000000 || nth == 1) {
+    for (int i0 = 0; i0 < T.n0; ++i0) fill_slab(i0);
+  } else {
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nth; ++w)
+      pool.emplace_back([&, w]() {
+        for (int i0 = w; i0 < T.n0; i0 += nth) fill_slab(i0);
+      });
+    for (auto& th : pool) th.join();
+  }
   return EC_OK;
 }
 
