@@ -104,9 +104,12 @@ def test_library_rejects_bad_arguments():
     with pytest.raises(E.EcError) as ei:
         E.ec_host_tables(16, 3, -1.0, k, 32)
     assert ei.value.code == E.EC_ERR_ARG
-    with pytest.raises(E.EcError):
-        E.ec_host_tables(16, 3, 8.0, E.make_kernel(E.EC_KERNEL_VHS, 0.5, R), 32)
-    assert "kernel" in E.ec_last_error()
+    with pytest.raises(E.EcError) as ei:
+        E.ec_host_tables(16, 2, 8.0, E.make_kernel(E.EC_KERNEL_VHS, 0.5, R), 32)
+    assert ei.value.code == E.EC_ERR_UNSUPPORTED and "kernel" in E.ec_last_error()
+    with pytest.raises(E.EcError) as ei:
+        E.ec_host_tables(8, 3, 8.0, E.make_kernel(E.EC_KERNEL_VHS, 1.5, R), 8)
+    assert ei.value.code == E.EC_ERR_ARG
 
 
 def test_library_exports_every_declared_symbol():
