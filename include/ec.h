@@ -83,7 +83,7 @@ typedef struct ec_kernel {
 #define EC_BF16X3 2   /* as EC_FP32, but the inverse DFT along x of every term
                          runs on MFMA as a real (2N x 2N) DFT-matrix product
                          with split-BF16 operands (hi*hi + hi*lo + lo*hi, FP32
-                         accumulate); 3D cells with N = 16 or 32 only        */
+                         accumulate); 3D cells with N = 16, 32 or 64 only    */
 
 typedef struct ec_plan ec_plan;
 typedef struct ec_batch ec_batch;
@@ -91,8 +91,8 @@ typedef struct ec_batch ec_batch;
 /*
  * ec_setup_kernel -- build the FP64 tables of one (N, d, L, kernel, M) and
  * upload them to the current HIP device.
- *   N      points per axis; supported: d = 3: 8, 12, 16, 24, 32;
- *          d = 2: 8, 12, 16, 24, 32.
+ *   N      points per axis; supported: d = 3: 8, 12, 16, 24, 32, 64;
+ *          d = 2: 8, 12, 16, 24, 32, 64, 128, 256, 512 (N >= 64: FP64 only).
  *   d      2 or 3.
  *   L      half-width of the velocity box (> 0).
  *   M      number of products in the gain: d = 2: samples theta_t = t pi/(2M)

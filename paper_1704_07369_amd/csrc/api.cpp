@@ -122,6 +122,7 @@ void default_schedule(BatchGroup& g, int precision) {
   if (precision == EC_BF16X3) g.mode = EC_SCHED_TWO_PASS;   // the MFMA x pass is a separate kernel
   if (g.mode == EC_SCHED_FUSED && (T.d != 3 || fused_default_split(T.N, precision) == 0))
     g.mode = EC_SCHED_TWO_PASS;
+  if (g.mode == EC_SCHED_PIPELINE && T.N > 32) g.mode = EC_SCHED_TWO_PASS;   // register lines <= 32
   if (T.d == 3 && g.mode == EC_SCHED_FUSED) {
     // one spectrum per cell of workspace; 2048 cells keep >= 2048 workgroups busy
     g.chunk = (int)std::min<int64_t>(2048, count);
@@ -145,9 +146,12 @@ void default_schedule(BatchGroup& g, int precision) {
     g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, count));
     g.G = 1;
   } else {
-    // two-pass: aim for about 2048 waves in the slab pass (N0 * N threads per cell)
+    // two-pass: aim for about 2048 waves in the slab pass (N0 * N threads per cell),
+    // with the per-term intermediates of a pass under ~16 GiB
     const int64_t threads_per_cell = (int64_t)T.n0 * T.n1;
     int64_t c = (2048 * 64 + threads_per_cell - 1) / threads_per_cell;
+    const double zcell = (double)(T.d == 3 ? T.J : 1) * T.n * csize(precision);
+    c = std::min<int64_t>(c, (int64_t)std::max(1.0, std::floor(16.0 * 1073741824.0 / zcell)));
     g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, count));
     g.G = 1;
   }
@@ -446,8 +450,9 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
     if (precision == EC_BF16X3)
       for (int g = 0; g < n_groups; ++g)
         if (plans[g] && counts[g] > 0 &&
-            !(plans[g]->host.d == 3 && (plans[g]->host.N == 16 || plans[g]->host.N == 32)))
-          return fail(EC_ERR_UNSUPPORTED, "split-BF16 transforms need 3D cells with N = 16 or 32");
+            !(plans[g]->host.d == 3 &&
+              (plans[g]->host.N == 16 || plans[g]->host.N == 32 || plans[g]->host.N == 64)))
+          return fail(EC_ERR_UNSUPPORTED, "split-BF16 transforms need 3D cells with N = 16, 32 or 64");
     if (precision != EC_FP64)
       for (int g = 0; g < n_groups; ++g)
         if (plans[g] && counts[g] > 0 && is_large2d(plans[g]->host))
@@ -693,7 +698,7 @@ int ec_autotune(ec_batch* b, const double* f, double* Q, const char* cache_path,
               cand.push_back(Sched{EC_SCHED_FUSED, (int)std::min<int64_t>(c, count), P});
             }
       }
-      if (T.d == 3) {
+      if (T.d == 3 && T.N <= 32) {
         for (int c : {4, 6, 8, 12, 16, 24})
           for (int G : {1, 2, 4, 8}) {
             if (c > count && c != 4) continue;

@@ -205,6 +205,8 @@ static hipError_t launch_chunk_r(const ChunkArgs& a, hipStream_t st) {
     EFM_CASE(16)
     EFM_CASE(24)
     EFM_CASE(32)
+    case 64:
+      return a.d == 3 ? launch_chunk_t<R, 64, 64>(a, st) : hipErrorInvalidValue;
     default:
       return hipErrorInvalidValue;
   }
@@ -228,6 +230,7 @@ static hipError_t launch_fwd_r(const ChunkArgs& a, hipStream_t st) {
     case 16: return launch_fwd_t<R, 16>(a, st);
     case 24: return launch_fwd_t<R, 24>(a, st);
     case 32: return launch_fwd_t<R, 32>(a, st);
+    case 64: return launch_fwd_t<R, 64>(a, st);
     default: return hipErrorInvalidValue;
   }
 }

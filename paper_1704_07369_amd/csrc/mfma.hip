@@ -5,6 +5,7 @@
 // i.e. a (2N x 2N) real matrix times (2N x pencils).  It runs on
 // v_mfma_f32_32x32x16_bf16 with each operand split as v = hi + lo
 // (hi = bf16(v), lo = bf16(v - hi)) and three products hi*hi + hi*lo + lo*hi
+// (N = 16, 32, 64)
 // accumulated in FP32 (about 16 significant bits per operand).  The forward
 // DFT along x (once per pencil), the y/z passes (k_fwd, k_slab) and the
 // storage stay FP32; the sum over terms stays FP64 (k_slab).
@@ -24,6 +25,15 @@ namespace efm {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 
+// exact sign flip of 8 bf16 values
+__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
+  struct U4 { unsigned u[4]; };
+  U4 w = __builtin_bit_cast(U4, v);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w.u[i] ^= 0x80008000u;
+  return __builtin_bit_cast(bf16x8, w);
+}
+
 // k0 of the m-th spectral value a lane of half h holds (m < N/2)
 template <int N>
 __device__ __forceinline__ int kset(int h, int m) {
@@ -34,12 +44,18 @@ template <int N>
 __global__ __launch_bounds__(64) void k_pencil_bf16(const cx<float>* __restrict__ W,
                                                     const cx<float>* __restrict__ G, int J,
                                                     int ncells, cx<float>* __restrict__ Z) {
-  static_assert(N == 16 || N == 32, "split-BF16 x pass: N = 16 or 32");
+  static_assert(N == 16 || N == 32 || N == 64, "split-BF16 x pass: N = 16, 32 or 64");
   constexpr int P = N * N;
   constexpr int NT = 2 * N / 32;      // output row tiles (Re/Im blocks of 32 rows)
   constexpr int NQ = 2 * N / 16;      // K chunks of 16 rows
   constexpr int NH = N / 2;           // spectral values per lane
+  // N = 64: the 128 x 128 matrix does not fit in registers; its C and S blocks
+  // (hi, lo) live in LDS by (row tile, K chunk, lane) and the tiles of
+  // [[C, -S], [S, C]] are assembled from them
+  constexpr bool ALDS = N == 64;
+  constexpr int AT = ALDS ? NT / 2 : 1, AQ = ALDS ? NQ / 2 : 1;
   __shared__ cx<float> fh[N][32];
+  __shared__ bf16x8 cs_lds[ALDS ? 2 : 1][AT][AQ][2][64];   // [C, S][row tile][K chunk][hi, lo][lane]
   const int l = threadIdx.x, col = l % 32, h = l / 32;
   const int64_t pb = blockIdx.x;                    // block of 32 pencils
   const int cc = (int)(pb / (P / 32));
@@ -48,23 +64,47 @@ __global__ __launch_bounds__(64) void k_pencil_bf16(const cx<float>* __restrict_
   const int ccs = active ? cc : 0;
 
   // A operand: the real 2N x 2N inverse DFT matrix, split hi/lo
-  bf16x8 ahi[NT][NQ], alo[NT][NQ];
+  constexpr int RR = ALDS ? 1 : NT, RQ = ALDS ? 1 : NQ;
+  bf16x8 ahi[RR][RQ], alo[RR][RQ];
+  if constexpr (!ALDS) {
 #pragma unroll
-  for (int R = 0; R < NT; ++R) {
+    for (int R = 0; R < NT; ++R) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
+      for (int q = 0; q < NQ; ++q) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int r = R * 32 + col;                 // output row
-        const int kr = q * 16 + h * 8 + j;          // K row
-        const bool oim = r >= N, iim = kr >= N;
-        const int x = oim ? r - N : r, k0 = iim ? kr - N : kr;
-        double sn, cs;
-        sincospi(2.0 * (double)((x * k0) % N) / (double)N, &sn, &cs);
-        const double v = (!oim && !iim) ? cs : (!oim && iim) ? -sn : (oim && !iim) ? sn : cs;
-        const __bf16 hi = (__bf16)(float)v;
-        ahi[R][q][j] = hi;
-        alo[R][q][j] = (__bf16)((float)v - (float)hi);
+        for (int j = 0; j < 8; ++j) {
+          const int r = R * 32 + col;                 // output row
+          const int kr = q * 16 + h * 8 + j;          // K row
+          const bool oim = r >= N, iim = kr >= N;
+          const int x = oim ? r - N : r, k0 = iim ? kr - N : kr;
+          double sn, cs;
+          sincospi(2.0 * (double)((x * k0) % N) / (double)N, &sn, &cs);
+          const double v = (!oim && !iim) ? cs : (!oim && iim) ? -sn : (oim && !iim) ? sn : cs;
+          const __bf16 hi = (__bf16)(float)v;
+          ahi[R][q][j] = hi;
+          alo[R][q][j] = (__bf16)((float)v - (float)hi);
+        }
+      }
+    }
+  } else {
+    for (int R = 0; R < AT; ++R) {
+      for (int q = 0; q < AQ; ++q) {
+        bf16x8 chi, clo, shi, slo;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int x = R * 32 + col, k0 = q * 16 + h * 8 + j;
+          double sn, cs;
+          sincospi(2.0 * (double)((x * k0) % N) / (double)N, &sn, &cs);
+          const __bf16 ch = (__bf16)(float)cs, sh = (__bf16)(float)sn;
+          chi[j] = ch;
+          clo[j] = (__bf16)((float)cs - (float)ch);
+          shi[j] = sh;
+          slo[j] = (__bf16)((float)sn - (float)sh);
+        }
+        cs_lds[0][R][q][0][l] = chi;
+        cs_lds[0][R][q][1][l] = clo;
+        cs_lds[1][R][q][0][l] = shi;
+        cs_lds[1][R][q][1][l] = slo;
       }
     }
   }
@@ -111,14 +151,38 @@ __global__ __launch_bounds__(64) void k_pencil_bf16(const cx<float>* __restrict_
       }
 #pragma unroll
       for (int R = 0; R < NT; ++R) {
-        acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[R][q], bhi, acc[R], 0, 0, 0);
-        acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[R][q], blo, acc[R], 0, 0, 0);
-        acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[R][q], bhi, acc[R], 0, 0, 0);
+        bf16x8 ah, al;
+        if constexpr (ALDS) {
+          // Re rows x Re cols: C; Re x Im: -S; Im x Re: S; Im x Im: C
+          const bool re_out = R < NT / 2, re_in = q < NQ / 2;
+          const int blk = re_out != re_in ? 1 : 0;
+          ah = cs_lds[blk][R % AT][q % AQ][0][l];
+          al = cs_lds[blk][R % AT][q % AQ][1][l];
+          if (re_out && !re_in) {
+            ah = neg8(ah);
+            al = neg8(al);
+          }
+        } else {
+          ah = ahi[R % RR][q % RQ];
+          al = alo[R % RR][q % RQ];
+        }
+        acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bhi, acc[R], 0, 0, 0);
+        acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, blo, acc[R], 0, 0, 0);
+        acc[R] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bhi, acc[R], 0, 0, 0);
       }
     }
     if (active) {
       cx<float>* Zj = Z + ((int64_t)ccs * J + j) * N * P + p;
-      if constexpr (N == 32) {
+      if constexpr (N == 64) {
+        // tiles 0, 1 rows = Re Z(x), x = 32 R + ..; tiles 2, 3 the matching Im Z(x)
+#pragma unroll
+        for (int R = 0; R < 2; ++R)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int x = 32 * R + 8 * (i / 4) + 4 * h + (i % 4);
+            Zj[(int64_t)x * P] = {acc[R][i], acc[R + 2][i]};
+          }
+      } else if constexpr (N == 32) {
         // tile 0 rows = Re Z(x), tile 1 rows = Im Z(x), same x per (lane, i)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -141,7 +205,10 @@ hipError_t launch_pencil_bf16(const void* W, const void* G, int J, int ncells, v
                               hipStream_t st) {
   if (ncells <= 0) return hipSuccess;
   const int blocks = ncells * N * N / 32;
-  if (N == 32) {
+  if (N == 64) {
+    hipLaunchKernelGGL(k_pencil_bf16<64>, dim3(blocks), dim3(64), 0, st, (const cx<float>*)W,
+                       (const cx<float>*)G, J, ncells, (cx<float>*)Z);
+  } else if (N == 32) {
     hipLaunchKernelGGL(k_pencil_bf16<32>, dim3(blocks), dim3(64), 0, st, (const cx<float>*)W,
                        (const cx<float>*)G, J, ncells, (cx<float>*)Z);
   } else if (N == 16) {
