@@ -272,6 +272,55 @@ def surrogate_leg(E, torch, seconds=40.0, n_traj=500, n_steps=100, n_test=1024, 
     }
 
 
+def precision_sweep_leg(E, torch, n_cells=256, reps=2):
+    """Precision sweep on the non-separable kernel: 3D variable hard spheres
+    (gamma = 0.5), N = 64^3, M = 64 directions x 8 radial nodes (513
+    transforms per evaluation), n_cells two-Gaussian mixtures (means
+    U[-2,2]^3, temperatures U[0.5,1.5], seed 4001 + cell).  FP64, FP32 and
+    split-BF16 evaluations timed; FP32 and split-BF16 errors against the FP64
+    GPU result on every cell (the FP64 path itself is checked against the
+    oracle at 64^3 in the GPU tests; the oracle's tables at this size are out
+    of reach of a bench run)."""
+    import numpy as np
+    import synth
+    Nn, Mm, nr, gam = 64, 64, 8, 0.5
+    t0 = time.perf_counter()
+    plan = E.Plan(Nn, D, L, Mm, kind=E.EC_KERNEL_VHS, R=R, gamma=gam, n_radial=nr)
+    t_plan = time.perf_counter() - t0
+    cells = [synth.sample_mixture(synth.mixture_two_gaussians(4001 + c, D), Nn, L) for c in range(n_cells)]
+    out = {"workload": f"3D VHS gamma={gam}, N=64^3, M={Mm} x {nr} radial = {plan.terms()} products, "
+                       f"{n_cells} two-Gaussian cells", "plan_setup_s": round(t_plan, 2)}
+    Qs, P = {}, {}
+    for prec, name in ((E.EC_FP64, "fp64"), (E.EC_FP32, "fp32"), (E.EC_BF16X3, "bf16x3")):
+        b = E.Batch([plan], [n_cells], prec)
+        f = torch.from_numpy(E.pack(b, cells)).to("cuda:0")
+        Q = torch.zeros_like(f)
+        b.collide(f, Q)                       # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.collide(f, Q)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        ep = torch.zeros(n_cells, dtype=torch.float64, device="cuda:0")
+        b.entropy_prod(f, Q, ep)
+        torch.cuda.synchronize()
+        Qs[name] = torch.stack([Q[int(o):int(o) + Nn ** 3] for o in b.offsets])
+        P[name] = ep.cpu().numpy()
+        out[name] = {"evals_per_s": n_cells / t, "ms_per_eval_batch": t * 1e3,
+                     "schedule": list(b.get_schedule(0))}
+        log(f"bench: sweep {name} {n_cells / t:.4g} evals/s")
+        del b, f, Q
+    q64 = Qs["fp64"]
+    for name in ("fp32", "bf16x3"):
+        d = (Qs[name] - q64).view(n_cells, -1).norm(dim=1) / q64.view(n_cells, -1).norm(dim=1)
+        d = d.cpu().numpy()
+        pe = np.abs(P[name] - P["fp64"]) / np.abs(P["fp64"])
+        out[name].update({"rel_l2_vs_fp64_median": float(np.median(d)), "rel_l2_vs_fp64_max": float(d.max()),
+                          "entropy_prod_rel_err_max": float(pe.max())})
+    return out
+
+
 def cpu_baseline(cells, efm, oplan):
     """The oracle (plain double sum over modes, OpenMP) on one cell of the
     workload; evals/s = 1 / time of one full evaluation."""
@@ -300,6 +349,7 @@ def main():
     ap.add_argument("--term-groups", type=int, default=0)
     ap.add_argument("--skip-relax", action="store_true", help="omit the mixed-N relaxation leg")
     ap.add_argument("--skip-surrogate", action="store_true", help="omit the learned-surrogate leg")
+    ap.add_argument("--skip-sweep", action="store_true", help="omit the 64^3 VHS precision sweep")
     ap.add_argument("--surrogate-seconds", type=float, default=40.0, help="surrogate training budget")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run ec_copy on a buffer of this size (counter calibration)")
@@ -384,6 +434,9 @@ def main():
     if not args.skip_relax:
         log("bench: mixed-N relaxation leg (200 graph-replayed FE steps)")
         out["relaxation"] = relaxation_leg(E, torch)
+    if not args.skip_sweep:
+        log("bench: 64^3 VHS precision sweep")
+        out["precision_sweep"] = precision_sweep_leg(E, torch)
     if not args.skip_surrogate:
         log("bench: learned surrogate (data, training, screened inference)")
         out["surrogate"] = surrogate_leg(E, torch, seconds=args.surrogate_seconds, log_fn=log)

@@ -147,11 +147,11 @@ void default_schedule(BatchGroup& g, int precision) {
     g.G = 1;
   } else {
     // two-pass: aim for about 2048 waves in the slab pass (N0 * N threads per cell),
-    // with the per-term intermediates of a pass under ~16 GiB
+    // with the per-term intermediates of a pass under ~48 GiB (a sixth of HBM)
     const int64_t threads_per_cell = (int64_t)T.n0 * T.n1;
     int64_t c = (2048 * 64 + threads_per_cell - 1) / threads_per_cell;
     const double zcell = (double)(T.d == 3 ? T.J : 1) * T.n * csize(precision);
-    c = std::min<int64_t>(c, (int64_t)std::max(1.0, std::floor(16.0 * 1073741824.0 / zcell)));
+    c = std::min<int64_t>(c, (int64_t)std::max(1.0, std::floor(48.0 * 1073741824.0 / zcell)));
     g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, count));
     g.G = 1;
   }
