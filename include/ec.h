@@ -74,6 +74,10 @@ typedef struct ec_kernel {
                         1.2, eq. approximated_collision); R <= 0 selects the
                         largest R allowed by T >= (3 sqrt 2 + 1) R / 4        */
   int n_radial;      /* radial nodes of a non-separable kernel (<= 0: 8)     */
+  int unfiltered;    /* 0: the entropic method (Jackson filter sigma);
+                        1: sigma = 1, the unfiltered Fourier collocation method
+                        (eq. FCM) -- not positivity preserving; the comparison
+                        of the positivity study (section 4.2, Fig. 2)        */
 } ec_kernel;
 
 /* ---- precision of the transforms --------------------------------------- */

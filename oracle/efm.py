@@ -139,6 +139,19 @@ def sigma_nd(N: int, d: int) -> np.ndarray:
     return out.ravel()
 
 
+def unfiltered_nd(N: int, d: int) -> np.ndarray:
+    """The unfiltered method (sigma = 1) on the same mode set: for even N the
+    modes with a component -N/2 are zeroed (section 4.1: even N reduces to
+    the odd N - 1 case), as the filter itself does."""
+    one = np.ones(N)
+    if N % 2 == 0:
+        one[modes_1d(N) == -(N // 2)] = 0.0
+    out = one
+    for _ in range(d - 1):
+        out = np.multiply.outer(out, one)
+    return out.ravel()
+
+
 # ----------------------------------------------------------------------------
 # Quadrature rules (library primitives: numpy's Gauss-Legendre nodes)
 # ----------------------------------------------------------------------------
@@ -380,7 +393,7 @@ def make_plan(N: int, d: int, L: float, M: int, kind: str | None = None,
         lr = lowrank_3d_vhs(N, L, R, M, g, n_radial)
     else:
         raise NotImplementedError(f"oracle kernel {kind} in {d}D")
-    sig = sigma_nd(N, d) if filtered else np.ones(N ** d)
+    sig = sigma_nd(N, d) if filtered else unfiltered_nd(N, d)
     return Plan(N, d, L, R, M, kind, sig, lr)
 
 

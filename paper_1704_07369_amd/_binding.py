@@ -36,7 +36,8 @@ class EcError(RuntimeError):
 
 
 class ec_kernel(ctypes.Structure):
-    _fields_ = [("kind", _c_int), ("gamma", _c_double), ("R", _c_double), ("n_radial", _c_int)]
+    _fields_ = [("kind", _c_int), ("gamma", _c_double), ("R", _c_double), ("n_radial", _c_int),
+                ("unfiltered", _c_int)]
 
 
 _SIGS = {
@@ -138,8 +139,8 @@ def _stream(s):
     return s.cuda_stream
 
 
-def make_kernel(kind=EC_KERNEL_HARD_SPHERE, gamma=1.0, R=6.0, n_radial=0):
-    return ec_kernel(kind, gamma, R, n_radial)
+def make_kernel(kind=EC_KERNEL_HARD_SPHERE, gamma=1.0, R=6.0, n_radial=0, unfiltered=False):
+    return ec_kernel(kind, gamma, R, n_radial, 1 if unfiltered else 0)
 
 
 # ---- same-name wrappers -----------------------------------------------------

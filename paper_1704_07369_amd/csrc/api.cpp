@@ -374,7 +374,8 @@ int ec_host_tables(int N, int d, double L, const ec_kernel* kernel, int M, int* 
     if (!kernel) return fail(EC_ERR_ARG, "kernel is null");
     HostTables T;
     std::string err;
-    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial, M, T, err);
+    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial,
+                          kernel->unfiltered, M, T, err);
     if (rc) return fail(rc, err);
     if (n_terms) *n_terms = T.terms;
     if (gamma) std::memcpy(gamma, T.gamma.data(), T.gamma.size() * sizeof(double));
@@ -388,7 +389,8 @@ int ec_setup_kernel(int N, int d, double L, const ec_kernel* kernel, int M, ec_p
     *out = nullptr;
     auto* p = new ec_plan();
     std::string err;
-    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial, M, p->host, err);
+    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial,
+                          kernel->unfiltered, M, p->host, err);
     if (rc) { delete p; return fail(rc, err); }
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(EC_ERR_DEVICE, "no HIP device"); }
     const size_t cnt = p->host.gamma.size();
@@ -604,6 +606,7 @@ std::string tune_key(int dev, const HostTables& T, int precision, int64_t count)
     std::snprintf(buf, sizeof buf, "|g%.6g|nr%d", T.gamma_exp, T.n_radial);
     key += buf;
   }
+  if (T.unfiltered) key += "|nofilter";
   return key;
 }
 

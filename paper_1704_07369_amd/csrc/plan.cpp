@@ -196,7 +196,7 @@ static void hemisphere_split(int M, int& mm, int& mp) {
 }
 
 int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
-                 int n_radial, int M, HostTables& T, std::string& err) {
+                 int n_radial, int unfiltered, int M, HostTables& T, std::string& err) {
   if (d != 2 && d != 3) { err = "d must be 2 or 3"; return EC_ERR_ARG; }
   if (N < 4 || M < 1 || !(L > 0.0)) { err = "need N >= 4, M >= 1, L > 0"; return EC_ERR_ARG; }
   if (!supported_size(N, d)) {
@@ -216,6 +216,7 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
 
   T.N = N; T.d = d; T.M = M; T.kind = kind; T.L = L; T.R = R; T.gamma_exp = gamma_exp;
   T.n_radial = nrad;
+  T.unfiltered = unfiltered != 0;
   T.n0 = (d == 3) ? N : 1;
   T.n1 = N;
   T.n2 = N;
@@ -256,7 +257,14 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
   const double kf = PI / L;
   T.gamma.assign((size_t)2 * T.J * T.n, 0.0);
   std::vector<double> sig1(N);
-  for (int i = 0; i < N; ++i) sig1[i] = jackson(N, i < (N + 1) / 2 ? i : i - N);
+  // sigma = 1 gives the unfiltered Fourier collocation method (eq. FCM), the
+  // comparison of the positivity study (section 4.2, Fig. 2); for even N the
+  // modes with a component -N/2 stay zero (even N reduces to odd N - 1,
+  // section 4.1), as in the filtered case
+  for (int i = 0; i < N; ++i) {
+    const int k = i < (N + 1) / 2 ? i : i - N;
+    sig1[i] = unfiltered ? ((N % 2 == 0 && k == -N / 2) ? 0.0 : 1.0) : jackson(N, k);
+  }
   auto mode = [N](int i) { return i < (N + 1) / 2 ? i : i - N; };
 
   // radial factors of the non-separable kernels

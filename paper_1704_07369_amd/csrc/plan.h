@@ -13,6 +13,7 @@ struct HostTables {
   int n0 = 0, n1 = 0, n2 = 0;   // cell dims: (N,N,N) in 3D, (1,N,N) in 2D
   int64_t n = 0;                // points per cell
   int n_radial = 1;             // radial nodes (non-separable kernels), else 1
+  bool unfiltered = false;      // sigma = 1 (Fourier collocation, no entropic filter)
   int terms = 0;                // M' products in the gain (M n_radial)
   int J = 0;                    // transforms after the forward one: M' + 1
   // gamma[(j * n + idx) * 2 + {0,1}], idx = (k0 * n2 + k2) * n1 + k1
@@ -21,7 +22,7 @@ struct HostTables {
 
 // Returns 0 or an EC_ERR_* code with a message in err.
 int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
-                 int n_radial, int M, HostTables& out, std::string& err);
+                 int n_radial, int unfiltered, int M, HostTables& out, std::string& err);
 
 // Modified Jackson filter (section 3.2.2, eq. JacksonFilter2) for the mode
 // value k of an N-point axis.

@@ -76,6 +76,19 @@ def test_library_nonseparable_tables_reproduce_oracle_operator(N, M, gamma, nr):
     assert np.abs(ell - efm.collision_frequency(p, F)).max() < 1e-13 * np.abs(ell).max()
 
 
+@pytest.mark.parametrize("N,d,L,M", [(16, 2, 8.0, 8), (8, 3, 8.0, 8)])
+def test_unfiltered_tables_reproduce_oracle_fcm(N, d, L, M):
+    """sigma = 1 (the Fourier collocation method of the positivity study)."""
+    k = E.make_kernel(E.EC_KERNEL_MAXWELL if d == 2 else E.EC_KERNEL_HARD_SPHERE,
+                      0.0 if d == 2 else 1.0, R, unfiltered=True)
+    G = _as_nat(E.ec_host_tables(N, d, L, k, M), N, d)
+    p = efm.make_plan(N, d, L, M, R=R, filtered=False)
+    F = synth.sample_mixture(synth.mixture_anisotropic(21 + N, d), N, L)
+    q, qp, ell = model_pipeline(G, F)
+    ref = efm.collide_modes(p, F)
+    assert np.linalg.norm(q - ref.Q) < 1e-13 * np.linalg.norm(ref.Qplus)
+
+
 def test_library_table_symmetries_and_zero_band():
     """Multipliers are even in k, vanish wherever sigma does (|k_i| >= N/2),
     and D is the diagonal of the same low-rank kernel (mass conservation:
