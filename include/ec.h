@@ -167,7 +167,8 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
  * 0 for cells_per_pass or term_groups selects the default (chosen from the
  * cache size); the autotuner picks measured values.  A new batch starts with
  * the fused schedule where it exists and the group has at least 32 cells,
- * and with the two-pass schedule otherwise.  Reallocates the workspace (synchronises
+ * with the pipelined schedule (3D, N <= 32) for smaller groups, and with the
+ * two-pass schedule otherwise.  Reallocates the workspace (synchronises
  * the device); call it outside graph capture.
  */
 #define EC_SCHED_PIPELINE 0

@@ -473,8 +473,9 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
       bg.count = counts[g];
       bg.first = cell;
       // the fused schedule runs P workgroups per cell: below a few dozen cells
-      // the two-pass schedule (N^2 pencils and N slabs per cell) fills more CUs
-      bg.mode = counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_TWO_PASS;
+      // the pipelined schedule (term groups spread one cell over many
+      // workgroups) fills more CUs; both fall back to two-pass where absent
+      bg.mode = counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_PIPELINE;
       default_schedule(bg, precision);
       const HostTables& T = plans[g]->host;
       const double hd = std::pow(2.0 * T.L / T.N, T.d);
