@@ -697,9 +697,11 @@ int ec_autotune(ec_batch* b, const double* f, double* Q, const char* cache_path,
       if (T.d == 3 && fused_default_split(T.N, b->precision) > 0) {
         for (int P : {1, 2, 3, 4})
           if (fused_supported(T.N, b->precision, P))
-            for (int c : {256, 2048}) {
-              if (c > count && c != 256) continue;
-              cand.push_back(Sched{EC_SCHED_FUSED, (int)std::min<int64_t>(c, count), P});
+            for (int c : {256, 512, 1024, 2048}) {
+              const Sched sc{EC_SCHED_FUSED, (int)std::min<int64_t>(c, count), P};
+              bool dup = false;
+              for (auto& x : cand) dup |= (x.mode == sc.mode && x.chunk == sc.chunk && x.G == sc.G);
+              if (!dup) cand.push_back(sc);
             }
       }
       if (T.d == 3 && T.N <= 32) {
