@@ -10,8 +10,9 @@
 //   G_s(k', .) = e^{2 pi i k' s/N} sum_{j<P} e^{2 pi i j s/P} Zh(k' + jN/P, .),
 // where Zh = gamma_t Fh is transformed along y and z first.  One workgroup
 // owns one (cell, s): for every term it forms G_s straight from Fh and the
-// term's table (both read from L2: Fh is reused by the cell's P workgroups
-// and by every term, the table by every cell), runs the inverse transforms
+// term's table (the table read from L2, where every cell reuses it; Fh read
+// once per workgroup for the planes kept in registers, from L2 per term for
+// the rest, where the cell's P workgroups share it), runs the inverse transforms
 // along z, y (register lines, LDS transposes) and x (length N/P), and adds
 // Re c Im c into FP64 registers that cover its N^3/P output points.  The loss
 // term goes first, so the accumulator starts at -F l.
@@ -53,6 +54,15 @@ __global__ __launch_bounds__(64) void k_fwdx(cx<R>* __restrict__ W, int ncells) 
   for (int k = 0; k < N; ++k) Wc[(int64_t)k * P2] = v[k];
 }
 
+// Planes k2 < C of this thread's Fh inputs kept in registers across terms
+// (measured on MI355X, 1024 cells: more planes spill or cost occupancy)
+template <int N, int P, int B>
+constexpr int fh_cache() {
+  if (N == 32) return B == 8 || P == 2 ? 8 : 4;
+  if (N == 16 && P == 2 && B == 8) return 8;
+  return 4;
+}
+
 template <int N, int P>
 constexpr int fused_threads() { return N / P * N; }
 
@@ -86,19 +96,45 @@ __device__ __forceinline__ void accum_roots(const cx<R> (&g)[P], const cx<R> (&f
   }
 }
 
+// one plane pair of G_s: the entry at (a, kk, bq) and its mirror
 template <typename R, int N, int P, int S>
+__device__ __forceinline__ void gather_store(const cx<R> (&g)[P], const cx<R> (&fv)[P], int kk,
+                                             int a, int bq, int am, int bm, cx<R> tw,
+                                             cx<R> twc, cx<R>* vol) {
+  constexpr int LD = N + 1;
+  cx<R> SA = {(R)0, (R)0}, SB = {(R)0, (R)0};
+  accum_roots<P, S>(g, fv, SA, SB);
+  vol[(a * N + kk) * LD + bq] = cmul(tw, cx<R>{SA.x - SB.y, SA.y + SB.x});
+  if (kk > 0) vol[(am * N + (N - kk)) * LD + bm] = cmul(twc, cx<R>{SA.x + SB.y, SB.x - SA.y});
+}
+
+template <typename R, int N, int P, int C, int S>
 __device__ __forceinline__ void gather_term(const cx<R>* __restrict__ Gt,
-                                            const cx<R>* __restrict__ Fc, int a, int bq,
+                                            const cx<R>* __restrict__ Fc,
+                                            const cx<R> (&fh)[C > 0 ? C : 1][P], int a, int bq,
                                             int am, int bm, cx<R> tw, cx<R>* vol) {
   constexpr int NP = N / P, LD = N + 1;
-  // planes per group: all of a group's loads are in flight together (8-plane
-  // groups measured slower at 32^3: the gather is bound by L2-to-CU delivery,
-  // about 42 of 64 B/clk, not by latency)
+  // planes per group: a group's loads are in flight together
   constexpr int GP = 4;
-  static_assert((N / 2) % GP == 0, "half-space planes come in whole groups");
+  static_assert((N / 2) % GP == 0 && C % GP == 0, "half-space planes come in whole groups");
   const cx<R> twc = {tw.x, -tw.y};
+  // planes k2 < C: Fh from registers (compile-time indices), table from L2
+#pragma unroll
+  for (int k2 = 0; k2 < C; k2 += GP) {
+    cx<R> gl[GP][P];
+#pragma unroll
+    for (int u = 0; u < GP; ++u) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) gl[u][j] = Gt[((a + NP * j) * N + k2 + u) * N + bq];
+    }
+#pragma unroll
+    for (int u = 0; u < GP; ++u)
+      gather_store<R, N, P, S>(gl[u], fh[k2 + u], k2 + u, a, bq, am, bm, tw, twc, vol);
+    __builtin_amdgcn_sched_barrier(0);  // keep the next group's loads behind this group
+  }
+  // remaining planes: both from L2
 #pragma unroll 1
-  for (int k2 = 0; k2 < N / 2; k2 += GP) {
+  for (int k2 = C; k2 < N / 2; k2 += GP) {
     cx<R> gl[GP][P], fl[GP][P];
 #pragma unroll
     for (int u = 0; u < GP; ++u) {
@@ -110,23 +146,64 @@ __device__ __forceinline__ void gather_term(const cx<R>* __restrict__ Gt,
       }
     }
 #pragma unroll
-    for (int u = 0; u < GP; ++u) {
-      const int kk = k2 + u;
-      cx<R> SA = {(R)0, (R)0}, SB = {(R)0, (R)0};
-      accum_roots<P, S>(gl[u], fl[u], SA, SB);
-      vol[(a * N + kk) * LD + bq] = cmul(tw, cx<R>{SA.x - SB.y, SA.y + SB.x});
-      if (kk > 0) vol[(am * N + (N - kk)) * LD + bm] = cmul(twc, cx<R>{SA.x + SB.y, SB.x - SA.y});
-    }
+    for (int u = 0; u < GP; ++u)
+      gather_store<R, N, P, S>(gl[u], fl[u], k2 + u, a, bq, am, bm, tw, twc, vol);
   }
   vol[(a * N + N / 2) * LD + bq] = {(R)0, (R)0};
 }
 
-template <typename R, int N, int P, int S = 0>
+template <typename R, int N, int P, int C, int S = 0>
 __device__ __forceinline__ void gather_term_s(int s, const cx<R>* __restrict__ Gt,
-                                              const cx<R>* __restrict__ Fc, int a, int bq,
-                                              int am, int bm, cx<R> tw, cx<R>* vol) {
-  if (s == S) gather_term<R, N, P, S>(Gt, Fc, a, bq, am, bm, tw, vol);
-  else if constexpr (S + 1 < P) gather_term_s<R, N, P, S + 1>(s, Gt, Fc, a, bq, am, bm, tw, vol);
+                                              const cx<R>* __restrict__ Fc,
+                                              const cx<R> (&fh)[C > 0 ? C : 1][P], int a,
+                                              int bq, int am, int bm, cx<R> tw, cx<R>* vol) {
+  if (s == S) gather_term<R, N, P, C, S>(Gt, Fc, fh, a, bq, am, bm, tw, vol);
+  else if constexpr (S + 1 < P)
+    gather_term_s<R, N, P, C, S + 1>(s, Gt, Fc, fh, a, bq, am, bm, tw, vol);
+}
+
+// One term: gather G_s into vol, inverse passes along z and y (register
+// lines, LDS transposes), then along x for each of the thread's P lines.
+// LOSS (the first term, table D): acc = -F l; otherwise acc += Re c Im c.
+template <typename R, int N, int P, int C, bool LOSS>
+__device__ __forceinline__ void run_term(int s, const cx<R>* __restrict__ Gt,
+                                         const cx<R>* __restrict__ Fc,
+                                         const cx<R> (&fh)[C > 0 ? C : 1][P],
+                                         int a, int bq, int am, int bm, cx<R> tw, cx<R>* vol,
+                                         const double* __restrict__ fc, double (&acc)[P][N / P]) {
+  constexpr int NP = N / P, T = NP * N, LD = N + 1;
+  const int th = threadIdx.x;
+  __syncthreads();                      // the previous term's x pass is done with vol
+  gather_term_s<R, N, P, C>(s, Gt, Fc, fh, a, bq, am, bm, tw, vol);
+  __syncthreads();                      // mirrored entries land in other threads' columns
+  cx<R> v[N];
+#pragma unroll
+  for (int k2 = 0; k2 < N; ++k2) v[k2] = vol[(a * N + k2) * LD + bq];
+  fft_line<N, +1>(v);                   // along z: (k', k1 = bq, z), same column
+#pragma unroll
+  for (int z = 0; z < N; ++z) vol[(a * N + z) * LD + bq] = v[z];
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) v[k1] = vol[(a * N + bq) * LD + k1];
+  fft_line<N, +1>(v);                   // along y: (k', y, z = bq)
+  __syncthreads();
+#pragma unroll
+  for (int y = 0; y < N; ++y) vol[(a * N + y) * LD + bq] = v[y];
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int line = th + T * p;        // (y, z) of this x line
+    const int y = line / N, z = line % N;
+    cx<R> u[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) u[q] = vol[(q * N + y) * LD + z];
+    fft_line<NP, +1>(u);                // x = P q + s
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      if constexpr (LOSS) acc[p][q] = -fc[((P * q + s) * N + y) * N + z] * (double)u[q].x;
+      else acc[p][q] += (double)u[q].x * (double)u[q].y;
+    }
+  }
 }
 
 template <typename R, int N, int P>
@@ -152,45 +229,22 @@ __global__ __launch_bounds__(N / P * N) void k_fused(
   const cx<R>* Fc = Fh + (int64_t)cc * n;
   const int64_t base = off[cell0 + cc];
   const double* fc = f + base;
-  double acc[P][NP];
-  cx<R> v[N];
-  for (int it = 0; it < J; ++it) {
-    const int term = it == 0 ? J - 1 : it - 1;      // loss first
-    const cx<R>* Gt = G + (int64_t)term * n;
-    __syncthreads();                    // the previous term's x pass is done with vol
-    gather_term_s<R, N, P>(s, Gt, Fc, a, bq, am, bm, tw, vol);
-    __syncthreads();                    // mirrored entries land in other threads' columns
+  // this thread's half-space inputs of Fh (the first C planes), the same for
+  // every term: kept in registers, so a term's gather reads its table and
+  // only the remaining planes of Fh
+  constexpr int C = fh_cache<N, P, (int)sizeof(R)>();
+  cx<R> fh[C > 0 ? C : 1][P];
 #pragma unroll
-    for (int k2 = 0; k2 < N; ++k2) v[k2] = vol[(a * N + k2) * LD + bq];
-    fft_line<N, +1>(v);                 // along z: (k', k1 = bq, z), same column
+  for (int k2 = 0; k2 < C; ++k2) {
 #pragma unroll
-    for (int z = 0; z < N; ++z) vol[(a * N + z) * LD + bq] = v[z];
-    __syncthreads();
-#pragma unroll
-    for (int k1 = 0; k1 < N; ++k1) v[k1] = vol[(a * N + bq) * LD + k1];
-    fft_line<N, +1>(v);                 // along y: (k', y, z = bq)
-    __syncthreads();
-#pragma unroll
-    for (int y = 0; y < N; ++y) vol[(a * N + y) * LD + bq] = v[y];
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int line = th + T * p;      // (y, z) of this x line
-      const int y = line / N, z = line % N;
-      cx<R> u[NP];
-#pragma unroll
-      for (int q = 0; q < NP; ++q) u[q] = vol[(q * N + y) * LD + z];
-      fft_line<NP, +1>(u);              // x = P q + s
-      if (it == 0) {
-#pragma unroll
-        for (int q = 0; q < NP; ++q)
-          acc[p][q] = -fc[((P * q + s) * N + y) * N + z] * (double)u[q].x;
-      } else {
-#pragma unroll
-        for (int q = 0; q < NP; ++q) acc[p][q] += (double)u[q].x * (double)u[q].y;
-      }
-    }
+    for (int j = 0; j < P; ++j) fh[k2][j] = Fc[((a + NP * j) * N + k2) * N + bq];
   }
+  double acc[P][NP];
+  // the loss term (last table entry) first, outside the loop, so that the
+  // addresses of F are not kept live across the gain terms
+  run_term<R, N, P, C, true>(s, G + (int64_t)(J - 1) * n, Fc, fh, a, bq, am, bm, tw, vol, fc, acc);
+  for (int term = 0; term < J - 1; ++term)
+    run_term<R, N, P, C, false>(s, G + (int64_t)term * n, Fc, fh, a, bq, am, bm, tw, vol, fc, acc);
   double* qc = Q + base;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
