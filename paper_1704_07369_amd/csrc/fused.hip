@@ -19,6 +19,8 @@
 //
 // Block -> (cell, s): blocks b, b+8, ... land on one XCD, so the P workgroups
 // of a cell share that XCD's L2 (cell = (b / 8P) * 8 + b % 8, s = (b / 8) % P).
+// N = 16, 24 run k_fused (volume staged in LDS); N = 32 runs k_fused_col
+// (volume in registers, exchanges through LDS and lane permutes).
 #include "fused.h"
 
 #include "fft.h"
@@ -58,9 +60,7 @@ __global__ __launch_bounds__(64) void k_fwdx(cx<R>* __restrict__ W, int ncells) 
 // (measured on MI355X, 1024 cells: more planes spill or cost occupancy)
 template <int N, int P, int B>
 constexpr int fh_cache() {
-  if (N == 32) return B == 8 || P == 2 ? 8 : 4;
-  if (N == 16 && P == 2 && B == 8) return 8;
-  return 4;
+  return N == 16 && P == 2 && B == 8 ? 8 : 4;
 }
 
 template <int N, int P>
@@ -258,7 +258,221 @@ __global__ __launch_bounds__(N / P * N) void k_fused(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Column form for N = 32 (same mathematics as k_fused above).
+//
+// k_fused stages the whole (N/P) x N x N term volume in LDS, so at N = 32 one
+// workgroup fills a CU (P = 4 in FP64) and the gather of a term cannot
+// overlap the transform passes of another.  Here the volume lives in
+// registers (one z column, then one y line per thread) and only exchanges go
+// through memory:
+//   - the mirrored half-space entries of the gather go to their owner by a
+//     lane permute: the owner of plane am = -a mod N/P is placed in the same
+//     wave (wave w holds planes w and N/P - w; wave 0 holds 0 and N/P/2), and
+//     the column bm = -bq mod N in the same half-wave;
+//   - the z -> y transpose stays inside a half-wave (one plane): real parts,
+//     then imaginary parts, through that plane's LDS rows;
+//   - the y -> x exchange crosses waves: real parts, then imaginary parts,
+//     through an (N/P) x N x (N+1) LDS array of reals.
+// Splitting the exchanges into real and imaginary halves keeps one line of
+// registers live (at most 256 registers per thread, two waves per SIMD).  P = 2
+// (512 threads, 132 KiB in FP64) halves the gathered bytes per cell against
+// P = 4 (two workgroups of 66 KiB per CU, whose gathers and transform passes
+// interleave).
+// ---------------------------------------------------------------------------
+
+// v as held by lane src4 / 4 of this wave (a lane permute; no LDS storage)
+__device__ __forceinline__ double lane_read(double v, int src4) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src4, (int)(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_ds_bpermute(src4, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_read(float v, int src4) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(v)));
+}
+template <typename R>
+__device__ __forceinline__ cx<R> lane_read(cx<R> v, int src4) {
+  return {lane_read(v.x, src4), lane_read(v.y, src4)};
+}
+
+// 0, opaque to the optimizer: offsets a loop-invariant pointer so that
+// addresses formed from it are not hoisted (the pointer keeps its address space)
+__device__ __forceinline__ int opaque_zero() {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+}
+
+// LDS writes of this wave visible to its other lanes (and earlier reads done)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Gather of one term into the thread's z column v[k2] (plane a, column bq;
+// col = a N^2 + bq indexes its first input): entries k2 < N/2 from its own
+// loads, k2 > N/2 from the mirror partner, whose lane is partner4 / 4.
+template <typename R, int N, int P, int S>
+__device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
+                                           const cx<R>* __restrict__ Fc, int col,
+                                           int partner4, cx<R> tw, cx<R> (&v)[N]) {
+  constexpr int NP = N / P;
+  constexpr int GP = 2;                 // planes per group of loads (4 spill in FP64)
+  const cx<R> twc = {tw.x, -tw.y};
+#pragma unroll
+  for (int k2 = 0; k2 < N / 2; k2 += GP) {
+    cx<R> gl[GP][P], fl[GP][P];
+#pragma unroll
+    for (int u = 0; u < GP; ++u) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int idx = col + (NP * j * N + k2 + u) * N;
+        gl[u][j] = Gt[idx];
+        fl[u][j] = Fc[idx];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GP; ++u) {
+      const int kk = k2 + u;
+      cx<R> SA = {(R)0, (R)0}, SB = {(R)0, (R)0};
+      accum_roots<P, S>(gl[u], fl[u], SA, SB);
+      v[kk] = cmul(tw, cx<R>{SA.x - SB.y, SA.y + SB.x});
+      if (kk > 0) v[N - kk] = lane_read(cmul(twc, cx<R>{SA.x + SB.y, SB.x - SA.y}), partner4);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the next group's loads behind this group
+  }
+  v[N / 2] = {(R)0, (R)0};
+}
+
+template <typename R, int N, int P, int S = 0>
+__device__ __forceinline__ void gather_col_s(int s, const cx<R>* __restrict__ Gt,
+                                             const cx<R>* __restrict__ Fc, int col,
+                                             int partner4, cx<R> tw, cx<R> (&v)[N]) {
+  if (s == S) gather_col<R, N, P, S>(Gt, Fc, col, partner4, tw, v);
+  else if constexpr (S + 1 < P) gather_col_s<R, N, P, S + 1>(s, Gt, Fc, col, partner4, tw, v);
+}
+
+template <typename R, int N, int P, bool LOSS>
+__device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt,
+                                             const cx<R>* __restrict__ Fc, int a, int bq,
+                                             int partner4, cx<R> tw, R* buf,
+                                             const double* __restrict__ fc,
+                                             double (&acc)[P][N / P]) {
+  constexpr int NP = N / P, T = NP * N, LD = N + 1;
+  const int th = threadIdx.x;
+  // offset by an opaque zero, the per-element addresses are formed here
+  // instead of being hoisted out of the term loop (64 of them would stay live
+  // across every term)
+  const int z0 = opaque_zero();
+  const double* fp = fc + z0;
+  cx<R> v[N];
+  gather_col_s<R, N, P>(s, Gt, Fc, a * N * N + bq + z0, partner4, tw, v);
+  fft_line<N, +1>(v);                   // along z: (k', k1 = bq, z)
+  R* pl = buf + a * N * LD;             // this half-wave's plane
+  __syncthreads();                      // every wave is done reading the previous term
+  // z -> y transpose inside the half-wave, real parts then imaginary parts
+#pragma unroll
+  for (int z = 0; z < N; ++z) pl[z * LD + bq] = v[z].x;
+  wave_sync();
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) v[k1].x = pl[bq * LD + k1];   // now the y line's
+  wave_sync();
+  // the imaginary parts are still those of the z column
+#pragma unroll
+  for (int z = 0; z < N; ++z) pl[z * LD + bq] = v[z].y;
+  wave_sync();
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) v[k1].y = pl[bq * LD + k1];
+  fft_line<N, +1>(v);                   // along y: (k', y, z = bq)
+  wave_sync();
+  // y -> x exchange across waves
+#pragma unroll
+  for (int y = 0; y < N; ++y) pl[y * LD + bq] = v[y].x;
+  __syncthreads();
+  cx<R> u[P][NP];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int line = th + T * p;        // (y, z) of this x line
+    const int y = line / N, z = line % N;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) u[p][q].x = buf[(q * N + y) * LD + z];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int y = 0; y < N; ++y) pl[y * LD + bq] = v[y].y;
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int line = th + T * p;
+    const int y = line / N, z = line % N;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) u[p][q].y = buf[(q * N + y) * LD + z];
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int line = th + T * p;
+    const int y = line / N, z = line % N;
+    fft_line<NP, +1>(u[p]);             // x = P q + s
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      if constexpr (LOSS) acc[p][q] = -fp[((P * q + s) * N + y) * N + z] * (double)u[p][q].x;
+      else acc[p][q] += (double)u[p][q].x * (double)u[p][q].y;
+    }
+  }
+}
+
 template <typename R, int N, int P>
+__global__ __launch_bounds__(N / P * N) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_fused_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int J,
+                 const double* f, const int64_t* __restrict__ off, int64_t cell0, int ncells,
+                 double* Q, double dt) {
+  static_assert(N == 32, "one half-wave per (plane, column) line");
+  constexpr int NP = N / P, T = NP * N, LD = N + 1, n = N * N * N;
+  static_assert(T % 64 == 0 && T / 64 == NP / 2, "two planes per wave");
+  __shared__ R buf[NP * N * LD];
+  const int blk = blockIdx.x;
+  const int s = (blk / 8) % P;
+  const int cc = (blk / (8 * P)) * 8 + blk % 8;
+  if (cc >= ncells) return;             // whole workgroup
+  const int th = threadIdx.x;
+  const int w = th / 64, h = (th / 32) % 2, bq = th % 32;
+  const int a = h == 0 ? w : (w == 0 ? NP / 2 : NP - w);
+  const int bm = (N - bq) % N;
+  // mirror partner (plane -a mod NP, column bm): other half-wave, except in
+  // wave 0 whose planes 0 and NP/2 are their own mirrors
+  const int partner4 = 4 * ((w == 0 ? h : 1 - h) * 32 + bm);
+  const cx<R> tw = unit_root<N, R>((a * s) % N);
+  const cx<R>* Fc = Fh + (int64_t)cc * n;
+  const int64_t base = off[cell0 + cc];
+  const double* fc = f + base;
+  double acc[P][NP];
+  run_term_col<R, N, P, true>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4, tw, buf, fc,
+                              acc);
+  for (int term = 0; term < J - 1; ++term)
+    run_term_col<R, N, P, false>(s, G + (int64_t)term * n, Fc, a, bq, partner4, tw, buf, fc,
+                                 acc);
+  // fresh copies again, so that the output addresses are not shared with
+  // (and kept live from) the loss term's reads of F
+  const int z0 = opaque_zero();
+  double* qc = Q + base + z0;
+  const double* fe = fc + z0;
+  const int se = s + z0;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int line = th + T * p;
+    const int y = line / N, z = line % N;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int idx = ((P * q + se) * N + y) * N + z;
+      qc[idx] = dt == 0.0 ? acc[p][q] : fe[idx] + dt * acc[p][q];
+    }
+  }
+}
+
+// k_fwd, k_fwdx, then the fused kernel (COL: the column form)
+template <typename R, int N, int P, bool COL>
 static hipError_t launch_fused_t(const ChunkArgs& a, hipStream_t st) {
   cx<R>* W = (cx<R>*)a.W;
   hipError_t e = launch_fwd(a, st);
@@ -268,10 +482,13 @@ static hipError_t launch_fused_t(const ChunkArgs& a, hipStream_t st) {
   hipLaunchKernelGGL((k_fwdx<R, N>), dim3((unsigned)((pencils + 63) / 64)), dim3(64), 0, st, W,
                      a.ncells);
   if (a.ev) (void)hipEventRecord(a.ev[2], st);
-  const int64_t groups8 = (a.ncells + 7) / 8;
-  hipLaunchKernelGGL((k_fused<R, N, P>), dim3((unsigned)(groups8 * 8 * P)),
-                     dim3(fused_threads<N, P>()), 0, st, (const cx<R>*)W,
-                     (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
+  const dim3 grid((unsigned)((a.ncells + 7) / 8 * 8 * P)), block(fused_threads<N, P>());
+  if constexpr (COL)
+    hipLaunchKernelGGL((k_fused_col<R, N, P>), grid, block, 0, st, (const cx<R>*)W,
+                       (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
+  else
+    hipLaunchKernelGGL((k_fused<R, N, P>), grid, block, 0, st, (const cx<R>*)W,
+                       (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
   if (a.ev) (void)hipEventRecord(a.ev[3], st);
   return hipGetLastError();
 }
@@ -280,8 +497,8 @@ int fused_default_split(int N, int precision) {
   if (precision == 2) return 0;         // split-BF16 keeps its MFMA x pass
   switch (N) {
     case 16: return 1;
-    case 24: return 2;
-    case 32: return precision == 0 ? 4 : 2;
+    case 24: return 3;
+    case 32: return 2;
     default: return 0;
   }
 }
@@ -291,7 +508,7 @@ bool fused_supported(int N, int precision, int split) {
   switch (N) {
     case 16: return split == 1 || split == 2;
     case 24: return split == 2 || split == 3;
-    case 32: return split == 2 ? precision != 0 : split == 4;
+    case 32: return split == 2 || split == 4;
     default: return false;
   }
 }
@@ -300,17 +517,19 @@ hipError_t launch_fused(const ChunkArgs& a, int split, hipStream_t st) {
   if (a.ncells <= 0) return hipSuccess;
   if (a.d != 3 || !fused_supported(a.N, a.precision, split)) return hipErrorInvalidValue;
   if (a.precision == 0) {
-    if (a.N == 16) return split == 1 ? launch_fused_t<double, 16, 1>(a, st)
-                                     : launch_fused_t<double, 16, 2>(a, st);
-    if (a.N == 24) return split == 2 ? launch_fused_t<double, 24, 2>(a, st)
-                                     : launch_fused_t<double, 24, 3>(a, st);
-    return launch_fused_t<double, 32, 4>(a, st);
+    if (a.N == 16) return split == 1 ? launch_fused_t<double, 16, 1, false>(a, st)
+                                     : launch_fused_t<double, 16, 2, false>(a, st);
+    if (a.N == 24) return split == 2 ? launch_fused_t<double, 24, 2, false>(a, st)
+                                     : launch_fused_t<double, 24, 3, false>(a, st);
+    return split == 2 ? launch_fused_t<double, 32, 2, true>(a, st)
+                      : launch_fused_t<double, 32, 4, true>(a, st);
   }
-  if (a.N == 16) return split == 1 ? launch_fused_t<float, 16, 1>(a, st)
-                                   : launch_fused_t<float, 16, 2>(a, st);
-  if (a.N == 24) return split == 2 ? launch_fused_t<float, 24, 2>(a, st)
-                                   : launch_fused_t<float, 24, 3>(a, st);
-  return split == 2 ? launch_fused_t<float, 32, 2>(a, st) : launch_fused_t<float, 32, 4>(a, st);
+  if (a.N == 16) return split == 1 ? launch_fused_t<float, 16, 1, false>(a, st)
+                                   : launch_fused_t<float, 16, 2, false>(a, st);
+  if (a.N == 24) return split == 2 ? launch_fused_t<float, 24, 2, false>(a, st)
+                                   : launch_fused_t<float, 24, 3, false>(a, st);
+  return split == 2 ? launch_fused_t<float, 32, 2, true>(a, st)
+                    : launch_fused_t<float, 32, 4, true>(a, st);
 }
 
 }  // namespace efm

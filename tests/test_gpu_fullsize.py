@@ -1,8 +1,9 @@
 """Parity at the headline size in the launch configuration the bench times:
 1024 cells of 32^3 (hard spheres, M = 32, L = 8, R = 6, the bench's
 anisotropic mixtures, seed 2001 + cell) with the schedule read from the
-measured tune cache (fused passes of 256 / 512 cells), checked against the
-oracle's point form on sampled points of cells at the pass boundaries.
+measured tune cache (fused passes of 1024 cells in FP64 and 512 in FP32, x
+split 2), checked against the oracle's point form on sampled points of cells
+at pass and workgroup-round boundaries.
 Degenerate cells inside a fused batch: F = 0 gives Q = 0 exactly, a spike
 stays finite, a Maxwellian matches the oracle.
 
