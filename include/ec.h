@@ -67,17 +67,38 @@ extern "C" {
  * hard-sphere kernel as n_radial grows.
  */
 
+/*
+ * Truncation of the collision integral (the fast algorithm integrates the
+ * Carleman form over a bounded set of (y, z)):
+ *   EC_TRUNC_BOX:  |y| <= R and |z| <= R, the truncation of section 1.2 with
+ *                  the box bound T >= (3 sqrt 2 + 1) R / 4;
+ *   EC_TRUNC_BALL: |g| <= R in the classical form (eq. classical_hatB and the
+ *                  remark after it; box bound T >= (3 + sqrt 2) R / 4).  With
+ *                  y = (g + |g| w)/2, z = (g - |g| w)/2 (orthogonal,
+ *                  |y|^2 + |z|^2 = |g|^2) this is the ball |y|^2 + |z|^2 <= R^2
+ *                  of the same integrand: phi_{t,j} integrates over the disk of
+ *                  radius sqrt(R^2 - rho_j^2), with rho_j = R sin(theta_j),
+ *                  Gauss-Legendre in theta on [0, pi/2].  Non-separable (radial)
+ *                  kernels only: 3D EC_KERNEL_MAXWELL and EC_KERNEL_VHS
+ *                  (gamma = 1 gives hard spheres in this truncation).  3D
+ *                  Maxwell with this truncation is the kernel of the paper's 3D
+ *                  BKW experiment (section 4.2, Example 4, Table 3).
+ */
+#define EC_TRUNC_BOX  0
+#define EC_TRUNC_BALL 1
+
 typedef struct ec_kernel {
   int kind;          /* EC_KERNEL_*                                          */
   double gamma;      /* used by EC_KERNEL_VHS only                           */
   double R;          /* truncation radius of the Carleman integrals (section
                         1.2, eq. approximated_collision); R <= 0 selects the
-                        largest R allowed by T >= (3 sqrt 2 + 1) R / 4        */
+                        largest R allowed by the truncation's box bound       */
   int n_radial;      /* radial nodes of a non-separable kernel (<= 0: 8)     */
   int unfiltered;    /* 0: the entropic method (Jackson filter sigma);
                         1: sigma = 1, the unfiltered Fourier collocation method
                         (eq. FCM) -- not positivity preserving; the comparison
                         of the positivity study (section 4.2, Fig. 2)        */
+  int truncation;    /* EC_TRUNC_BOX (0) or EC_TRUNC_BALL (1)                 */
 } ec_kernel;
 
 /* ---- precision of the transforms --------------------------------------- */

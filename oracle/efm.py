@@ -62,6 +62,12 @@ def default_box(R: float) -> float:
     return (3.0 * math.sqrt(2.0) + 1.0) * R / 4.0
 
 
+def classical_box(R: float) -> float:
+    """Smallest half-width with T >= (3 + sqrt 2) R / 4, the bound of the
+    remark on the classical form (section 1.2, eq. classical_hatB)."""
+    return (3.0 + math.sqrt(2.0)) * R / 4.0
+
+
 # ----------------------------------------------------------------------------
 # Grid, modes, DFT
 # ----------------------------------------------------------------------------
@@ -319,24 +325,40 @@ def hankel_disk(q: np.ndarray, rho: float, a: float, R: float) -> np.ndarray:
     return out
 
 
-def lowrank_3d_vhs(N: int, L: float, R: float, M: int, gamma: float, n_radial: int) -> LowRank:
+def lowrank_3d_vhs(N: int, L: float, R: float, M: int, gamma: float, n_radial: int,
+                   truncation: str = "box") -> LowRank:
     """Variable hard spheres B = C_3 |g|^gamma in 3D: Carleman weight
     Bt(y, z) = 2^2 C_3 (|y|^2 + |z|^2)^a with a = (gamma - 1)/2 (section 1),
     which does not factor in (|y|, |z|).  The polar form of the 3D kernel
     (as for hard spheres) keeps the factor inside both radial integrals;
-    discretising the radius of y by Gauss-Legendre (rho_j, omega_j) on [0, R]
-    (the integrand is even in rho) separates them (the form
-    alpha_{l+m} beta_l gamma_m of section 4.1, here with M' = M n_radial
-    terms):
+    discretising the radius of y by Gauss-Legendre (rho_j, omega_j) separates
+    them (the form alpha_{l+m} beta_l gamma_m of section 4.1, here with
+    M' = M n_radial terms):
         psi_{t,j}(l) = 2 omega_j rho_j cos(pi rho_j l.e_t / T),
-        phi_{t,j}(m) = 2 int_{disk perp e_t} (rho_j^2 + |x|^2)^a cos(pi m.x / T) dx,
+        phi_{t,j}(m) = 2 int_{disk perp e_t, |x| <= r_j} (rho_j^2 + |x|^2)^a cos(pi m.x / T) dx,
     with the hemisphere rule over e_t and the constant (Bt/2) w_t as for hard
-    spheres.  gamma = 1 reduces to the hard-sphere kernel as n_radial grows."""
+    spheres.  gamma = 1 reduces to the hard-sphere kernel as n_radial grows.
+
+    truncation "box": |y| <= R and |z| <= R (the Carleman truncation of
+    section 1.2): rho_j Gauss-Legendre on [0, R], r_j = R.
+    truncation "ball": |y|^2 + |z|^2 = |g|^2 <= R^2, the truncation of the
+    classical form (eq. classical_hatB: y = (g + |g| w)/2, z = (g - |g| w)/2
+    are orthogonal with |y|^2 + |z|^2 = |g|^2): r_j = sqrt(R^2 - rho_j^2),
+    with rho = R sin(theta) and Gauss-Legendre in theta on [0, pi/2] (the
+    substitution removes the square-root endpoint of r_j)."""
     kx, ky, kz = mode_grid(N, 3)
     dirs, w = directions_3d(M)
     bt = 4.0 * C_D[3]
     a = 0.5 * (gamma - 1.0)
-    rho, om = gauss_legendre(n_radial, 0.0, R)
+    if truncation == "box":
+        rho, om = gauss_legendre(n_radial, 0.0, R)
+        rdisk = np.full(n_radial, R)
+    elif truncation == "ball":
+        th, wt = gauss_legendre(n_radial, 0.0, 0.5 * math.pi)
+        rho, om = R * np.sin(th), R * np.cos(th) * wt
+        rdisk = R * np.cos(th)
+    else:
+        raise ValueError(f"truncation {truncation}")
     T = len(w)
     U = np.empty((T * n_radial, kx.size)); V = np.empty((T * n_radial, kx.size))
     c = np.empty(T * n_radial)
@@ -347,9 +369,47 @@ def lowrank_3d_vhs(N: int, L: float, R: float, M: int, gamma: float, n_radial: i
         for j in range(n_radial):
             i = t * n_radial + j
             U[i] = 2.0 * om[j] * rho[j] * np.cos(rho[j] * s)
-            V[i] = hankel_disk(qperp, rho[j], a, R)
+            V[i] = hankel_disk(qperp, rho[j], a, rdisk[j])
             c[i] = 0.5 * bt * w[t]
     return LowRank(c, U, V)
+
+
+def ball_radial_integral(p: np.ndarray, q: np.ndarray, R: float) -> np.ndarray:
+    """int_0^R rho^2 sinc(p rho) sinc(q rho) d rho (sinc x = sin x / x) for
+    p, q >= 0, from the antiderivative of sin(p rho) sin(q rho) / (p q):
+    R [sinc((p - q) R) - sinc((p + q) R)] / (2 p q); the limits p = 0 or
+    q = 0 are int_0^R rho sin(x rho) / x d rho = (sin xR - xR cos xR) / x^3."""
+    p, q = np.broadcast_arrays(np.asarray(p, float), np.asarray(q, float))
+    out = np.empty(p.shape)
+    sinc = lambda x: np.sinc(x / math.pi)
+    both = (p > 0) & (q > 0)
+    pp, qq = p[both], q[both]
+    out[both] = R * (sinc((pp - qq) * R) - sinc((pp + qq) * R)) / (2.0 * pp * qq)
+    for one, x in (((p > 0) & (q == 0), p), ((p == 0) & (q > 0), q)):
+        xx = x[one]
+        out[one] = (np.sin(xx * R) - xx * R * np.cos(xx * R)) / xx ** 3
+    out[(p == 0) & (q == 0)] = R ** 3 / 3.0
+    return out
+
+
+def classical_kernel_3d(N: int, L: float, R: float) -> np.ndarray:
+    """Dense kernel modes of the classical form (eq. classical_hatB) for 3D
+    Maxwell molecules, B = C_3: the sphere integral of E over w is
+    4 pi sinc(a |g| |l - m|) and then the ball integral of E_{l+m}(g/2)
+    gives
+        B(l, m) = C_3 (4 pi)^2 int_0^R rho^2 sinc(a rho |l+m|) sinc(a rho |l-m|) d rho,
+    a = pi / (2 T).  Exact (no direction or radial quadrature); n x n in the
+    mode order of mode_grid, for small grids."""
+    k = np.array(mode_grid(N, 3), dtype=float).T
+    n = k.shape[0]
+    a = math.pi / (2.0 * L)
+    B = np.empty((n, n))
+    for i0 in range(0, n, 256):
+        l = k[i0:i0 + 256, None, :]
+        sp = np.sqrt(((l + k[None]) ** 2).sum(axis=2))
+        sm = np.sqrt(((l - k[None]) ** 2).sum(axis=2))
+        B[i0:i0 + 256] = C_D[3] * (4.0 * math.pi) ** 2 * ball_radial_integral(a * sp, a * sm, R)
+    return B
 
 
 # ----------------------------------------------------------------------------
@@ -378,10 +438,11 @@ class Plan:
 
 def make_plan(N: int, d: int, L: float, M: int, kind: str | None = None,
               R: float = 6.0, filtered: bool = True, gamma: float | None = None,
-              n_radial: int = 8) -> Plan:
+              n_radial: int = 8, truncation: str = "box") -> Plan:
     """kind None: 2D Maxwell / 3D hard spheres.  In 3D, KIND_MAXWELL is the
     variable-hard-sphere kernel with gamma = 0 and KIND_VHS takes gamma; both
-    use n_radial radial nodes (M' = M n_radial terms)."""
+    use n_radial radial nodes (M' = M n_radial terms) and either truncation
+    (lowrank_3d_vhs)."""
     if kind is None:
         kind = KIND_MAXWELL if d == 2 else KIND_HARD_SPHERE
     if d == 2 and kind == KIND_MAXWELL:
@@ -390,9 +451,11 @@ def make_plan(N: int, d: int, L: float, M: int, kind: str | None = None,
         lr = lowrank_3d_hard_sphere(N, L, R, M)
     elif d == 3 and kind in (KIND_MAXWELL, KIND_VHS):
         g = 0.0 if kind == KIND_MAXWELL else float(gamma)
-        lr = lowrank_3d_vhs(N, L, R, M, g, n_radial)
+        lr = lowrank_3d_vhs(N, L, R, M, g, n_radial, truncation)
     else:
         raise NotImplementedError(f"oracle kernel {kind} in {d}D")
+    if truncation != "box" and not (d == 3 and kind in (KIND_MAXWELL, KIND_VHS)):
+        raise NotImplementedError("the ball truncation needs the radial (non-separable) path")
     sig = sigma_nd(N, d) if filtered else unfiltered_nd(N, d)
     return Plan(N, d, L, R, M, kind, sig, lr)
 
@@ -446,6 +509,29 @@ def collide_modes(plan: Plan, F: np.ndarray) -> Collision:
     q = qp - qm
     imag = float(max(np.abs(qp.imag).max(), np.abs(qm.imag).max()))
     return Collision(q.real, qp.real, qm.real, imag, G - Lh)
+
+
+def collide_dense(B: np.ndarray, sigma: np.ndarray, F: np.ndarray, L: float) -> np.ndarray:
+    """Q^sigma on the grid (section 3.2.2, eq. EFMk) from a dense kernel-mode
+    matrix B (mode order of mode_grid): Qh_k = sum_{l + m = k mod N}
+    (sigma_l sigma_m B(l,m) - sigma_m^2 B(m,m)) Fh_l Fh_m, summed with numpy
+    over l for every output mode k."""
+    N, d = F.shape[0], F.ndim
+    n = N ** d
+    Bs = B * sigma[:, None] * sigma[None, :]
+    diag = np.diag(Bs).copy()
+    pos = np.array(mode_grid(N, d)).T % N
+    Fh = dft(F, L).ravel()
+    Qh = np.empty(n, complex)
+    ar = np.arange(n)
+    for k in range(n):
+        mp = (pos[k] - pos) % N
+        m = mp[:, 0]
+        for i in range(1, d):
+            m = m * N + mp[:, i]
+        pr = Fh * Fh[m]
+        Qh[k] = np.dot(Bs[ar, m] - diag[m], pr)
+    return idft(Qh.reshape((N,) * d), L).real
 
 
 def collide_modes_some(plan: Plan, F: np.ndarray, ks: np.ndarray):

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libefm.so")
 EC_OK = 0
 EC_ERR_ARG, EC_ERR_DEVICE, EC_ERR_OOM, EC_ERR_UNSUPPORTED, EC_ERR_DOMAIN = -1, -2, -3, -4, -5
 EC_KERNEL_MAXWELL, EC_KERNEL_HARD_SPHERE, EC_KERNEL_VHS = 0, 1, 2
+EC_TRUNC_BOX, EC_TRUNC_BALL = 0, 1
 EC_FP64, EC_FP32, EC_BF16X3 = 0, 1, 2
 EC_NMON = 7
 EC_SCHED_PIPELINE, EC_SCHED_TWO_PASS, EC_SCHED_FUSED = 0, 1, 2
@@ -37,7 +38,7 @@ class EcError(RuntimeError):
 
 class ec_kernel(ctypes.Structure):
     _fields_ = [("kind", _c_int), ("gamma", _c_double), ("R", _c_double), ("n_radial", _c_int),
-                ("unfiltered", _c_int)]
+                ("unfiltered", _c_int), ("truncation", _c_int)]
 
 
 _SIGS = {
@@ -139,8 +140,9 @@ def _stream(s):
     return s.cuda_stream
 
 
-def make_kernel(kind=EC_KERNEL_HARD_SPHERE, gamma=1.0, R=6.0, n_radial=0, unfiltered=False):
-    return ec_kernel(kind, gamma, R, n_radial, 1 if unfiltered else 0)
+def make_kernel(kind=EC_KERNEL_HARD_SPHERE, gamma=1.0, R=6.0, n_radial=0, unfiltered=False,
+                truncation=0):
+    return ec_kernel(kind, gamma, R, n_radial, 1 if unfiltered else 0, truncation)
 
 
 # ---- same-name wrappers -----------------------------------------------------

@@ -8,13 +8,20 @@ from . import _binding as B
 
 
 class Plan:
-    def __init__(self, N, d, L, M, kind=None, R=6.0, gamma=None, n_radial=0, filtered=True):
+    def __init__(self, N, d, L, M, kind=None, R=6.0, gamma=None, n_radial=0, filtered=True,
+                 truncation="box"):
+        """truncation "box" (|y|, |z| <= R) or "ball" (|g| <= R, the classical
+        form; 3D Maxwell / VHS)."""
         if kind is None:
             kind = B.EC_KERNEL_MAXWELL if d == 2 else B.EC_KERNEL_HARD_SPHERE
         if gamma is None:
             gamma = 0.0 if kind == B.EC_KERNEL_MAXWELL else 1.0
+        if truncation not in ("box", "ball"):
+            raise ValueError(f"truncation {truncation!r}: 'box' or 'ball'")
         self.N, self.d, self.L, self.M, self.kind, self.R = N, d, L, M, kind, R
-        self.kernel = B.make_kernel(kind, gamma, R, n_radial, unfiltered=not filtered)
+        self.kernel = B.make_kernel(kind, gamma, R, n_radial, unfiltered=not filtered,
+                                    truncation=B.EC_TRUNC_BALL if truncation == "ball"
+                                    else B.EC_TRUNC_BOX)
         self.handle = B.ec_setup_kernel(N, d, L, self.kernel, M)
 
     @property

@@ -135,6 +135,15 @@ static double phi3(double q, double R) {
 // when gamma = 1).  Phi_j is an entire function of q; it is sampled at the
 // Chebyshev points of [0, q_max] (each sample by Gauss-Legendre panels in r,
 // graded at r ~ rho_j where the weight changes) and evaluated by Clenshaw.
+//
+// Truncation.  The box |y| <= R, |z| <= R is the Carleman truncation of
+// section 1.2.  The classical form (eq. classical_hatB) integrates over
+// |g| <= R; with y = (g + |g| w)/2 and z = (g - |g| w)/2, which are orthogonal
+// with |y|^2 + |z|^2 = |g|^2, that is the ball |y|^2 + |z|^2 <= R^2 of the
+// same Carleman integrand: the disk of phi_{t,j} shrinks to radius
+// sqrt(R^2 - rho_j^2).  The radii are then rho = R sin(theta) with
+// Gauss-Legendre in theta on [0, pi/2] (omega = R cos(theta) w_theta), which
+// removes the square-root endpoint of the disk radius at rho = R.
 struct ChebFn {
   double qmax = 0.0;
   std::vector<double> c;   // Chebyshev coefficients on [0, qmax]
@@ -196,18 +205,30 @@ static void hemisphere_split(int M, int& mm, int& mp) {
 }
 
 int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
-                 int n_radial, int unfiltered, int M, HostTables& T, std::string& err) {
+                 int n_radial, int unfiltered, int truncation, int M, HostTables& T,
+                 std::string& err) {
   if (d != 2 && d != 3) { err = "d must be 2 or 3"; return EC_ERR_ARG; }
   if (N < 4 || M < 1 || !(L > 0.0)) { err = "need N >= 4, M >= 1, L > 0"; return EC_ERR_ARG; }
   if (!supported_size(N, d)) {
     err = "unsupported N (supported: 8, 12, 16, 24, 32, 3D also 64; 2D also 64 .. 512)";
     return EC_ERR_UNSUPPORTED;
   }
-  if (R <= 0.0) R = 4.0 * L / (3.0 * std::sqrt(2.0) + 1.0);
+  if (truncation != EC_TRUNC_BOX && truncation != EC_TRUNC_BALL) {
+    err = "truncation must be EC_TRUNC_BOX or EC_TRUNC_BALL";
+    return EC_ERR_ARG;
+  }
+  const bool ball = truncation == EC_TRUNC_BALL;
+  // largest R of the box bound: T >= (3 sqrt 2 + 1) R / 4 (Carleman),
+  // T >= (3 + sqrt 2) R / 4 (classical form)
+  if (R <= 0.0) R = 4.0 * L / (ball ? 3.0 + std::sqrt(2.0) : 3.0 * std::sqrt(2.0) + 1.0);
   const bool separable = (d == 2 && kind == EC_KERNEL_MAXWELL) || (d == 3 && kind == EC_KERNEL_HARD_SPHERE);
   const bool radial = d == 3 && (kind == EC_KERNEL_MAXWELL || kind == EC_KERNEL_VHS);
   if (!separable && !radial) {
     err = "kernels: 2D Maxwell; 3D hard spheres, Maxwell and variable hard spheres";
+    return EC_ERR_UNSUPPORTED;
+  }
+  if (ball && !radial) {
+    err = "the ball truncation needs a 3D radial kernel (EC_KERNEL_MAXWELL or EC_KERNEL_VHS)";
     return EC_ERR_UNSUPPORTED;
   }
   const double gexp = kind == EC_KERNEL_MAXWELL ? 0.0 : (kind == EC_KERNEL_HARD_SPHERE ? 1.0 : gamma_exp);
@@ -217,6 +238,7 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
   T.N = N; T.d = d; T.M = M; T.kind = kind; T.L = L; T.R = R; T.gamma_exp = gamma_exp;
   T.n_radial = nrad;
   T.unfiltered = unfiltered != 0;
+  T.truncation = truncation;
   T.n0 = (d == 3) ? N : 1;
   T.n1 = N;
   T.n2 = N;
@@ -268,21 +290,31 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
   auto mode = [N](int i) { return i < (N + 1) / 2 ? i : i - N; };
 
   // radial factors of the non-separable kernels
-  std::vector<double> rho, om;
+  std::vector<double> rho, om, rdisk;
   std::vector<ChebFn> hank;
   if (radial) {
     std::vector<double> x, w;
     gauss_legendre(nrad, x, w);
     rho.resize(nrad);
     om.resize(nrad);
+    rdisk.resize(nrad);
     for (int j = 0; j < nrad; ++j) {
-      rho[j] = 0.5 * R * (x[j] + 1.0);
-      om[j] = 0.5 * R * w[j];
+      if (ball) {
+        const double th = 0.25 * PI * (x[j] + 1.0), wth = 0.25 * PI * w[j];
+        rho[j] = R * std::sin(th);
+        om[j] = R * std::cos(th) * wth;
+        rdisk[j] = R * std::cos(th);
+      } else {
+        rho[j] = 0.5 * R * (x[j] + 1.0);
+        om[j] = 0.5 * R * w[j];
+        rdisk[j] = R;
+      }
     }
     double kmax2 = 0.0;   // largest |k|^2 over the modes bounds |k_perp|
     for (int i = 0; i < N; ++i) kmax2 = std::max(kmax2, (double)mode(i) * mode(i));
     const double qmax = kf * std::sqrt(3.0 * kmax2) * 1.0001;
-    for (int j = 0; j < nrad; ++j) hank.push_back(hankel_cheb(rho[j], 0.5 * (gexp - 1.0), R, qmax));
+    for (int j = 0; j < nrad; ++j)
+      hank.push_back(hankel_cheb(rho[j], 0.5 * (gexp - 1.0), rdisk[j], qmax));
   }
 
   auto fill_slab = [&](int i0) {

@@ -57,17 +57,21 @@ def test_library_tables_reproduce_oracle_operator(N, d, L, M):
     assert np.abs(ell - efm.collision_frequency(p, F)).max() < 1e-13 * np.abs(ell).max()
 
 
-@pytest.mark.parametrize("N,M,gamma,nr", [(8, 8, 0.0, 4), (8, 8, 0.5, 4), (12, 8, 0.25, 3)])
-def test_library_nonseparable_tables_reproduce_oracle_operator(N, M, gamma, nr):
-    """3D Maxwell / VHS: the library's radial products (Chebyshev-interpolated
-    Hankel factors) give the oracle's operator (direct Gauss-Legendre Hankel
-    transforms) to 1e-13 of the gain."""
+@pytest.mark.parametrize("N,M,gamma,nr,trunc", [(8, 8, 0.0, 4, "box"), (8, 8, 0.5, 4, "box"),
+                                                 (12, 8, 0.25, 3, "box"), (8, 8, 0.0, 5, "ball"),
+                                                 (12, 18, 0.5, 4, "ball")])
+def test_library_nonseparable_tables_reproduce_oracle_operator(N, M, gamma, nr, trunc):
+    """3D Maxwell / VHS, both truncations: the library's radial products
+    (Chebyshev-interpolated Hankel factors) give the oracle's operator (direct
+    Gauss-Legendre Hankel transforms) to 1e-13 of the gain."""
     L = 8.0
     kind = E.EC_KERNEL_MAXWELL if gamma == 0.0 else E.EC_KERNEL_VHS
-    G = _as_nat(E.ec_host_tables(N, 3, L, E.make_kernel(kind, gamma, R, nr), M), N, 3)
+    tr = E.EC_TRUNC_BALL if trunc == "ball" else E.EC_TRUNC_BOX
+    G = _as_nat(E.ec_host_tables(N, 3, L, E.make_kernel(kind, gamma, R, nr, truncation=tr), M),
+                N, 3)
     assert G.shape[0] == M * nr + 1
     okind = efm.KIND_MAXWELL if gamma == 0.0 else efm.KIND_VHS
-    p = efm.make_plan(N, 3, L, M, kind=okind, R=R, gamma=gamma, n_radial=nr)
+    p = efm.make_plan(N, 3, L, M, kind=okind, R=R, gamma=gamma, n_radial=nr, truncation=trunc)
     F = synth.sample_mixture(synth.mixture_anisotropic(11 + N, 3), N, L)
     q, qp, ell = model_pipeline(G, F)
     ref = efm.collide_modes(p, F)
@@ -122,6 +126,15 @@ def test_library_rejects_bad_arguments():
     assert ei.value.code == E.EC_ERR_UNSUPPORTED and "kernel" in E.ec_last_error()
     with pytest.raises(E.EcError) as ei:
         E.ec_host_tables(8, 3, 8.0, E.make_kernel(E.EC_KERNEL_VHS, 1.5, R), 8)
+    assert ei.value.code == E.EC_ERR_ARG
+    # the ball truncation needs the radial path; truncation codes are 0 or 1
+    for kern, d in ((E.make_kernel(E.EC_KERNEL_HARD_SPHERE, 1.0, R, truncation=E.EC_TRUNC_BALL), 3),
+                    (E.make_kernel(E.EC_KERNEL_MAXWELL, 0.0, R, truncation=E.EC_TRUNC_BALL), 2)):
+        with pytest.raises(E.EcError) as ei:
+            E.ec_host_tables(8, d, 8.0, kern, 8)
+        assert ei.value.code == E.EC_ERR_UNSUPPORTED and "ball" in E.ec_last_error()
+    with pytest.raises(E.EcError) as ei:
+        E.ec_host_tables(8, 3, 8.0, E.make_kernel(E.EC_KERNEL_MAXWELL, 0.0, R, 4, truncation=2), 8)
     assert ei.value.code == E.EC_ERR_ARG
 
 
