@@ -86,6 +86,16 @@ extern "C" {
  */
 #define EC_TRUNC_BOX  0
 #define EC_TRUNC_BALL 1
+/*
+ * Angular factor of the classical form: B(g, w) = C_3 |g|^gamma b(cos theta),
+ * cos theta = g.w / |g|, b(x) = sum_{i < n_bcos} bcos[i] x^i (n_bcos = 0:
+ * b = 1, the isotropic kernels).  In the Carleman variables
+ * cos theta = (|y|^2 - |z|^2) / (|y|^2 + |z|^2), a function of the two radii,
+ * so it joins the radial weight of phi_{t,j} (3D radial kernels only, either
+ * truncation).  b should be >= 0 on [-1, 1] for a physical kernel; the
+ * library does not check it.
+ */
+#define EC_MAX_BCOS 8
 
 typedef struct ec_kernel {
   int kind;          /* EC_KERNEL_*                                          */
@@ -99,6 +109,9 @@ typedef struct ec_kernel {
                         (eq. FCM) -- not positivity preserving; the comparison
                         of the positivity study (section 4.2, Fig. 2)        */
   int truncation;    /* EC_TRUNC_BOX (0) or EC_TRUNC_BALL (1)                 */
+  int n_bcos;        /* 0 .. EC_MAX_BCOS coefficients of b(cos theta)        */
+  double bcos[EC_MAX_BCOS];   /* b(x) = sum_i bcos[i] x^i (copied by the
+                                  plan; unused entries ignored)              */
 } ec_kernel;
 
 /* ---- precision of the transforms --------------------------------------- */

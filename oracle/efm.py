@@ -300,11 +300,21 @@ def lowrank_3d_hard_sphere(N: int, L: float, R: float, M: int) -> LowRank:
     return LowRank(0.5 * bt * w, U, V)
 
 
-def hankel_disk(q: np.ndarray, rho: float, a: float, R: float) -> np.ndarray:
-    """2 int_{|x|<=R, x in a plane} (rho^2 + |x|^2)^a cos(q x_1) dx
-    = 4 pi int_0^R (rho^2 + r^2)^a J_0(q r) r dr (the angular integral of the
-    disk is 2 pi J_0), by Gauss-Legendre in r.  rho > 0 keeps the weight
-    smooth.  a = 0 gives the hard-sphere disk integral."""
+def bcos_eval(bcos, x):
+    """b(x) = sum_i bcos[i] x^i (b = 1 when bcos is empty or None)."""
+    if not bcos:
+        return np.ones_like(x)
+    return np.polynomial.polynomial.polyval(x, np.asarray(bcos, float))
+
+
+def hankel_disk(q: np.ndarray, rho: float, a: float, R: float, bcos=None) -> np.ndarray:
+    """2 int_{|x|<=R, x in a plane} (rho^2 + |x|^2)^a b(cos theta) cos(q x_1) dx
+    = 4 pi int_0^R (rho^2 + r^2)^a b(cos theta) J_0(q r) r dr (the angular
+    integral of the disk is 2 pi J_0), by Gauss-Legendre in r.  rho > 0 keeps
+    the weight smooth.  a = 0, b = 1 gives the hard-sphere disk integral.
+    cos theta = (rho^2 - r^2)/(rho^2 + r^2) is the angle between g = y + z and
+    w = (y - z)/|g| of the classical form for |y| = rho, |z| = r (y, z
+    orthogonal)."""
     from scipy.special import j0
     qmax = float(np.max(np.abs(q))) if q.size else 0.0
     n = int(math.ceil(0.75 * qmax * R)) + 64
@@ -317,6 +327,7 @@ def hankel_disk(q: np.ndarray, rho: float, a: float, R: float) -> np.ndarray:
     r = np.concatenate([x for x, _ in parts])
     w = np.concatenate([y for _, y in parts])
     wt = 4.0 * math.pi * w * r * (rho * rho + r * r) ** a
+    wt = wt * bcos_eval(bcos, (rho * rho - r * r) / (rho * rho + r * r))
     out = np.empty(q.shape)
     flat_q, flat_o = q.ravel(), out.ravel()
     for c0 in range(0, flat_q.size, 2048):
@@ -326,7 +337,7 @@ def hankel_disk(q: np.ndarray, rho: float, a: float, R: float) -> np.ndarray:
 
 
 def lowrank_3d_vhs(N: int, L: float, R: float, M: int, gamma: float, n_radial: int,
-                   truncation: str = "box") -> LowRank:
+                   truncation: str = "box", bcos=None) -> LowRank:
     """Variable hard spheres B = C_3 |g|^gamma in 3D: Carleman weight
     Bt(y, z) = 2^2 C_3 (|y|^2 + |z|^2)^a with a = (gamma - 1)/2 (section 1),
     which does not factor in (|y|, |z|).  The polar form of the 3D kernel
@@ -345,7 +356,11 @@ def lowrank_3d_vhs(N: int, L: float, R: float, M: int, gamma: float, n_radial: i
     classical form (eq. classical_hatB: y = (g + |g| w)/2, z = (g - |g| w)/2
     are orthogonal with |y|^2 + |z|^2 = |g|^2): r_j = sqrt(R^2 - rho_j^2),
     with rho = R sin(theta) and Gauss-Legendre in theta on [0, pi/2] (the
-    substitution removes the square-root endpoint of r_j)."""
+    substitution removes the square-root endpoint of r_j).
+
+    bcos: an angular factor B = C_3 |g|^gamma b(cos theta), b a polynomial
+    (coefficients of 1, x, x^2, ...), inside the radial weight of phi_{t,j}
+    (cos theta = (rho^2 - r^2)/(rho^2 + r^2), see hankel_disk)."""
     kx, ky, kz = mode_grid(N, 3)
     dirs, w = directions_3d(M)
     bt = 4.0 * C_D[3]
@@ -369,7 +384,7 @@ def lowrank_3d_vhs(N: int, L: float, R: float, M: int, gamma: float, n_radial: i
         for j in range(n_radial):
             i = t * n_radial + j
             U[i] = 2.0 * om[j] * rho[j] * np.cos(rho[j] * s)
-            V[i] = hankel_disk(qperp, rho[j], a, rdisk[j])
+            V[i] = hankel_disk(qperp, rho[j], a, rdisk[j], bcos)
             c[i] = 0.5 * bt * w[t]
     return LowRank(c, U, V)
 
@@ -390,6 +405,43 @@ def ball_radial_integral(p: np.ndarray, q: np.ndarray, R: float) -> np.ndarray:
         out[one] = (np.sin(xx * R) - xx * R * np.cos(xx * R)) / xx ** 3
     out[(p == 0) & (q == 0)] = R ** 3 / 3.0
     return out
+
+
+def classical_kernel_3d_angular(N: int, L: float, R: float, bcos, gamma: float = 0.0,
+                                n_rho: int = 96) -> np.ndarray:
+    """Dense classical-form modes (eq. classical_hatB) for B = C_3 |g|^gamma
+    b(g.w / |g|), b a polynomial, by the Funk-Hecke formula: with
+    b = sum_n beta_n P_n (Legendre coefficients), the sphere integral of
+    b(g^.w) E over w is 4 pi sum_n beta_n i^n j_n(a |g| |l-m|) P_n(g^.u), and
+    the sphere integral over g^ then gives
+        B(l,m) = C_3 (4 pi)^2 sum_n beta_n (-1)^n P_n(cos phi)
+                 int_0^R rho^{2+gamma} j_n(a rho |l+m|) j_n(a rho |l-m|) d rho,
+    cos phi = (|l|^2 - |m|^2) / (|l+m| |l-m|), a = pi / (2T); the radial
+    integral by Gauss-Legendre (n_rho nodes).  b = 1 is classical_kernel_3d."""
+    from scipy.special import eval_legendre, spherical_jn
+    beta = np.polynomial.legendre.poly2leg(np.asarray(bcos, float))
+    k = np.array(mode_grid(N, 3), dtype=float).T
+    n = k.shape[0]
+    a = math.pi / (2.0 * L)
+    rho, w = gauss_legendre(n_rho, 0.0, R)
+    wr = w * rho ** (2.0 + gamma)
+    B = np.zeros((n, n))
+    for i0 in range(0, n, 64):
+        l = k[i0:i0 + 64, None, :]
+        sp = np.sqrt(((l + k[None]) ** 2).sum(axis=2))
+        sm = np.sqrt(((l - k[None]) ** 2).sum(axis=2))
+        num = (l * l).sum(axis=2) - (k[None] * k[None]).sum(axis=2)
+        den = sp * sm
+        cphi = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+        blk = np.zeros(sp.shape)
+        for nn, bn in enumerate(beta):
+            if bn == 0.0:
+                continue
+            jp = spherical_jn(nn, a * sp[..., None] * rho)
+            jm = spherical_jn(nn, a * sm[..., None] * rho)
+            blk += bn * (-1.0) ** nn * eval_legendre(nn, cphi) * ((jp * jm) @ wr)
+        B[i0:i0 + 64] = C_D[3] * (4.0 * math.pi) ** 2 * blk
+    return B
 
 
 def classical_kernel_3d(N: int, L: float, R: float) -> np.ndarray:
@@ -438,7 +490,7 @@ class Plan:
 
 def make_plan(N: int, d: int, L: float, M: int, kind: str | None = None,
               R: float = 6.0, filtered: bool = True, gamma: float | None = None,
-              n_radial: int = 8, truncation: str = "box") -> Plan:
+              n_radial: int = 8, truncation: str = "box", bcos=None) -> Plan:
     """kind None: 2D Maxwell / 3D hard spheres.  In 3D, KIND_MAXWELL is the
     variable-hard-sphere kernel with gamma = 0 and KIND_VHS takes gamma; both
     use n_radial radial nodes (M' = M n_radial terms) and either truncation
@@ -451,11 +503,12 @@ def make_plan(N: int, d: int, L: float, M: int, kind: str | None = None,
         lr = lowrank_3d_hard_sphere(N, L, R, M)
     elif d == 3 and kind in (KIND_MAXWELL, KIND_VHS):
         g = 0.0 if kind == KIND_MAXWELL else float(gamma)
-        lr = lowrank_3d_vhs(N, L, R, M, g, n_radial, truncation)
+        lr = lowrank_3d_vhs(N, L, R, M, g, n_radial, truncation, bcos)
     else:
         raise NotImplementedError(f"oracle kernel {kind} in {d}D")
-    if truncation != "box" and not (d == 3 and kind in (KIND_MAXWELL, KIND_VHS)):
-        raise NotImplementedError("the ball truncation needs the radial (non-separable) path")
+    if (truncation != "box" or bcos) and not (d == 3 and kind in (KIND_MAXWELL, KIND_VHS)):
+        raise NotImplementedError("the ball truncation and an angular factor need the radial "
+                                  "(non-separable) path")
     sig = sigma_nd(N, d) if filtered else unfiltered_nd(N, d)
     return Plan(N, d, L, R, M, kind, sig, lr)
 

@@ -38,7 +38,8 @@ class EcError(RuntimeError):
 
 class ec_kernel(ctypes.Structure):
     _fields_ = [("kind", _c_int), ("gamma", _c_double), ("R", _c_double), ("n_radial", _c_int),
-                ("unfiltered", _c_int), ("truncation", _c_int)]
+                ("unfiltered", _c_int), ("truncation", _c_int), ("n_bcos", _c_int),
+                ("bcos", _c_double * 8)]
 
 
 _SIGS = {
@@ -140,9 +141,17 @@ def _stream(s):
     return s.cuda_stream
 
 
+EC_MAX_BCOS = 8
+
+
 def make_kernel(kind=EC_KERNEL_HARD_SPHERE, gamma=1.0, R=6.0, n_radial=0, unfiltered=False,
-                truncation=0):
-    return ec_kernel(kind, gamma, R, n_radial, 1 if unfiltered else 0, truncation)
+                truncation=0, bcos=None):
+    """bcos: coefficients of b(cos theta) = sum_i bcos[i] cos^i theta (None: b = 1)."""
+    bc = list(bcos or [])
+    if len(bc) > EC_MAX_BCOS:
+        raise ValueError(f"at most {EC_MAX_BCOS} coefficients of b(cos theta)")
+    arr = (_c_double * 8)(*(bc + [0.0] * (8 - len(bc))))
+    return ec_kernel(kind, gamma, R, n_radial, 1 if unfiltered else 0, truncation, len(bc), arr)
 
 
 # ---- same-name wrappers -----------------------------------------------------

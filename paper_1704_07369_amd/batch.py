@@ -9,9 +9,10 @@ from . import _binding as B
 
 class Plan:
     def __init__(self, N, d, L, M, kind=None, R=6.0, gamma=None, n_radial=0, filtered=True,
-                 truncation="box"):
+                 truncation="box", bcos=None):
         """truncation "box" (|y|, |z| <= R) or "ball" (|g| <= R, the classical
-        form; 3D Maxwell / VHS)."""
+        form; 3D Maxwell / VHS); bcos: coefficients of an angular factor
+        b(cos theta) = sum_i bcos[i] cos^i theta (3D Maxwell / VHS)."""
         if kind is None:
             kind = B.EC_KERNEL_MAXWELL if d == 2 else B.EC_KERNEL_HARD_SPHERE
         if gamma is None:
@@ -21,7 +22,7 @@ class Plan:
         self.N, self.d, self.L, self.M, self.kind, self.R = N, d, L, M, kind, R
         self.kernel = B.make_kernel(kind, gamma, R, n_radial, unfiltered=not filtered,
                                     truncation=B.EC_TRUNC_BALL if truncation == "ball"
-                                    else B.EC_TRUNC_BOX)
+                                    else B.EC_TRUNC_BOX, bcos=bcos)
         self.handle = B.ec_setup_kernel(N, d, L, self.kernel, M)
 
     @property

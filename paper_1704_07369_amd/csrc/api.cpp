@@ -375,7 +375,8 @@ int ec_host_tables(int N, int d, double L, const ec_kernel* kernel, int M, int* 
     HostTables T;
     std::string err;
     int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial,
-                          kernel->unfiltered, kernel->truncation, M, T, err);
+                          kernel->unfiltered, kernel->truncation, kernel->n_bcos,
+                          kernel->bcos, M, T, err);
     if (rc) return fail(rc, err);
     if (n_terms) *n_terms = T.terms;
     if (gamma) std::memcpy(gamma, T.gamma.data(), T.gamma.size() * sizeof(double));
@@ -390,7 +391,8 @@ int ec_setup_kernel(int N, int d, double L, const ec_kernel* kernel, int M, ec_p
     auto* p = new ec_plan();
     std::string err;
     int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial,
-                          kernel->unfiltered, kernel->truncation, M, p->host, err);
+                          kernel->unfiltered, kernel->truncation, kernel->n_bcos,
+                          kernel->bcos, M, p->host, err);
     if (rc) { delete p; return fail(rc, err); }
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(EC_ERR_DEVICE, "no HIP device"); }
     const size_t cnt = p->host.gamma.size();
@@ -609,6 +611,10 @@ std::string tune_key(int dev, const HostTables& T, int precision, int64_t count)
   }
   if (T.unfiltered) key += "|nofilter";
   if (T.truncation == EC_TRUNC_BALL) key += "|ball";
+  for (size_t i = 0; i < T.bcos.size(); ++i) {
+    std::snprintf(buf, sizeof buf, "%sb%.6g", i ? "," : "|", T.bcos[i]);
+    key += buf;
+  }
   return key;
 }
 

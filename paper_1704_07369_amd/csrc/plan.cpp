@@ -159,7 +159,20 @@ struct ChebFn {
   }
 };
 
-static ChebFn hankel_cheb(double rho, double a, double R, double qmax) {
+// b(x) = sum_i bcos[i] x^i (Horner); b = 1 when nb == 0
+static double bcos_eval(const double* bcos, int nb, double x) {
+  if (nb <= 0) return 1.0;
+  double acc = 0.0;
+  for (int i = nb - 1; i >= 0; --i) acc = acc * x + bcos[i];
+  return acc;
+}
+
+// With an angular factor b(cos theta) in B(g, w), cos theta = g.w / |g|
+// = (|y|^2 - |z|^2) / (|y|^2 + |z|^2) in the Carleman variables
+// (y = (g + |g| w)/2, z = (g - |g| w)/2, orthogonal): for |y| = rho_j and
+// |z| = r it joins the radial weight of Phi_j.
+static ChebFn hankel_cheb(double rho, double a, double R, double qmax, const double* bcos,
+                          int nb) {
   const double PI_ = 3.14159265358979323846;
   // r panels [0, 2 rho], [2 rho, 8 rho], [8 rho, R] (clipped to R)
   std::vector<double> edges = {0.0};
@@ -175,7 +188,8 @@ static ChebFn hankel_cheb(double rho, double a, double R, double qmax) {
     for (int i = 0; i < n; ++i) {
       const double r = 0.5 * (hi - lo) * (x[i] + 1.0) + lo;
       rr.push_back(r);
-      ww.push_back(0.5 * (hi - lo) * w[i] * 4.0 * PI_ * r * std::pow(rho * rho + r * r, a));
+      ww.push_back(0.5 * (hi - lo) * w[i] * 4.0 * PI_ * r * std::pow(rho * rho + r * r, a) *
+                   bcos_eval(bcos, nb, (rho * rho - r * r) / (rho * rho + r * r)));
     }
   }
   const int D = (int)std::ceil(0.75 * qmax * R) + 64;
@@ -205,8 +219,8 @@ static void hemisphere_split(int M, int& mm, int& mp) {
 }
 
 int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
-                 int n_radial, int unfiltered, int truncation, int M, HostTables& T,
-                 std::string& err) {
+                 int n_radial, int unfiltered, int truncation, int n_bcos, const double* bcos,
+                 int M, HostTables& T, std::string& err) {
   if (d != 2 && d != 3) { err = "d must be 2 or 3"; return EC_ERR_ARG; }
   if (N < 4 || M < 1 || !(L > 0.0)) { err = "need N >= 4, M >= 1, L > 0"; return EC_ERR_ARG; }
   if (!supported_size(N, d)) {
@@ -231,6 +245,14 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
     err = "the ball truncation needs a 3D radial kernel (EC_KERNEL_MAXWELL or EC_KERNEL_VHS)";
     return EC_ERR_UNSUPPORTED;
   }
+  if (n_bcos < 0 || n_bcos > EC_MAX_BCOS || (n_bcos > 0 && !bcos)) {
+    err = "n_bcos must be 0 .. EC_MAX_BCOS";
+    return EC_ERR_ARG;
+  }
+  if (n_bcos > 0 && !radial) {
+    err = "an angular factor b(cos theta) needs a 3D radial kernel (EC_KERNEL_MAXWELL or EC_KERNEL_VHS)";
+    return EC_ERR_UNSUPPORTED;
+  }
   const double gexp = kind == EC_KERNEL_MAXWELL ? 0.0 : (kind == EC_KERNEL_HARD_SPHERE ? 1.0 : gamma_exp);
   if (radial && !(gexp > -1.0 && gexp <= 1.0)) { err = "VHS needs -1 < gamma <= 1"; return EC_ERR_ARG; }
   const int nrad = radial ? (n_radial > 0 ? n_radial : 8) : 1;
@@ -239,6 +261,7 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
   T.n_radial = nrad;
   T.unfiltered = unfiltered != 0;
   T.truncation = truncation;
+  T.bcos.assign(bcos, bcos + std::max(0, n_bcos));
   T.n0 = (d == 3) ? N : 1;
   T.n1 = N;
   T.n2 = N;
@@ -314,7 +337,8 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
     for (int i = 0; i < N; ++i) kmax2 = std::max(kmax2, (double)mode(i) * mode(i));
     const double qmax = kf * std::sqrt(3.0 * kmax2) * 1.0001;
     for (int j = 0; j < nrad; ++j)
-      hank.push_back(hankel_cheb(rho[j], 0.5 * (gexp - 1.0), rdisk[j], qmax));
+      hank.push_back(hankel_cheb(rho[j], 0.5 * (gexp - 1.0), rdisk[j], qmax, T.bcos.data(),
+                                 (int)T.bcos.size()));
   }
 
   auto fill_slab = [&](int i0) {

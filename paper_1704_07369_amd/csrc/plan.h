@@ -15,6 +15,7 @@ struct HostTables {
   int n_radial = 1;             // radial nodes (non-separable kernels), else 1
   bool unfiltered = false;      // sigma = 1 (Fourier collocation, no entropic filter)
   int truncation = 0;           // EC_TRUNC_BOX or EC_TRUNC_BALL
+  std::vector<double> bcos;     // angular factor b(x) = sum_i bcos[i] x^i (empty: 1)
   int terms = 0;                // M' products in the gain (M n_radial)
   int J = 0;                    // transforms after the forward one: M' + 1
   // gamma[(j * n + idx) * 2 + {0,1}], idx = (k0 * n2 + k2) * n1 + k1
@@ -23,8 +24,8 @@ struct HostTables {
 
 // Returns 0 or an EC_ERR_* code with a message in err.
 int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
-                 int n_radial, int unfiltered, int truncation, int M, HostTables& out,
-                 std::string& err);
+                 int n_radial, int unfiltered, int truncation, int n_bcos, const double* bcos,
+                 int M, HostTables& out, std::string& err);
 
 // Modified Jackson filter (section 3.2.2, eq. JacksonFilter2) for the mode
 // value k of an N-point axis.

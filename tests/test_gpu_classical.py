@@ -1,9 +1,10 @@
-"""GPU runs of the classical-form truncation |g| <= R (EC_TRUNC_BALL):
+"""GPU runs of the classical form: the truncation |g| <= R (EC_TRUNC_BALL)
+and an angular factor b(cos theta):
 
-- parity of the collision operator with the oracle's ball kernel (same
-  hemisphere rule and radial nodes): FP64 1e-12 and FP32 1e-5 of the gain on
-  the full 16^3 grid, 3D Maxwell and VHS gamma = 0.5, through the pipelined,
-  fused and two-pass schedules;
+- parity of the collision operator with the oracle's kernel (same hemisphere
+  rule and radial nodes): FP64 1e-12 and FP32 1e-5 of the gain on the full
+  16^3 grid, 3D Maxwell and VHS gamma = 0.5, b = 1 and b = 1 + x/2 + x^2/4,
+  through the pipelined, fused and two-pass schedules;
 - section 4.2, Example 4, Table 3: one SSP-RK3 step (dt = 0.01) of the library
   from the 3D BKW datum, box T = (3 + sqrt 2) R / 4, R = 6, rows N = 16, 32, 64
   (N = 128 is beyond the supported 3D grids).  Every entry within 0.5 % of
@@ -27,17 +28,24 @@ R = 6.0
 TOL = {0: 1e-12, 1: 1e-5}
 
 
-@pytest.mark.parametrize("gamma,prec,mode,split", [
-    (0.0, 0, 0, 0), (0.0, 0, 2, 2), (0.0, 1, 2, 1), (0.5, 0, 1, 0), (0.5, 1, 2, 2),
+BCOS = [1.0, 0.5, 0.25]
+
+
+@pytest.mark.parametrize("gamma,prec,mode,split,trunc,bcos", [
+    (0.0, 0, 0, 0, "ball", None), (0.0, 0, 2, 2, "ball", None), (0.0, 1, 2, 1, "ball", None),
+    (0.5, 0, 1, 0, "ball", None), (0.5, 1, 2, 2, "ball", None),
+    (0.0, 0, 2, 1, "ball", BCOS), (0.0, 1, 0, 0, "ball", BCOS), (0.5, 0, 1, 0, "box", BCOS),
 ])
-def test_ball_parity_16_full_grid(gamma, prec, mode, split):
+def test_classical_parity_16_full_grid(gamma, prec, mode, split, trunc, bcos):
     import torch
-    say(f"case ball truncation 16^3 gamma={gamma} precision={prec} mode={mode} split={split}")
+    say(f"case classical form 16^3 gamma={gamma} precision={prec} mode={mode} split={split} "
+        f"truncation={trunc} bcos={bcos}")
     N, M, nr, L = 16, 8, 4, 8.0
     kind = E.EC_KERNEL_MAXWELL if gamma == 0.0 else E.EC_KERNEL_VHS
     okind = efm.KIND_MAXWELL if gamma == 0.0 else efm.KIND_VHS
-    p = E.Plan(N, 3, L, M, kind=kind, R=R, gamma=gamma, n_radial=nr, truncation="ball")
-    op = efm.make_plan(N, 3, L, M, kind=okind, R=R, gamma=gamma, n_radial=nr, truncation="ball")
+    p = E.Plan(N, 3, L, M, kind=kind, R=R, gamma=gamma, n_radial=nr, truncation=trunc, bcos=bcos)
+    op = efm.make_plan(N, 3, L, M, kind=okind, R=R, gamma=gamma, n_radial=nr, truncation=trunc,
+                       bcos=bcos)
     cells = [synth.sample_mixture(synth.mixture_anisotropic(9700 + i, 3), N, L) for i in range(3)]
     b = E.Batch([p], [3], prec)
     b.set_schedule(0, mode, 0, split)

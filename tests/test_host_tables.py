@@ -57,21 +57,24 @@ def test_library_tables_reproduce_oracle_operator(N, d, L, M):
     assert np.abs(ell - efm.collision_frequency(p, F)).max() < 1e-13 * np.abs(ell).max()
 
 
-@pytest.mark.parametrize("N,M,gamma,nr,trunc", [(8, 8, 0.0, 4, "box"), (8, 8, 0.5, 4, "box"),
-                                                 (12, 8, 0.25, 3, "box"), (8, 8, 0.0, 5, "ball"),
-                                                 (12, 18, 0.5, 4, "ball")])
-def test_library_nonseparable_tables_reproduce_oracle_operator(N, M, gamma, nr, trunc):
-    """3D Maxwell / VHS, both truncations: the library's radial products
-    (Chebyshev-interpolated Hankel factors) give the oracle's operator (direct
-    Gauss-Legendre Hankel transforms) to 1e-13 of the gain."""
+@pytest.mark.parametrize("N,M,gamma,nr,trunc,bcos", [
+    (8, 8, 0.0, 4, "box", None), (8, 8, 0.5, 4, "box", None), (12, 8, 0.25, 3, "box", None),
+    (8, 8, 0.0, 5, "ball", None), (12, 18, 0.5, 4, "ball", None),
+    (8, 8, 0.0, 4, "ball", [1.0, 0.5, 0.25]), (8, 8, 0.5, 4, "box", [0.5, -0.3, 0.0, 0.2])])
+def test_library_nonseparable_tables_reproduce_oracle_operator(N, M, gamma, nr, trunc, bcos):
+    """3D Maxwell / VHS, both truncations, with and without an angular factor:
+    the library's radial products (Chebyshev-interpolated Hankel factors) give
+    the oracle's operator (direct Gauss-Legendre Hankel transforms) to 1e-13
+    of the gain."""
     L = 8.0
     kind = E.EC_KERNEL_MAXWELL if gamma == 0.0 else E.EC_KERNEL_VHS
     tr = E.EC_TRUNC_BALL if trunc == "ball" else E.EC_TRUNC_BOX
-    G = _as_nat(E.ec_host_tables(N, 3, L, E.make_kernel(kind, gamma, R, nr, truncation=tr), M),
-                N, 3)
+    G = _as_nat(E.ec_host_tables(N, 3, L, E.make_kernel(kind, gamma, R, nr, truncation=tr,
+                                                        bcos=bcos), M), N, 3)
     assert G.shape[0] == M * nr + 1
     okind = efm.KIND_MAXWELL if gamma == 0.0 else efm.KIND_VHS
-    p = efm.make_plan(N, 3, L, M, kind=okind, R=R, gamma=gamma, n_radial=nr, truncation=trunc)
+    p = efm.make_plan(N, 3, L, M, kind=okind, R=R, gamma=gamma, n_radial=nr, truncation=trunc,
+                      bcos=bcos)
     F = synth.sample_mixture(synth.mixture_anisotropic(11 + N, 3), N, L)
     q, qp, ell = model_pipeline(G, F)
     ref = efm.collide_modes(p, F)
@@ -135,6 +138,15 @@ def test_library_rejects_bad_arguments():
         assert ei.value.code == E.EC_ERR_UNSUPPORTED and "ball" in E.ec_last_error()
     with pytest.raises(E.EcError) as ei:
         E.ec_host_tables(8, 3, 8.0, E.make_kernel(E.EC_KERNEL_MAXWELL, 0.0, R, 4, truncation=2), 8)
+    assert ei.value.code == E.EC_ERR_ARG
+    # an angular factor needs the radial path; at most EC_MAX_BCOS coefficients
+    with pytest.raises(E.EcError) as ei:
+        E.ec_host_tables(8, 3, 8.0, E.make_kernel(E.EC_KERNEL_HARD_SPHERE, 1.0, R, bcos=[1.0, 0.5]), 8)
+    assert ei.value.code == E.EC_ERR_UNSUPPORTED and "angular" in E.ec_last_error()
+    k = E.make_kernel(E.EC_KERNEL_MAXWELL, 0.0, R, 4, bcos=[1.0])
+    k.n_bcos = E.EC_MAX_BCOS + 1
+    with pytest.raises(E.EcError) as ei:
+        E.ec_host_tables(8, 3, 8.0, k, 8)
     assert ei.value.code == E.EC_ERR_ARG
 
 

@@ -9,6 +9,10 @@ other than the formula under test:
   (sphere integral of E in closed form, one radial integral): two independent
   routes to the same operator;
 - Theorem 1 (mass, H-theorem) for the ball kernel;
+- an angular factor b(cos theta): the exact modes by the Funk-Hecke formula
+  (Legendre expansion of b, spherical Bessel radial integrals) reduce to the
+  closed form for b = 1, have the parity of a linear b, and the low-rank
+  kernel (b inside the radial weight) converges to them;
 - section 4.2, Example 4, Table 3, row N = 16: one SSP-RK3 step of the exact
   classical-form operator at T = (3 + sqrt 2) R / 4 reproduces the printed
   errors (reading: the 3D BKW experiment uses the classical form).
@@ -101,3 +105,52 @@ def test_table3_row16_with_exact_classical_modes(golden):
     for got, printed in zip(errs, row[1:4]):
         assert abs(got - printed) <= 5e-3 * printed
     assert float(f"{errs[1]:.2e}") == row[2] and float(f"{errs[2]:.2e}") == row[3]
+
+
+# ---- angular factor b(cos theta) of the classical form -----------------------
+
+BCOS = [1.0, 0.5, 0.25]          # b(x) = 1 + x/2 + x^2/4 > 0 on [-1, 1]
+
+
+def test_funk_hecke_modes_reduce_to_closed_form_for_b_one():
+    N = 4
+    T = efm.classical_box(R)
+    B1 = efm.classical_kernel_3d_angular(N, T, R, [1.0])
+    B0 = efm.classical_kernel_3d(N, T, R)
+    assert np.abs(B1 - B0).max() <= 1e-13 * np.abs(B0).max()
+
+
+def test_funk_hecke_modes_of_a_linear_b():
+    """b(x) = x: only the P_1 term, B(l,m) = -C_3 (4 pi)^2 cos(phi) int rho^2
+    j_1(a rho |l+m|) j_1(a rho |l-m|) d rho; it vanishes when |l| = |m| and is
+    odd under l <-> m (cos phi changes sign)."""
+    N = 4
+    T = efm.classical_box(R)
+    B = efm.classical_kernel_3d_angular(N, T, R, [0.0, 1.0])
+    k = np.array(efm.mode_grid(N, 3)).T
+    n2 = (k * k).sum(1)
+    same = n2[:, None] == n2[None, :]
+    assert np.abs(B[same]).max() <= 1e-14 * np.abs(B).max()
+    assert np.abs(B + B.T).max() <= 1e-14 * np.abs(B).max()
+
+
+def test_lowrank_ball_with_angular_factor_converges():
+    N = 4
+    T = efm.classical_box(R)
+    Bx = efm.classical_kernel_3d_angular(N, T, R, BCOS)
+    errs = []
+    for M, nr in [(18, 8), (50, 16), (72, 24)]:
+        B = efm.lowrank_3d_vhs(N, T, R, M, 0.0, nr, "ball", BCOS).matrix()
+        errs.append(np.abs(B - Bx).max() / np.abs(Bx).max())
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 2e-3
+
+
+@pytest.mark.parametrize("trunc", ["box", "ball"])
+def test_theorem1_with_angular_factor(trunc):
+    N, L = 8, 8.0
+    p = efm.make_plan(N, 3, L, 8, kind=efm.KIND_MAXWELL, n_radial=4, truncation=trunc, bcos=BCOS)
+    F = synth.sample_mixture(synth.mixture_anisotropic(93, 3), N, L)
+    c = efm.collide_modes(p, F)
+    assert abs(c.Q.sum()) <= 1e-13 * np.abs(c.Q).sum()
+    assert np.sum(c.Q * np.log(F)) <= 0.0
+    assert c.imag_max <= 1e-13 * np.abs(c.Qplus).max()
