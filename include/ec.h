@@ -197,7 +197,8 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
  * term's inverse transform on chip (the x axis split by decimation in
  * frequency into term_groups residue classes, one workgroup per class) and
  * accumulates the gain in FP64 registers, so no per-term intermediate touches
- * device memory; splits: N = 16: 1, 2; N = 24: 2, 3; N = 32: 4 (FP32 also 2).
+ * device memory; splits: N = 16: 1, 2; N = 24: 2, 3; N = 32: 2, 4 (at 32^3
+ * the term volume is held in registers, one column or line per thread).
  * 0 for cells_per_pass or term_groups selects the default (chosen from the
  * cache size); the autotuner picks measured values.  A new batch starts with
  * the fused schedule where it exists and the group has at least 32 cells,
