@@ -40,9 +40,10 @@ __device__ __forceinline__ cx<R> unit_root(int m) {
 }
 
 // forward DFT along x of every (cell, k2, k1) pencil of W[cell][x][k2][k1], in place
-template <typename R, int N>
+// (KZ = N / 2: the half-space layout W[cell][x][k2 < N/2][k1])
+template <typename R, int N, int KZ = N>
 __global__ __launch_bounds__(64) void k_fwdx(cx<R>* __restrict__ W, int ncells) {
-  constexpr int P2 = N * N;
+  constexpr int P2 = KZ * N;
   const int64_t gid = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (gid >= (int64_t)ncells * P2) return;
   const int64_t cc = gid / P2;
@@ -312,11 +313,13 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Gather of one term into the thread's z column v[k2] (plane a, column bq;
-// col = a N^2 + bq indexes its first input): entries k2 < N/2 from its own
-// loads, k2 > N/2 from the mirror partner, whose lane is partner4 / 4.
+// col = a N^2 + bq indexes its first table entry, fcol = a N^2 / 2 + bq its
+// first input in the half-space spectrum [k0][k2 < N/2][k1]): entries
+// k2 < N/2 from its own loads, k2 > N/2 from the mirror partner, whose lane
+// is partner4 / 4.
 template <typename R, int N, int P, int S>
 __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
-                                           const cx<R>* __restrict__ Fc, int col,
+                                           const cx<R>* __restrict__ Fc, int col, int fcol,
                                            int partner4, cx<R> tw, cx<R> (&v)[N]) {
   constexpr int NP = N / P;
   constexpr int GP = 2;                 // planes per group of loads (4 spill in FP64)
@@ -330,7 +333,7 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
       for (int j = 0; j < P; ++j) {
         const int idx = col + (NP * j * N + k2 + u) * N;
         gl[u][j] = Gt[idx];
-        fl[u][j] = Fc[idx];
+        fl[u][j] = Fc[fcol + (NP * j * (N / 2) + k2 + u) * N];
       }
     }
 #pragma unroll
@@ -348,10 +351,11 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
 
 template <typename R, int N, int P, int S = 0>
 __device__ __forceinline__ void gather_col_s(int s, const cx<R>* __restrict__ Gt,
-                                             const cx<R>* __restrict__ Fc, int col,
+                                             const cx<R>* __restrict__ Fc, int col, int fcol,
                                              int partner4, cx<R> tw, cx<R> (&v)[N]) {
-  if (s == S) gather_col<R, N, P, S>(Gt, Fc, col, partner4, tw, v);
-  else if constexpr (S + 1 < P) gather_col_s<R, N, P, S + 1>(s, Gt, Fc, col, partner4, tw, v);
+  if (s == S) gather_col<R, N, P, S>(Gt, Fc, col, fcol, partner4, tw, v);
+  else if constexpr (S + 1 < P)
+    gather_col_s<R, N, P, S + 1>(s, Gt, Fc, col, fcol, partner4, tw, v);
 }
 
 template <typename R, int N, int P, bool LOSS>
@@ -368,7 +372,8 @@ __device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt
   const int z0 = opaque_zero();
   const double* fp = fc + z0;
   cx<R> v[N];
-  gather_col_s<R, N, P>(s, Gt, Fc, a * N * N + bq + z0, partner4, tw, v);
+  gather_col_s<R, N, P>(s, Gt, Fc, a * N * N + bq + z0, a * N * N / 2 + bq + z0, partner4, tw,
+                        v);
   fft_line<N, +1>(v);                   // along z: (k', k1 = bq, z)
   R* pl = buf + a * N * LD;             // this half-wave's plane
   __syncthreads();                      // every wave is done reading the previous term
@@ -444,7 +449,7 @@ void k_fused_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
   // wave 0 whose planes 0 and NP/2 are their own mirrors
   const int partner4 = 4 * ((w == 0 ? h : 1 - h) * 32 + bm);
   const cx<R> tw = unit_root<N, R>((a * s) % N);
-  const cx<R>* Fc = Fh + (int64_t)cc * n;
+  const cx<R>* Fc = Fh + (int64_t)cc * (n / 2);   // half-space spectrum
   const int64_t base = off[cell0 + cc];
   const double* fc = f + base;
   double acc[P][NP];
@@ -475,12 +480,14 @@ void k_fused_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
 template <typename R, int N, int P, bool COL>
 static hipError_t launch_fused_t(const ChunkArgs& a, hipStream_t st) {
   cx<R>* W = (cx<R>*)a.W;
-  hipError_t e = launch_fwd(a, st);
+  // the column form reads only the half space k2 < N/2 of the spectrum
+  constexpr int KZ = COL ? N / 2 : N;
+  hipError_t e = launch_fwd(a, st, COL);
   if (e != hipSuccess) return e;
   if (a.ev) (void)hipEventRecord(a.ev[1], st);
-  const int64_t pencils = (int64_t)a.ncells * N * N;
-  hipLaunchKernelGGL((k_fwdx<R, N>), dim3((unsigned)((pencils + 63) / 64)), dim3(64), 0, st, W,
-                     a.ncells);
+  const int64_t pencils = (int64_t)a.ncells * KZ * N;
+  hipLaunchKernelGGL((k_fwdx<R, N, KZ>), dim3((unsigned)((pencils + 63) / 64)), dim3(64), 0, st,
+                     W, a.ncells);
   if (a.ev) (void)hipEventRecord(a.ev[2], st);
   const dim3 grid((unsigned)((a.ncells + 7) / 8 * 8 * P)), block(fused_threads<N, P>());
   if constexpr (COL)

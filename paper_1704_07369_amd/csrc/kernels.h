@@ -31,9 +31,10 @@ struct ChunkArgs {
 
 hipError_t launch_chunk(const ChunkArgs& a, hipStream_t s);
 
-// k_fwd only (3D, N in 16, 24, 32): W[cell][x][k2][k1] = 2D transform of
-// every x slab; records a.ev[0] before it when a.ev is set.
-hipError_t launch_fwd(const ChunkArgs& a, hipStream_t s);
+// k_fwd only (3D, N in 16, 24, 32, 64): W[cell][x][k2][k1] = 2D transform of
+// every x slab; half (N = 32 only): only k2 < N/2, W[cell][x][k2 < N/2][k1].
+// Records a.ev[0] before it when a.ev is set.
+hipError_t launch_fwd(const ChunkArgs& a, hipStream_t s, bool half = false);
 
 // Per-cell reductions (fixed order, deterministic).  Any output may be null.
 //   full:    [cell][EC_NMON]

@@ -34,7 +34,8 @@ constexpr int slabs_per_block() {
 // ---------------------------------------------------------------------------
 // forward 2D transform of each (cell, x) slab
 // ---------------------------------------------------------------------------
-template <typename R, int N0, int N>
+// KZ < N keeps only the outputs k2 < KZ (W[cell][x][k2 < KZ][k1])
+template <typename R, int N0, int N, int KZ = N>
 __global__ __launch_bounds__(slabs_per_block<N>() * N) void k_fwd(
     const double* __restrict__ f, const int64_t* __restrict__ off, int64_t cell0,
     int ncells, cx<R>* __restrict__ W) {
@@ -59,9 +60,9 @@ __global__ __launch_bounds__(slabs_per_block<N>() * N) void k_fwd(
   for (int z = 0; z < N; ++z) v[z] = lds[s][i][z];
   fft_line<N, -1>(v);                       // along z: (k1 = i, k2)
   if (active) {
-    cx<R>* Wc = W + ((int64_t)cc * N0 + x) * N * N;
+    cx<R>* Wc = W + ((int64_t)cc * N0 + x) * KZ * N;
 #pragma unroll
-    for (int k2 = 0; k2 < N; ++k2) Wc[k2 * N + i] = v[k2];
+    for (int k2 = 0; k2 < KZ; ++k2) Wc[k2 * N + i] = v[k2];
   }
 }
 
@@ -213,31 +214,31 @@ static hipError_t launch_chunk_r(const ChunkArgs& a, hipStream_t st) {
 #undef EFM_CASE
 }
 
-template <typename R, int N>
+template <typename R, int N, int KZ>
 static hipError_t launch_fwd_t(const ChunkArgs& a, hipStream_t st) {
   constexpr int SPB = slabs_per_block<N>();
   const int64_t slabs = (int64_t)a.ncells * N;
   const int slab_blocks = (int)((slabs + SPB - 1) / SPB);
   if (a.ev) (void)hipEventRecord(a.ev[0], st);
-  hipLaunchKernelGGL((k_fwd<R, N, N>), dim3(slab_blocks), dim3(SPB * N), 0, st, a.f, a.off,
+  hipLaunchKernelGGL((k_fwd<R, N, N, KZ>), dim3(slab_blocks), dim3(SPB * N), 0, st, a.f, a.off,
                      a.cell0, a.ncells, (cx<R>*)a.W);
   return hipGetLastError();
 }
 
 template <typename R>
-static hipError_t launch_fwd_r(const ChunkArgs& a, hipStream_t st) {
+static hipError_t launch_fwd_r(const ChunkArgs& a, bool half, hipStream_t st) {
   switch (a.N) {
-    case 16: return launch_fwd_t<R, 16>(a, st);
-    case 24: return launch_fwd_t<R, 24>(a, st);
-    case 32: return launch_fwd_t<R, 32>(a, st);
-    case 64: return launch_fwd_t<R, 64>(a, st);
+    case 16: return launch_fwd_t<R, 16, 16>(a, st);
+    case 24: return launch_fwd_t<R, 24, 24>(a, st);
+    case 32: return half ? launch_fwd_t<R, 32, 16>(a, st) : launch_fwd_t<R, 32, 32>(a, st);
+    case 64: return launch_fwd_t<R, 64, 64>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_fwd(const ChunkArgs& a, hipStream_t st) {
-  if (a.d != 3) return hipErrorInvalidValue;
-  return a.precision != 0 ? launch_fwd_r<float>(a, st) : launch_fwd_r<double>(a, st);
+hipError_t launch_fwd(const ChunkArgs& a, hipStream_t st, bool half) {
+  if (a.d != 3 || (half && a.N != 32)) return hipErrorInvalidValue;
+  return a.precision != 0 ? launch_fwd_r<float>(a, half, st) : launch_fwd_r<double>(a, half, st);
 }
 
 hipError_t launch_chunk(const ChunkArgs& a, hipStream_t st) {
