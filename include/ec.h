@@ -129,8 +129,9 @@ typedef struct ec_batch ec_batch;
 /*
  * ec_setup_kernel -- build the FP64 tables of one (N, d, L, kernel, M) and
  * upload them to the current HIP device.
- *   N      points per axis; supported: d = 3: 8, 12, 16, 24, 32, 64;
- *          d = 2: 8, 12, 16, 24, 32, 64, 128, 256, 512 (N >= 64: FP64 only).
+ *   N      points per axis; supported: d = 3: 8, 12, 16, 24, 32, 64, 128
+ *          (128: FP64 only, lines schedule); d = 2: 8, 12, 16, 24, 32, 64, 128,
+ *          256, 512 (N >= 64: FP64 only).
  *   d      2 or 3.
  *   L      half-width of the velocity box (> 0).
  *   M      number of products in the gain: d = 2: samples theta_t = t pi/(2M)
@@ -199,6 +200,10 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
  * accumulates the gain in FP64 registers, so no per-term intermediate touches
  * device memory; splits: N = 16: 1, 2; N = 24: 2, 3; N = 32: 2, 4 (at 32^3
  * the term volume is held in registers, one column or line per thread).
+ * EC_SCHED_LINES (3D, N = 64, 128; FP64): every axis by line FFTs in LDS,
+ * one term at a time through device memory (per cell of a pass: spectrum and
+ * term volume, complex FP64, and an FP64 accumulator, 40 N^3 bytes); the only
+ * schedule of 128^3 grids, whose plans are FP64 only.
  * 0 for cells_per_pass or term_groups selects the default (chosen from the
  * cache size); the autotuner picks measured values.  A new batch starts with
  * the fused schedule where it exists and the group has at least 32 cells,
@@ -209,6 +214,7 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
 #define EC_SCHED_PIPELINE 0
 #define EC_SCHED_TWO_PASS 1
 #define EC_SCHED_FUSED 2
+#define EC_SCHED_LINES 3
 int ec_batch_set_schedule(ec_batch* batch, int group, int mode, int cells_per_pass,
                           int term_groups);
 int ec_batch_get_schedule(const ec_batch* batch, int group, int* mode, int* cells_per_pass,

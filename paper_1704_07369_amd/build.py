@@ -22,7 +22,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function"]
-SOURCES = ["kernels.hip", "pipe.hip", "mfma.hip", "fused.hip", "large2d.hip", "fno.hip", "api.cpp", "surrogate.cpp", "plan.cpp"]
+SOURCES = ["kernels.hip", "pipe.hip", "mfma.hip", "fused.hip", "large2d.hip", "large3d.hip", "fno.hip",
+           "api.cpp", "surrogate.cpp", "plan.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -15,6 +15,7 @@
 #include "../../include/ec.h"
 #include "fused.h"
 #include "large2d.h"
+#include "large3d.h"
 #include "internal.h"
 #include "kernels.h"
 #include "pipe.h"
@@ -67,6 +68,13 @@ struct ec_plan {
 
 namespace {
 bool is_large2d(const HostTables& T) { return T.d == 2 && large2d_supported(T.N); }
+// 3D grids whose only schedule is the lines schedule (128^3)
+bool is_large3d_only(const HostTables& T) { return T.d == 3 && T.N == 128; }
+// plans that run in FP64 only (no FP32 copy of their tables is kept)
+bool fp64_only(const HostTables& T) { return is_large2d(T) || is_large3d_only(T); }
+bool lines_supported(const HostTables& T, int precision) {
+  return T.d == 3 && large3d_supported(T.N) && precision == EC_FP64;
+}
 }  // namespace
 
 struct BatchGroup {
@@ -120,6 +128,8 @@ void default_schedule(BatchGroup& g, int precision) {
   const HostTables& T = g.plan->host;
   const int64_t count = std::max<int64_t>(1, g.count);
   if (precision == EC_BF16X3) g.mode = EC_SCHED_TWO_PASS;   // the MFMA x pass is a separate kernel
+  if (is_large3d_only(T)) g.mode = EC_SCHED_LINES;
+  if (g.mode == EC_SCHED_LINES && !lines_supported(T, precision)) g.mode = EC_SCHED_TWO_PASS;
   if (g.mode == EC_SCHED_FUSED && (T.d != 3 || fused_default_split(T.N, precision) == 0))
     g.mode = EC_SCHED_TWO_PASS;
   if (g.mode == EC_SCHED_PIPELINE && T.N > 32) g.mode = EC_SCHED_TWO_PASS;   // register lines <= 32
@@ -138,6 +148,13 @@ void default_schedule(BatchGroup& g, int precision) {
     const int64_t slab_blocks = ((int64_t)g.chunk * T.N + spb - 1) / spb;
     int G = (int)std::max<int64_t>(1, (1024 + slab_blocks - 1) / slab_blocks);
     g.G = std::min(G, std::min(T.J, 16));
+  } else if (T.d == 3 && g.mode == EC_SCHED_LINES) {
+    // per cell: spectrum and term volume (complex FP64) and the FP64
+    // accumulator, 40 N^3 bytes; keep a pass under ~4 GiB of workspace
+    const double per_cell = 40.0 * (double)T.n;
+    const int64_t c = (int64_t)std::max(1.0, std::floor(4.0 * 1073741824.0 / per_cell));
+    g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, count));
+    g.G = 1;
   } else if (is_large2d(T)) {
     // per cell N^2 (spectrum) + J N^2 (per-term columns) complex FP64: keep a
     // pass under ~2 GiB of workspace
@@ -159,6 +176,7 @@ void default_schedule(BatchGroup& g, int precision) {
 
 bool use_pipe(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_PIPELINE; }
 bool use_fused(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_FUSED; }
+bool use_lines(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_LINES; }
 bool fp32_tables(int precision) { return precision != EC_FP64; }
 
 size_t group_ws_bytes(const BatchGroup& g, int precision) {
@@ -166,6 +184,7 @@ size_t group_ws_bytes(const BatchGroup& g, int precision) {
   const size_t cs = csize(precision);
   const size_t n = (size_t)T.n;
   if (use_fused(g)) return (size_t)g.chunk * n * cs + 256;
+  if (use_lines(g)) return (size_t)g.chunk * n * 16 + 256 + (size_t)g.chunk * n * 24 + 256;
   if (use_pipe(g))
     return 2 * ((size_t)g.chunk * n * cs + (size_t)g.chunk * T.J * n * cs +
                 (size_t)g.G * g.chunk * n * 8 + (size_t)g.chunk * n * 8) + 8 * 256;
@@ -241,6 +260,8 @@ int run_group_two_pass(ec_batch* b, int gi, const double* f, double* Q, double d
     }
     if (is_large2d(T)) {
       HIPCHK(launch_large2d(a, a.tw, s));
+    } else if (use_lines(g)) {
+      HIPCHK(launch_large3d(a, a.tw, s));
     } else {
       HIPCHK(launch_chunk(a, s));
     }
@@ -396,19 +417,25 @@ int ec_setup_kernel(int N, int d, double L, const ec_kernel* kernel, int M, ec_p
     if (rc) { delete p; return fail(rc, err); }
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(EC_ERR_DEVICE, "no HIP device"); }
     const size_t cnt = p->host.gamma.size();
-    std::vector<float> g32(cnt);
-    for (size_t i = 0; i < cnt; ++i) g32[i] = (float)p->host.gamma[i];
+    const bool with32 = !fp64_only(p->host);   // FP64-only plans keep no FP32 copy
     if (hipMalloc(&p->d_gamma64, cnt * sizeof(double)) != hipSuccess ||
-        hipMalloc(&p->d_gamma32, cnt * sizeof(float)) != hipSuccess) {
+        (with32 && hipMalloc(&p->d_gamma32, cnt * sizeof(float)) != hipSuccess)) {
       ec_plan_destroy(p);
       return fail(EC_ERR_OOM, "plan tables");
     }
-    if (hipMemcpy(p->d_gamma64, p->host.gamma.data(), cnt * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_gamma32, g32.data(), cnt * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(p->d_gamma64, p->host.gamma.data(), cnt * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
       ec_plan_destroy(p);
       return fail(EC_ERR_DEVICE, "upload of plan tables failed");
     }
-    if (is_large2d(p->host)) {
+    if (with32) {
+      std::vector<float> g32(cnt);
+      for (size_t i = 0; i < cnt; ++i) g32[i] = (float)p->host.gamma[i];
+      if (hipMemcpy(p->d_gamma32, g32.data(), cnt * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        ec_plan_destroy(p);
+        return fail(EC_ERR_DEVICE, "upload of plan tables failed");
+      }
+    }
+    if (is_large2d(p->host) || (p->host.d == 3 && large3d_supported(p->host.N))) {
       const std::vector<double> tw = twiddle_table(N);
       if (hipMalloc(&p->d_tw, tw.size() * sizeof(double)) != hipSuccess) {
         ec_plan_destroy(p);
@@ -459,8 +486,8 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
           return fail(EC_ERR_UNSUPPORTED, "split-BF16 transforms need 3D cells with N = 16, 32 or 64");
     if (precision != EC_FP64)
       for (int g = 0; g < n_groups; ++g)
-        if (plans[g] && counts[g] > 0 && is_large2d(plans[g]->host))
-          return fail(EC_ERR_UNSUPPORTED, "2D grids of N >= 64 are FP64 only");
+        if (plans[g] && counts[g] > 0 && fp64_only(plans[g]->host))
+          return fail(EC_ERR_UNSUPPORTED, "2D grids of N >= 64 and 3D grids of N = 128 are FP64 only");
     *out = nullptr;
     auto* b = new ec_batch();
     b->precision = precision;
@@ -545,9 +572,14 @@ int ec_batch_offsets(const ec_batch* b, int64_t* offsets) {
 int ec_batch_set_schedule(ec_batch* b, int group, int mode, int cells_per_pass, int term_groups) {
   return guarded([&]() -> int {
     if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
-    if (mode != EC_SCHED_PIPELINE && mode != EC_SCHED_TWO_PASS && mode != EC_SCHED_FUSED)
+    if (mode != EC_SCHED_PIPELINE && mode != EC_SCHED_TWO_PASS && mode != EC_SCHED_FUSED &&
+        mode != EC_SCHED_LINES)
       return fail(EC_ERR_ARG, "bad mode");
     BatchGroup& g = b->groups[group];
+    if (mode == EC_SCHED_LINES && !lines_supported(g.plan->host, b->precision))
+      return fail(EC_ERR_UNSUPPORTED, "the lines schedule needs 3D cells of N = 64 or 128 in FP64");
+    if (mode != EC_SCHED_LINES && is_large3d_only(g.plan->host))
+      return fail(EC_ERR_UNSUPPORTED, "128^3 grids run only the lines schedule");
     g.mode = mode;
     default_schedule(g, b->precision);
     const int64_t count = std::max<int64_t>(1, g.count);
@@ -573,7 +605,10 @@ int ec_batch_get_schedule(const ec_batch* b, int group, int* mode, int* cells_pe
                           int* term_groups) {
   if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
   const BatchGroup& g = b->groups[group];
-  if (mode) *mode = use_fused(g) ? EC_SCHED_FUSED : (use_pipe(g) ? EC_SCHED_PIPELINE : EC_SCHED_TWO_PASS);
+  if (mode)
+    *mode = use_fused(g) ? EC_SCHED_FUSED
+                         : (use_pipe(g) ? EC_SCHED_PIPELINE
+                                        : (use_lines(g) ? EC_SCHED_LINES : EC_SCHED_TWO_PASS));
   if (cells_per_pass) *cells_per_pass = g.chunk;
   if (term_groups) *term_groups = g.G;
   return EC_OK;
@@ -695,7 +730,15 @@ int ec_autotune(ec_batch* b, const double* f, double* Q, const char* cache_path,
       }
       std::vector<Sched> cand;
       const int64_t count = g.count;
+      if (lines_supported(T, b->precision))
+        for (int c : {1, 4, 16, 64}) {
+          const Sched sl{EC_SCHED_LINES, (int)std::min<int64_t>(c, count), 0};
+          bool dup = false;
+          for (auto& x : cand) dup |= (x.mode == sl.mode && x.chunk == sl.chunk);
+          if (!dup) cand.push_back(sl);
+        }
       for (int c : {16, 32, 64, 128, 256, 1024, 4096}) {
+        if (is_large3d_only(T)) break;
         Sched s{EC_SCHED_TWO_PASS, (int)std::min<int64_t>(c, count), 0};
         bool dup = false;
         for (auto& x : cand) dup |= (x.mode == s.mode && x.chunk == s.chunk);

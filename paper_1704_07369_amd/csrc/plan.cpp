@@ -78,7 +78,7 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 
 bool supported_size(int N, int d) {
   if (N == 8 || N == 12 || N == 16 || N == 24 || N == 32) return true;
-  if (d == 3 && N == 64) return true;                                 // two-pass schedule
+  if (d == 3 && (N == 64 || N == 128)) return true;   // two-pass / lines schedule
   return d == 2 && (N == 64 || N == 128 || N == 256 || N == 512);   // LDS line transforms
 }
 
@@ -224,7 +224,7 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
   if (d != 2 && d != 3) { err = "d must be 2 or 3"; return EC_ERR_ARG; }
   if (N < 4 || M < 1 || !(L > 0.0)) { err = "need N >= 4, M >= 1, L > 0"; return EC_ERR_ARG; }
   if (!supported_size(N, d)) {
-    err = "unsupported N (supported: 8, 12, 16, 24, 32, 3D also 64; 2D also 64 .. 512)";
+    err = "unsupported N (supported: 8, 12, 16, 24, 32, 3D also 64, 128; 2D also 64 .. 512)";
     return EC_ERR_UNSUPPORTED;
   }
   if (truncation != EC_TRUNC_BOX && truncation != EC_TRUNC_BALL) {
