@@ -16,6 +16,7 @@
 #include "fused.h"
 #include "large2d.h"
 #include "large3d.h"
+#include "tables.h"
 #include "internal.h"
 #include "kernels.h"
 #include "pipe.h"
@@ -411,29 +412,25 @@ int ec_setup_kernel(int N, int d, double L, const ec_kernel* kernel, int M, ec_p
     *out = nullptr;
     auto* p = new ec_plan();
     std::string err;
-    int rc = build_tables(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial,
-                          kernel->unfiltered, kernel->truncation, kernel->n_bcos,
-                          kernel->bcos, M, p->host, err);
+    TableSpec spec;
+    int rc = build_spec(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial,
+                        kernel->unfiltered, kernel->truncation, kernel->n_bcos, kernel->bcos, M,
+                        p->host, spec, err);
     if (rc) { delete p; return fail(rc, err); }
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(EC_ERR_DEVICE, "no HIP device"); }
-    const size_t cnt = p->host.gamma.size();
+    // the tables are filled on the device (the same per-mode formulas as the
+    // host fill of ec_host_tables); no host copy is kept
+    const size_t cnt = (size_t)2 * p->host.J * p->host.n;
     const bool with32 = !fp64_only(p->host);   // FP64-only plans keep no FP32 copy
     if (hipMalloc(&p->d_gamma64, cnt * sizeof(double)) != hipSuccess ||
         (with32 && hipMalloc(&p->d_gamma32, cnt * sizeof(float)) != hipSuccess)) {
       ec_plan_destroy(p);
       return fail(EC_ERR_OOM, "plan tables");
     }
-    if (hipMemcpy(p->d_gamma64, p->host.gamma.data(), cnt * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    if (fill_tables_device(spec, (double*)p->d_gamma64, with32 ? (float*)p->d_gamma32 : nullptr) !=
+        hipSuccess) {
       ec_plan_destroy(p);
-      return fail(EC_ERR_DEVICE, "upload of plan tables failed");
-    }
-    if (with32) {
-      std::vector<float> g32(cnt);
-      for (size_t i = 0; i < cnt; ++i) g32[i] = (float)p->host.gamma[i];
-      if (hipMemcpy(p->d_gamma32, g32.data(), cnt * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-        ec_plan_destroy(p);
-        return fail(EC_ERR_DEVICE, "upload of plan tables failed");
-      }
+      return fail(EC_ERR_DEVICE, "device fill of the plan tables failed");
     }
     if (is_large2d(p->host) || (p->host.d == 3 && large3d_supported(p->host.N))) {
       const std::vector<double> tw = twiddle_table(N);
@@ -468,7 +465,8 @@ int ec_plan_terms(const ec_plan* p, int* n_terms) {
 
 int ec_plan_tables(const ec_plan* p, double* gamma) {
   if (!p || !gamma) return fail(EC_ERR_ARG, "null argument");
-  std::memcpy(gamma, p->host.gamma.data(), p->host.gamma.size() * sizeof(double));
+  HIPCHK(hipMemcpy(gamma, p->d_gamma64, (size_t)2 * p->host.J * p->host.n * sizeof(double),
+                   hipMemcpyDeviceToHost));
   return EC_OK;
 }
 

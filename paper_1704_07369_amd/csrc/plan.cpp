@@ -23,6 +23,7 @@
 //                          = 4 pi R J_1(R q)/q,
 //                   B_fast = (Bt/2) sum_t w_t psi_3 Phi over a hemisphere rule.
 #include "plan.h"
+#include "table_math.h"
 
 #include <algorithm>
 #include <cmath>
@@ -100,29 +101,8 @@ std::vector<double> twiddle_table(int N) {
   return t;
 }
 
-static double sinc(double x) {
-  if (std::fabs(x) < 1e-4) {
-    const double x2 = x * x;
-    return 1.0 - x2 / 6.0 + x2 * x2 / 120.0;
-  }
-  return std::sin(x) / x;
-}
-
-static double psi2(double s, double R) { return 2.0 * R * sinc(R * s); }
-
-static double psi3(double s, double R) {
-  const double x = R * s;
-  const double h = sinc(0.5 * x);
-  return 2.0 * R * R * (sinc(x) - 0.5 * h * h);
-}
-
-static double phi3(double q, double R) {
-  const double x = R * q;
-  double j1x;  // J_1(x)/x
-  if (x < 1e-4) j1x = 0.5 - x * x / 16.0;
-  else j1x = std::cyl_bessel_j(1.0, x) / x;
-  return 4.0 * PI * R * R * j1x;
-}
+// The separable kernels' closed forms psi_2, psi_3 and Phi (above) are
+// evaluated per mode by tm_psi2, tm_psi3 and tm_phi3 (table_math.h).
 
 // ---- non-separable kernels (variable hard spheres, 3D Maxwell) ----------------
 // Bt(y, z) = (1/pi) (|y|^2 + |z|^2)^a, a = (gamma - 1)/2, does not factor in
@@ -146,17 +126,7 @@ static double phi3(double q, double R) {
 // removes the square-root endpoint of the disk radius at rho = R.
 struct ChebFn {
   double qmax = 0.0;
-  std::vector<double> c;   // Chebyshev coefficients on [0, qmax]
-  double operator()(double q) const {
-    const double x = qmax > 0.0 ? 2.0 * q / qmax - 1.0 : -1.0;
-    double b1 = 0.0, b2 = 0.0;
-    for (int k = (int)c.size() - 1; k >= 1; --k) {
-      const double b0 = 2.0 * x * b1 - b2 + c[k];
-      b2 = b1;
-      b1 = b0;
-    }
-    return x * b1 - b2 + c[0];
-  }
+  std::vector<double> c;   // Chebyshev coefficients on [0, qmax] (summed by tm_cheb)
 };
 
 // b(x) = sum_i bcos[i] x^i (Horner); b = 1 when nb == 0
@@ -218,9 +188,9 @@ static void hemisphere_split(int M, int& mm, int& mp) {
   mp = M / mm;
 }
 
-int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
-                 int n_radial, int unfiltered, int truncation, int n_bcos, const double* bcos,
-                 int M, HostTables& T, std::string& err) {
+int build_spec(int N, int d, double L, int kind, double gamma_exp, double R, int n_radial,
+               int unfiltered, int truncation, int n_bcos, const double* bcos, int M,
+               HostTables& T, TableSpec& S, std::string& err) {
   if (d != 2 && d != 3) { err = "d must be 2 or 3"; return EC_ERR_ARG; }
   if (N < 4 || M < 1 || !(L > 0.0)) { err = "need N >= 4, M >= 1, L > 0"; return EC_ERR_ARG; }
   if (!supported_size(N, d)) {
@@ -300,7 +270,6 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
 
   const double scale = 1.0 / (double)T.n;   // N^-d
   const double kf = PI / L;
-  T.gamma.assign((size_t)2 * T.J * T.n, 0.0);
   std::vector<double> sig1(N);
   // sigma = 1 gives the unfiltered Fourier collocation method (eq. FCM), the
   // comparison of the positivity study (section 4.2, Fig. 2); for even N the
@@ -341,59 +310,47 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
                                  (int)T.bcos.size()));
   }
 
-  auto fill_slab = [&](int i0) {
-    for (int i2 = 0; i2 < T.n2; ++i2)
-      for (int i1 = 0; i1 < T.n1; ++i1) {
-        const int64_t idx = ((int64_t)i0 * T.n2 + i2) * T.n1 + i1;
-        double kx, ky, kz, sig;
-        if (d == 3) {
-          kx = mode(i0); ky = mode(i1); kz = mode(i2);
-          sig = sig1[i0] * sig1[i1] * sig1[i2];
-        } else {
-          kx = mode(i1); ky = mode(i2); kz = 0.0;
-          sig = sig1[i1] * sig1[i2];
-        }
-        const double k2 = kx * kx + ky * ky + kz * kz;
-        double diag = 0.0;
-        for (int t = 0; t < M; ++t) {
-          const double kd = kx * ex[t] + ky * ey[t] + kz * ez[t];
-          if (radial) {
-            const double q = kf * std::sqrt(std::max(0.0, k2 - kd * kd));
-            for (int j = 0; j < nrad; ++j) {
-              const size_t term = (size_t)t * nrad + j;
-              const double ps = 2.0 * om[j] * rho[j] * std::cos(rho[j] * kf * kd);
-              const double ph = hank[j](q);
-              T.gamma[(term * T.n + idx) * 2 + 0] = scale * wt[t] * sig * ps;
-              T.gamma[(term * T.n + idx) * 2 + 1] = scale * sig * ph;
-              diag += wt[t] * ps * ph;
-            }
-            continue;
-          }
-          double ps, ph;
-          if (d == 2) {
-            ps = psi2(kf * kd, R);
-            ph = psi2(kf * (kx * px[t] + ky * py[t]), R);
-          } else {
-            ps = psi3(kf * kd, R);
-            ph = phi3(kf * std::sqrt(std::max(0.0, k2 - kd * kd)), R);
-          }
-          T.gamma[((size_t)t * T.n + idx) * 2 + 0] = scale * wt[t] * sig * ps;
-          T.gamma[((size_t)t * T.n + idx) * 2 + 1] = scale * sig * ph;
-          diag += wt[t] * ps * ph;
-        }
-        T.gamma[((size_t)T.terms * T.n + idx) * 2 + 0] = scale * sig * sig * diag;
-        T.gamma[((size_t)T.terms * T.n + idx) * 2 + 1] = 0.0;
-      }
-  };
-  // slabs in parallel on the host threads (each writes its own entries)
+  S.N = N; S.d = d; S.M = M; S.nrad = nrad; S.radial = radial;
+  S.n = T.n; S.J = T.J;
+  S.R = R; S.kf = kf; S.scale = scale; S.qmax = 0.0;
+  S.ex = ex; S.ey = ey; S.ez = ez; S.px = px; S.py = py; S.wt = wt;
+  S.rho = rho; S.om = om; S.sig1 = sig1;
+  S.cheb.clear();
+  S.cheb_off.assign(1, 0);
+  for (auto& h : hank) {
+    S.qmax = h.qmax;
+    S.cheb.insert(S.cheb.end(), h.c.begin(), h.c.end());
+    S.cheb_off.push_back((int)S.cheb.size());
+  }
+  return EC_OK;
+}
+
+int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
+                 int n_radial, int unfiltered, int truncation, int n_bcos, const double* bcos,
+                 int M, HostTables& T, std::string& err) {
+  TableSpec S;
+  const int rc = build_spec(N, d, L, kind, gamma_exp, R, n_radial, unfiltered, truncation,
+                            n_bcos, bcos, M, T, S, err);
+  if (rc) return rc;
+  TableView V;
+  V.N = S.N; V.d = S.d; V.M = S.M; V.nrad = S.nrad; V.radial = S.radial ? 1 : 0;
+  V.n = S.n; V.J = S.J; V.R = S.R; V.kf = S.kf; V.scale = S.scale; V.qmax = S.qmax;
+  V.ex = S.ex.data(); V.ey = S.ey.data(); V.ez = S.ez.data();
+  V.px = S.px.data(); V.py = S.py.data(); V.wt = S.wt.data();
+  V.rho = S.rho.data(); V.om = S.om.data();
+  V.cheb = S.cheb.data(); V.cheb_off = S.cheb_off.data(); V.sig1 = S.sig1.data();
+  T.gamma.assign((size_t)2 * T.J * T.n, 0.0);
+  double* g = T.gamma.data();
+  // modes in parallel on the host threads (each writes its own entries)
   const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  if (T.n0 * (int64_t)T.J * T.n2 * T.n1 < 4000000 || nth == 1) {
-    for (int i0 = 0; i0 < T.n0; ++i0) fill_slab(i0);
+  const int64_t n = T.n;
+  if (n * (int64_t)T.J < 4000000 || nth == 1) {
+    for (int64_t idx = 0; idx < n; ++idx) fill_mode(V, idx, g, nullptr);
   } else {
     std::vector<std::thread> pool;
     for (int w = 0; w < nth; ++w)
       pool.emplace_back([&, w]() {
-        for (int i0 = w; i0 < T.n0; i0 += nth) fill_slab(i0);
+        for (int64_t idx = w; idx < n; idx += nth) fill_mode(V, idx, g, nullptr);
       });
     for (auto& th : pool) th.join();
   }

@@ -22,7 +22,28 @@ struct HostTables {
   std::vector<double> gamma;
 };
 
-// Returns 0 or an EC_ERR_* code with a message in err.
+// Inputs of the per-mode table formulas (table_math.h), host arrays.
+struct TableSpec {
+  int N = 0, d = 0, M = 0, nrad = 1;
+  bool radial = false;
+  int64_t n = 0;
+  int J = 0;
+  double R = 0, kf = 0, scale = 0, qmax = 0;
+  std::vector<double> ex, ey, ez, px, py, wt;   // directions, 2D partners, weights (M)
+  std::vector<double> rho, om;                  // radial nodes (nrad)
+  std::vector<double> cheb;                     // Chebyshev coefficients of Phi_j
+  std::vector<int> cheb_off;                    // nrad + 1 offsets into cheb
+  std::vector<double> sig1;                     // 1D filter (N)
+};
+
+// Validates the arguments, fills the metadata of T (not T.gamma) and the
+// inputs S of the per-mode formulas.  Returns 0 or an EC_ERR_* code with a
+// message in err.
+int build_spec(int N, int d, double L, int kind, double gamma_exp, double R, int n_radial,
+               int unfiltered, int truncation, int n_bcos, const double* bcos, int M,
+               HostTables& T, TableSpec& S, std::string& err);
+
+// build_spec, then every mode of T.gamma on the host threads.
 int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
                  int n_radial, int unfiltered, int truncation, int n_bcos, const double* bcos,
                  int M, HostTables& out, std::string& err);

@@ -7,8 +7,8 @@ and an angular factor b(cos theta):
   through the pipelined, fused and two-pass schedules;
 - section 4.2, Example 4, Table 3: one SSP-RK3 step (dt = 0.01) of the library
   from the 3D BKW datum, box T = (3 + sqrt 2) R / 4, R = 6, every row
-  N = 16, 32, 64, 128 (128^3 through the lines schedule; its plan of 1373
-  products takes about a minute of host setup).  Every entry within 0.5 % of
+  N = 16, 32, 64, 128 (128^3 through the lines schedule, its plan of 1373
+  products filled on the device).  Every entry within 0.5 % of
   the printed value (3 significant digits: half a unit of the last digit is
   up to 0.5 % relative), every printed rate to its last digit.  The direction
   and radial rules (M x n_radial = 72 x 12 at 16^3, 128 x 16 at 32^3 and
