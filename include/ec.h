@@ -127,8 +127,11 @@ typedef struct ec_plan ec_plan;
 typedef struct ec_batch ec_batch;
 
 /*
- * ec_setup_kernel -- build the FP64 tables of one (N, d, L, kernel, M) and
- * upload them to the current HIP device.
+ * ec_setup_kernel -- build the tables of one (N, d, L, kernel, M) on the
+ * current HIP device: the quadrature rules, the filter and the radial fits
+ * are computed on the host, the per-mode multipliers (FP64, plus an FP32 copy
+ * for plans that allow FP32 batches) by a kernel on the device; the call
+ * synchronizes the device before it returns.
  *   N      points per axis; supported: d = 3: 8, 12, 16, 24, 32, 64, 128
  *          (128: FP64 only, lines schedule); d = 2: 8, 12, 16, 24, 32, 64, 128,
  *          256, 512 (N >= 64: FP64 only).
@@ -155,7 +158,8 @@ int ec_plan_destroy(ec_plan* plan);
 int ec_plan_terms(const ec_plan* plan, int* n_terms);
 
 /*
- * ec_plan_tables -- host copy of the spectral multipliers, for inspection.
+ * ec_plan_tables -- host copy of the plan's FP64 device tables, for
+ * inspection (a synchronous device-to-host copy).
  * gamma: [M'+1][N^d] complex numbers stored as (re, im) FP64 pairs, modes in
  * FFT index order (index i holds the mode i for i < N/2, i - N otherwise),
  * axes ordered (k0, k2, k1) -- first axis slowest, then the last axis, then
