@@ -10,11 +10,14 @@
 namespace efm {
 
 constexpr int FNO_MAX_LAYERS = 8;
+// blocks per cell of the per-cell reductions (n is a multiple of it)
+constexpr int RED_CHUNKS = 16;
 
 // Device pointers of one forward/backward pass over B cells (all FP32 unless
 // noted).  n = N^3, NM = 4 K^3 kept modes, C channels, L layers.
 struct FnoArgs {
   int N = 0, K = 0, C = 0, L = 0, B = 0;
+  bool store_h = true;                // keep the pre-activations (needed by the backward pass)
   // parameters
   const float* Wl = nullptr;          // [C]
   const float* bl = nullptr;          // [C]
@@ -34,7 +37,6 @@ struct FnoArgs {
   float* u[FNO_MAX_LAYERS + 1] = {};  // [B][C][n]
   float* h[FNO_MAX_LAYERS] = {};      // [B][C][n] pre-activations
   cx<float>* Uh[FNO_MAX_LAYERS] = {}; // [B][NM][C] kept modes of u[l]
-  float* s = nullptr;                 // [B][C][n] spectral branch output
   cx<float>* T = nullptr;             // [B*C][N][2K*K] transform intermediate
   cx<float>* V = nullptr;             // [B][NM][C]
   cx<float>* V2 = nullptr;            // [B][NM][C]
@@ -53,8 +55,9 @@ hipError_t fno_forward(const FnoArgs& a, hipStream_t st);
 hipError_t fno_backward(const FnoArgs& a, hipStream_t st);   // needs a prior forward
 hipError_t fno_adam(float* p, const float* g, float* m, float* v, int64_t np, float lr, float b1,
                     float b2, float eps, int step, hipStream_t st);
+// part: RED_CHUNKS B doubles of scratch
 hipError_t fno_normalize(const double* f, const int64_t* off, int64_t cell0, int n, double hd,
-                         int B, float* Fin, double* mass, hipStream_t st);
+                         int B, double* part, float* Fin, double* mass, hipStream_t st);
 hipError_t fno_target(const double* Q, const int64_t* off, int64_t cell0, int n, int B,
                       const double* mass, float* t, hipStream_t st);
 hipError_t fno_denormalize(const float* y, const double* mass, const int64_t* off, int64_t cell0,

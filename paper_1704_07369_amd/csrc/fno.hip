@@ -41,158 +41,216 @@ __device__ __forceinline__ int kidx(int m) {   // index m in [0, 2K) -> FFT inde
 }
 
 // ---------------------------------------------------------------------------
-// truncated forward transform, slab pass: real u[s][x][y][z] -> T[s][x][ky][kz]
-// one block per (s, x) slab, N threads
+// Transform passes.  Slab passes take SB = 256 / N slabs per 256-thread block
+// (one thread per line, LDS transposes inside each slab); x passes take one
+// cell and a tile of TP = 256 / C pencils of every channel, and move the kept
+// modes Uh[b][mode][c] through LDS so that their global reads and writes are
+// contiguous (channel fastest).
 // ---------------------------------------------------------------------------
+template <int N>
+constexpr int slabs_per_block() { return 256 / N; }
+template <int C>
+constexpr int pens_per_block() { return 256 / C; }
+
+// truncated forward transform, slab pass: real u[s][x][y][z] -> T[s][x][ky][kz]
 template <int N, int K>
-__global__ __launch_bounds__(N) void k_fno_fwd_slab(const float* __restrict__ u,
-                                                    cx<float>* __restrict__ T) {
+__global__ __launch_bounds__(256) void k_fno_fwd_slab(const float* __restrict__ u,
+                                                      cx<float>* __restrict__ T, int64_t nslab) {
   using D = FnoDims<N, K>;
-  __shared__ cx<float> lds[N][K + 1];
-  const int i = threadIdx.x;
-  const int64_t slab = blockIdx.x;                // s * N + x
-  const float* us = u + slab * N * N;
-  cx<float> v[N];
+  constexpr int SB = slabs_per_block<N>();
+  __shared__ cx<float> lds[SB][N][K + 1];
+  const int ls = threadIdx.x / N, i = threadIdx.x % N;
+  const int64_t slab0 = (int64_t)blockIdx.x * SB;
+  if (slab0 + ls < nslab) {                       // thread (ls, i): line y = i of slab ls
+    const float* us = u + (slab0 + ls) * N * N;
+    cx<float> v[N];
 #pragma unroll
-  for (int z = 0; z < N; ++z) v[z] = {us[i * N + z], 0.f};   // thread i: line y = i
-  fft_line<N, -1>(v);
-#pragma unroll
-  for (int kz = 0; kz < K; ++kz) lds[i][kz] = v[kz];
-  __syncthreads();
-  if (i < K) {                                    // thread i: kz column i
-#pragma unroll
-    for (int y = 0; y < N; ++y) v[y] = lds[y][i];
+    for (int z = 0; z < N; ++z) v[z] = {us[i * N + z], 0.f};
     fft_line<N, -1>(v);
-    cx<float>* Ts = T + slab * D::PEN;
 #pragma unroll
-    for (int m = 0; m < D::KY; ++m) Ts[m * K + i] = v[kidx<N, K>(m)];
+    for (int kz = 0; kz < K; ++kz) lds[ls][i][kz] = v[kz];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < SB * K; t += 256) {   // (slab, kz column) items
+    const int l2 = t / K, col = t % K;
+    if (slab0 + l2 >= nslab) continue;
+    cx<float> v[N];
+#pragma unroll
+    for (int y = 0; y < N; ++y) v[y] = lds[l2][y][col];
+    fft_line<N, -1>(v);
+    cx<float>* Ts = T + (slab0 + l2) * D::PEN;
+#pragma unroll
+    for (int m = 0; m < D::KY; ++m) Ts[m * K + col] = v[kidx<N, K>(m)];
   }
 }
 
-// truncated forward transform, x pass: T[s][x][pen] -> Uh[b][mode][c] (s = b*C + c)
+// truncated forward transform, x pass: T[s][x][pen] -> Uh[b][mode][c] (s = b*C + c);
+// grid (pencil tiles, cells)
 template <int N, int K, int C>
-__global__ __launch_bounds__(64) void k_fno_fwd_x(const cx<float>* __restrict__ T, int nsc,
-                                                  cx<float>* __restrict__ Uh) {
+__global__ __launch_bounds__(256) void k_fno_fwd_x(const cx<float>* __restrict__ T,
+                                                   cx<float>* __restrict__ Uh) {
   using D = FnoDims<N, K>;
-  const int64_t gid = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (gid >= (int64_t)nsc * D::PEN) return;
-  const int s = (int)(gid / D::PEN), pen = (int)(gid % D::PEN);
-  const cx<float>* Ts = T + (int64_t)s * N * D::PEN + pen;
-  cx<float> v[N];
+  constexpr int TP = pens_per_block<C>(), LC = C + 1;
+  __shared__ cx<float> buf[D::KY][TP * LC];
+  const int b = blockIdx.y;
+  const int pen0 = blockIdx.x * TP;
+  const int np = min(TP, D::PEN - pen0);
+  const int c = threadIdx.x / TP, p = threadIdx.x % TP;
+  if (p < np) {
+    const cx<float>* Ts = T + ((int64_t)b * C + c) * N * D::PEN + pen0 + p;
+    cx<float> v[N];
 #pragma unroll
-  for (int x = 0; x < N; ++x) v[x] = Ts[(int64_t)x * D::PEN];
-  fft_line<N, -1>(v);
-  const int b = s / C, c = s % C;
+    for (int x = 0; x < N; ++x) v[x] = Ts[(int64_t)x * D::PEN];
+    fft_line<N, -1>(v);
 #pragma unroll
+    for (int mx = 0; mx < D::KY; ++mx) buf[mx][p * LC + c] = v[kidx<N, K>(mx)];
+  }
+  __syncthreads();
   for (int mx = 0; mx < D::KY; ++mx) {
-    const int mode = mx * D::PEN + pen;
-    Uh[((int64_t)b * D::NM + mode) * C + c] = v[kidx<N, K>(mx)];
+    cx<float>* out = Uh + ((int64_t)b * D::NM + mx * D::PEN + pen0) * C;
+    for (int e = threadIdx.x; e < np * C; e += 256) out[e] = buf[mx][(e / C) * LC + e % C];
   }
 }
 
-// truncated inverse transform, x pass: V[b][mode][c] -> T[s][x][pen]
+// truncated inverse transform, x pass: V[b][mode][c] -> T[s][x][pen]; grid (pencil tiles, cells)
 template <int N, int K, int C>
-__global__ __launch_bounds__(64) void k_fno_inv_x(const cx<float>* __restrict__ V, int nsc,
-                                                  cx<float>* __restrict__ T) {
+__global__ __launch_bounds__(256) void k_fno_inv_x(const cx<float>* __restrict__ V,
+                                                   cx<float>* __restrict__ T) {
   using D = FnoDims<N, K>;
-  const int64_t gid = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (gid >= (int64_t)nsc * D::PEN) return;
-  const int s = (int)(gid / D::PEN), pen = (int)(gid % D::PEN);
-  const int b = s / C, c = s % C;
+  constexpr int TP = pens_per_block<C>(), LC = C + 1;
+  __shared__ cx<float> buf[D::KY][TP * LC];
+  const int b = blockIdx.y;
+  const int pen0 = blockIdx.x * TP;
+  const int np = min(TP, D::PEN - pen0);
+  for (int mx = 0; mx < D::KY; ++mx) {
+    const cx<float>* in = V + ((int64_t)b * D::NM + mx * D::PEN + pen0) * C;
+    for (int e = threadIdx.x; e < np * C; e += 256) buf[mx][(e / C) * LC + e % C] = in[e];
+  }
+  __syncthreads();
+  const int c = threadIdx.x / TP, p = threadIdx.x % TP;
+  if (p >= np) return;
   cx<float> v[N];
 #pragma unroll
   for (int x = 0; x < N; ++x) v[x] = {0.f, 0.f};
 #pragma unroll
-  for (int mx = 0; mx < D::KY; ++mx)
-    v[kidx<N, K>(mx)] = V[((int64_t)b * D::NM + mx * D::PEN + pen) * C + c];
+  for (int mx = 0; mx < D::KY; ++mx) v[kidx<N, K>(mx)] = buf[mx][p * LC + c];
   fft_line<N, +1>(v);
-  cx<float>* Ts = T + (int64_t)s * N * D::PEN + pen;
+  cx<float>* Ts = T + ((int64_t)b * C + c) * N * D::PEN + pen0 + p;
 #pragma unroll
   for (int x = 0; x < N; ++x) Ts[(int64_t)x * D::PEN] = v[x];
 }
 
 // truncated inverse transform, slab pass: T[s][x][ky][kz] -> out[s][x][y][z] = Re(...)
-// (accumulate != 0: out += result)
+// (accumulate != 0: out += result); the real slabs are staged in LDS so that
+// the global stores are contiguous
 template <int N, int K>
-__global__ __launch_bounds__(N) void k_fno_inv_slab(const cx<float>* __restrict__ T,
-                                                    float* __restrict__ out, int accumulate) {
+__global__ __launch_bounds__(256) void k_fno_inv_slab(const cx<float>* __restrict__ T,
+                                                      float* __restrict__ out, int64_t nslab,
+                                                      int accumulate) {
   using D = FnoDims<N, K>;
-  __shared__ cx<float> lds[N][K + 1];
-  const int i = threadIdx.x;
-  const int64_t slab = blockIdx.x;
-  const cx<float>* Ts = T + slab * D::PEN;
-  cx<float> v[N];
-  if (i < K) {                                    // thread i: kz column i
+  constexpr int SB = slabs_per_block<N>(), LN = N + 1;
+  constexpr int CBYTES = (int)sizeof(cx<float>) * SB * N * (K + 1);
+  constexpr int RBYTES = (int)sizeof(float) * SB * N * LN;
+  __shared__ __align__(16) unsigned char raw[CBYTES > RBYTES ? CBYTES : RBYTES];
+  auto lds = reinterpret_cast<cx<float>(*)[N][K + 1]>(raw);   // [SB][N][K + 1] spectrum
+  auto rl = reinterpret_cast<float(*)[N][LN]>(raw);            // [SB][N][N + 1] real slabs
+  const int64_t slab0 = (int64_t)blockIdx.x * SB;
+  for (int t = threadIdx.x; t < SB * K; t += 256) {   // (slab, kz column) items
+    const int l2 = t / K, col = t % K;
+    if (slab0 + l2 >= nslab) continue;
+    const cx<float>* Ts = T + (slab0 + l2) * D::PEN;
+    cx<float> v[N];
 #pragma unroll
     for (int y = 0; y < N; ++y) v[y] = {0.f, 0.f};
 #pragma unroll
-    for (int m = 0; m < D::KY; ++m) v[kidx<N, K>(m)] = Ts[m * K + i];
+    for (int m = 0; m < D::KY; ++m) v[kidx<N, K>(m)] = Ts[m * K + col];
     fft_line<N, +1>(v);
 #pragma unroll
-    for (int y = 0; y < N; ++y) lds[y][i] = v[y];
+    for (int y = 0; y < N; ++y) lds[l2][y][col] = v[y];
   }
   __syncthreads();
+  const int ls = threadIdx.x / N, i = threadIdx.x % N;   // thread (ls, i): line y = i
+  cx<float> v[N];
 #pragma unroll
   for (int z = 0; z < N; ++z) v[z] = {0.f, 0.f};
+  if (slab0 + ls < nslab) {
 #pragma unroll
-  for (int kz = 0; kz < K; ++kz) v[kz] = lds[i][kz];        // thread i: line y = i
-  fft_line<N, +1>(v);
-  float* os = out + slab * N * N;
+    for (int kz = 0; kz < K; ++kz) v[kz] = lds[ls][i][kz];
+    fft_line<N, +1>(v);
+  }
+  __syncthreads();                                // every read of the spectrum is done
 #pragma unroll
-  for (int z = 0; z < N; ++z) {
-    if (accumulate) os[i * N + z] += v[z].x;
-    else os[i * N + z] = v[z].x;
+  for (int z = 0; z < N; ++z) rl[ls][i][z] = v[z].x;
+  __syncthreads();
+  const int64_t nval = (slab0 + SB <= nslab ? SB : nslab - slab0) * N * N;
+  float* os = out + slab0 * N * N;
+  for (int64_t e = threadIdx.x; e < nval; e += 256) {
+    const int sl = (int)(e / (N * N)), y = (int)((e / N) % N), z = (int)(e % N);
+    if (accumulate) os[e] += rl[sl][y][z];
+    else os[e] = rl[sl][y][z];
   }
 }
 
 // ---------------------------------------------------------------------------
 // mode mixing.  forward: Y[b][m][o] = scale sum_i R[m][i][o] X[b][m][i]
 // adjoint:              Y[b][m][i] = scale sum_o conj(R[m][i][o]) X[b][m][o]
-// one thread per (b, m, output channel)
+// one thread per (cell chunk, m, output channel): its C weights are read once
+// and reused for the MIX_CELLS cells of the chunk
 // ---------------------------------------------------------------------------
+constexpr int MIX_CELLS = 32;
+
 template <int C>
 __global__ __launch_bounds__(256) void k_fno_mix2(const cx<float>* __restrict__ R,
                                                   const cx<float>* __restrict__ X, int B, int NM,
                                                   int adjoint, float scale,
                                                   cx<float>* __restrict__ Y) {
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (gid >= (int64_t)B * NM * C) return;
+  const int64_t nmc = (int64_t)NM * C;
+  const int nchunk = (B + MIX_CELLS - 1) / MIX_CELLS;
+  if (gid >= nmc * nchunk) return;
   const int o = (int)(gid % C);
-  const int64_t bm = gid / C;
-  const int m = (int)(bm % NM);
-  const cx<float>* x = X + bm * C;
+  const int m = (int)((gid / C) % NM);
+  const int b0 = (int)(gid / nmc) * MIX_CELLS;
   const cx<float>* Rm = R + (int64_t)m * C * C;
-  cx<float> acc = {0.f, 0.f};
-  if (!adjoint) {
+  cx<float> r[C];
 #pragma unroll
-    for (int i = 0; i < C; ++i) acc = cadd(acc, cmul(Rm[i * C + o], x[i]));
-  } else {
-#pragma unroll
-    for (int oo = 0; oo < C; ++oo) {
-      const cx<float> r = Rm[o * C + oo];        // R[m][i = o][oo]
-      acc = cadd(acc, cmul({r.x, -r.y}, x[oo]));
-    }
+  for (int k = 0; k < C; ++k) {
+    // forward: R[m][k][o] (k = input channel); adjoint: conj R[m][o][k] (k = output channel)
+    const cx<float> w = adjoint ? Rm[o * C + k] : Rm[k * C + o];
+    r[k] = {w.x, adjoint ? -w.y : w.y};
   }
-  Y[gid] = {scale * acc.x, scale * acc.y};
+  const int b1 = min(B, b0 + MIX_CELLS);
+#pragma unroll 4
+  for (int b = b0; b < b1; ++b) {
+    const cx<float>* x = X + ((int64_t)b * NM + m) * C;
+    cx<float> acc = {0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc = cadd(acc, cmul(r[k], x[k]));
+    Y[((int64_t)b * NM + m) * C + o] = {scale * acc.x, scale * acc.y};
+  }
 }
 
-// dR[m][i][o] = scale sum_b G[b][m][o] conj(U[b][m][i]); one thread per (m, i, o)
+// dR[m][i][o] = scale sum_b G[b][m][o] conj(U[b][m][i]); one thread per (m, o),
+// summing every input channel i over the cells in order
 template <int C>
 __global__ __launch_bounds__(256) void k_fno_dR(const cx<float>* __restrict__ G,
                                                 const cx<float>* __restrict__ U, int B, int NM,
                                                 float scale, cx<float>* __restrict__ dR) {
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (gid >= (int64_t)NM * C * C) return;
+  if (gid >= (int64_t)NM * C) return;
   const int o = (int)(gid % C);
-  const int i = (int)((gid / C) % C);
-  const int64_t m = gid / (C * C);
-  cx<float> acc = {0.f, 0.f};
+  const int64_t m = gid / C;
+  cx<float> acc[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) acc[i] = {0.f, 0.f};
   for (int b = 0; b < B; ++b) {
     const cx<float> g = G[((int64_t)b * NM + m) * C + o];
-    const cx<float> uu = U[((int64_t)b * NM + m) * C + i];
-    acc = cadd(acc, cmul(g, {uu.x, -uu.y}));
+    const cx<float>* ub = U + ((int64_t)b * NM + m) * C;
+#pragma unroll
+    for (int i = 0; i < C; ++i) acc[i] = cadd(acc[i], cmul(g, {ub[i].x, -ub[i].y}));
   }
-  dR[gid] = {scale * acc.x, scale * acc.y};
+#pragma unroll
+  for (int i = 0; i < C; ++i) dR[(m * C + i) * C + o] = {scale * acc[i].x, scale * acc[i].y};
 }
 
 // ---------------------------------------------------------------------------
@@ -219,27 +277,62 @@ __global__ __launch_bounds__(256) void k_fno_lift(const float* __restrict__ Fin,
   for (int c = 0; c < C; ++c) u0[(b * C + c) * n + r] = Wl[c] * f + bl[c];
 }
 
-// h[b][o][r] = sum_i W[o][i] u[b][i][r] + bias[o] + s[b][o][r]; uo = gelu(h) or h
-template <int C>
-__global__ __launch_bounds__(256) void k_fno_pointwise(const float* __restrict__ u,
-                                                       const float* __restrict__ s, int B, int n,
-                                                       const float* __restrict__ W,
-                                                       const float* __restrict__ bias,
-                                                       int act, float* __restrict__ h,
-                                                       float* __restrict__ uo) {
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (gid >= (int64_t)B * n) return;
-  const int64_t b = gid / n, r = gid % n;
-  float in[C];
+// Forward layer tail, fused: the inverse slab pass of the spectral branch for
+// the slab x of every channel of cell b (grid (x, b), C N threads), then
+// h = W u + bias + s, uo = GELU(h) (or h) at the slab's points, so that the
+// spectral branch s never goes through global memory.  h is stored only when
+// it is non-null (the backward pass needs it).
+template <int N, int K, int C>
+__global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
+    const cx<float>* __restrict__ T, const float* __restrict__ u, const float* __restrict__ W,
+    const float* __restrict__ bias, int act, float* __restrict__ h, float* __restrict__ uo) {
+  using D = FnoDims<N, K>;
+  constexpr int NT = C * N, LN = N + 1, n = D::n;
+  constexpr int CBYTES = (int)sizeof(cx<float>) * C * N * (K + 1);
+  constexpr int RBYTES = (int)sizeof(float) * C * N * LN;
+  __shared__ __align__(16) unsigned char raw[CBYTES > RBYTES ? CBYTES : RBYTES];
+  auto lds = reinterpret_cast<cx<float>(*)[N][K + 1]>(raw);   // [C][N][K + 1] spectrum
+  auto rl = reinterpret_cast<float(*)[N][LN]>(raw);            // [C][N][N + 1] branch s
+  const int x = blockIdx.x;
+  const int64_t b = blockIdx.y;
+  for (int t = threadIdx.x; t < C * K; t += NT) {   // (channel, kz column) items
+    const int c = t / K, col = t % K;
+    const cx<float>* Ts = T + ((b * C + c) * N + x) * D::PEN;
+    cx<float> v[N];
 #pragma unroll
-  for (int i = 0; i < C; ++i) in[i] = u[(b * C + i) * n + r];
+    for (int y = 0; y < N; ++y) v[y] = {0.f, 0.f};
 #pragma unroll
-  for (int o = 0; o < C; ++o) {
-    float acc = bias[o] + s[(b * C + o) * n + r];
+    for (int m = 0; m < D::KY; ++m) v[kidx<N, K>(m)] = Ts[m * K + col];
+    fft_line<N, +1>(v);
 #pragma unroll
-    for (int i = 0; i < C; ++i) acc += W[o * C + i] * in[i];
-    h[(b * C + o) * n + r] = acc;
-    uo[(b * C + o) * n + r] = act ? gelu(acc) : acc;
+    for (int y = 0; y < N; ++y) lds[c][y][col] = v[y];
+  }
+  __syncthreads();
+  const int c = threadIdx.x / N, i = threadIdx.x % N;   // thread (c, i): line y = i
+  cx<float> v[N];
+#pragma unroll
+  for (int z = 0; z < N; ++z) v[z] = {0.f, 0.f};
+#pragma unroll
+  for (int kz = 0; kz < K; ++kz) v[kz] = lds[c][i][kz];
+  fft_line<N, +1>(v);
+  __syncthreads();                                // every read of the spectrum is done
+#pragma unroll
+  for (int z = 0; z < N; ++z) rl[c][i][z] = v[z].x;
+  __syncthreads();
+  for (int q = threadIdx.x; q < N * N; q += NT) {   // points (y, z) of the slab
+    const int y = q / N, z = q % N;
+    const int64_t r = (int64_t)x * N * N + q;
+    float in[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) in[k] = u[(b * C + k) * n + r];
+#pragma unroll
+    for (int o = 0; o < C; ++o) {
+      float acc = bias[o] + rl[o][y][z];
+#pragma unroll
+      for (int k = 0; k < C; ++k) acc += W[o * C + k] * in[k];
+      if (h) h[(b * C + o) * n + r] = acc;
+      uo[(b * C + o) * n + r] = act ? gelu(acc) : acc;
+    }
   }
 }
 
@@ -334,57 +427,107 @@ __global__ __launch_bounds__(256) void k_fno_pointwise_bwd(const float* __restri
 //   mode 0 (layer):  out[o*C+i] = sum dh[o] u[i], out[C*C + o] = sum dh[o]
 //   mode 1 (lift):   out[c] = sum du0[c] Fin, out[C + c] = sum du0[c]
 //   mode 2 (proj):   out[c] = sum dy u[c], out[C] = sum dy
-// grid: blocks over points; each block writes nvals partials to part[block]
+// Block k sums the points [k npb, (k+1) npb) (npb a multiple of the tile, n
+// too, so a tile never spans two cells): tiles of DG_TILE points of every
+// channel of g (rows G) and a (rows A) are staged in LDS; each thread sums its
+// values over a tile in FP32 and adds the tile sums in FP64.
+// part[block][v], v < nvals.
+constexpr int DG_TILE = 64;
+
 template <int C>
 __global__ __launch_bounds__(256) void k_fno_dense_partial(int mode, const float* __restrict__ a,
                                                            const float* __restrict__ g, int B,
                                                            int n, int npb,
                                                            float* __restrict__ part) {
-  constexpr int NV = C * C + C;
-  __shared__ float red[256];
-  const int64_t p0 = (int64_t)blockIdx.x * npb;
+  constexpr int NV = C * C + C, LT = DG_TILE + 4;   // rows 16-byte aligned, banks staggered
+  static_assert(NV <= 512, "two values per thread");
+  __shared__ __align__(16) float G[C][LT];
+  __shared__ __align__(16) float A[C][LT];
   const int64_t total = (int64_t)B * n;
   const int nvals = mode == 0 ? NV : (mode == 1 ? 2 * C : C + 1);
-  for (int v = 0; v < nvals; ++v) {
-    float acc = 0.f;
-    for (int64_t q = p0 + threadIdx.x; q < p0 + npb && q < total; q += 256) {
-      const int64_t b = q / n, r = q % n;
-      float x;
-      if (mode == 0) {
-        if (v < C * C) {
-          const int o = v / C, i = v % C;
-          x = g[(b * C + o) * n + r] * a[(b * C + i) * n + r];
-        } else {
-          x = g[(b * C + (v - C * C)) * n + r];
-        }
-      } else if (mode == 1) {
-        const int c = v % C;
-        x = g[(b * C + c) * n + r] * (v < C ? a[q] : 1.f);
+  const int gr = mode == 2 ? 1 : C;               // rows of G and A in this mode
+  const int ar = mode == 1 ? 1 : C;
+  // the rows of this thread's values (-1: factor 1)
+  int gi[2], ai[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int v = threadIdx.x + 256 * k;
+    if (mode == 0) {
+      gi[k] = v < C * C ? v / C : v - C * C;
+      ai[k] = v < C * C ? v % C : -1;
+    } else if (mode == 1) {
+      gi[k] = v < C ? v : v - C;
+      ai[k] = v < C ? 0 : -1;
+    } else {
+      gi[k] = 0;
+      ai[k] = v < C ? v : -1;
+    }
+    if (v >= nvals) gi[k] = -1;
+  }
+  double acc[2] = {0.0, 0.0};
+  const int64_t p0 = (int64_t)blockIdx.x * npb;
+  for (int64_t t0 = p0; t0 < p0 + npb && t0 < total; t0 += DG_TILE) {
+    const int64_t b = t0 / n, r0 = t0 % n;
+    __syncthreads();                              // the previous tile is consumed
+    for (int e = threadIdx.x; e < (gr + ar) * DG_TILE; e += 256) {
+      const int row = e / DG_TILE, p = e % DG_TILE;
+      const bool in = t0 + p < total;
+      if (row < gr) {
+        // mode 2: G row 0 = dy[b][r]; otherwise G rows = g[b][c][r]
+        const int64_t gx = mode == 2 ? t0 + p : (b * C + row) * n + r0 + p;
+        G[row][p] = in ? g[gx] : 0.f;
       } else {
-        x = v < C ? g[q] * a[(b * C + v) * n + r] : g[q];
+        const int ra = row - gr;
+        const int64_t ax = mode == 1 ? t0 + p : (b * C + ra) * n + r0 + p;
+        A[ra][p] = in ? a[ax] : 0.f;
       }
-      acc += x;
     }
-    red[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (gi[k] < 0) continue;
+      const float4* gp = reinterpret_cast<const float4*>(G[gi[k]]);
+      float s = 0.f;
+      if (ai[k] >= 0) {
+        const float4* ap = reinterpret_cast<const float4*>(A[ai[k]]);
+#pragma unroll
+        for (int p = 0; p < DG_TILE / 4; ++p) {
+          const float4 x = gp[p], y = ap[p];
+          s += x.x * y.x + x.y * y.y + x.z * y.z + x.w * y.w;
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < DG_TILE / 4; ++p) {
+          const float4 x = gp[p];
+          s += (x.x + x.y) + (x.z + x.w);
+        }
+      }
+      acc[k] += (double)s;
     }
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * NV + v] = red[0];
-    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int v = threadIdx.x + 256 * k;
+    if (v < nvals) part[(int64_t)blockIdx.x * NV + v] = (float)acc[k];
   }
 }
 
+// out[v] = sum_k part[k][v] (FP64, fixed order); one block per value
 template <int C>
-__global__ void k_fno_dense_final(const float* __restrict__ part, int nblocks, int nvals,
-                                  float* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_fno_dense_final(const float* __restrict__ part,
+                                                         int nblocks, float* __restrict__ out) {
   constexpr int NV = C * C + C;
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nvals) return;
+  __shared__ double red[256];
+  const int v = blockIdx.x;
   double acc = 0.0;
-  for (int k = 0; k < nblocks; ++k) acc += part[(int64_t)k * NV + v];
-  out[v] = (float)acc;
+  for (int k = threadIdx.x; k < nblocks; k += 256) acc += part[(int64_t)k * NV + v];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = (float)red[0];
 }
 
 // Adam (bias-corrected), FP32 parameters and moments
@@ -405,27 +548,45 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 // input scale c0 = (2 pi)^{3/2}
 constexpr double kInputScale = 15.749609945653303;
 
-// F~ = c0 F / mass (FP64 cell in the batch layout -> FP32), mass[b] = h^3 sum F
-__global__ __launch_bounds__(256) void k_fno_normalize(const double* __restrict__ f,
-                                                       const int64_t* __restrict__ off,
-                                                       int64_t cell0, int n, double hd,
-                                                       float* __restrict__ Fin,
-                                                       double* __restrict__ mass) {
+// F~ = c0 F / mass (FP64 cell in the batch layout -> FP32), mass[b] = h^3 sum F.
+// Two passes over grid (RED_CHUNKS, B): partial sums of F over each chunk of
+// a cell, then every block adds the partials of its cell in a fixed order and
+// scales its chunk (deterministic; each cell is spread over RED_CHUNKS blocks).
+__global__ __launch_bounds__(256) void k_fno_mass_partial(const double* __restrict__ f,
+                                                          const int64_t* __restrict__ off,
+                                                          int64_t cell0, int n,
+                                                          double* __restrict__ part) {
   __shared__ double red[256];
-  const int b = blockIdx.x;
-  const double* fc = f + off[cell0 + b];
+  const int b = blockIdx.y, j = blockIdx.x;
+  const int chunk = n / RED_CHUNKS;
+  const double* fc = f + off[cell0 + b] + (int64_t)j * chunk;
   double acc = 0.0;
-  for (int r = threadIdx.x; r < n; r += 256) acc += fc[r];
+  for (int r = threadIdx.x; r < chunk; r += 256) acc += fc[r];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  const double ms = hd * red[0];
-  if (threadIdx.x == 0) mass[b] = ms;
+  if (threadIdx.x == 0) part[(int64_t)b * RED_CHUNKS + j] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_fno_normalize(const double* __restrict__ f,
+                                                       const int64_t* __restrict__ off,
+                                                       int64_t cell0, int n, double hd,
+                                                       const double* __restrict__ part,
+                                                       float* __restrict__ Fin,
+                                                       double* __restrict__ mass) {
+  const int b = blockIdx.y, j = blockIdx.x;
+  const int chunk = n / RED_CHUNKS;
+  double sum = 0.0;
+  for (int k = 0; k < RED_CHUNKS; ++k) sum += part[(int64_t)b * RED_CHUNKS + k];
+  const double ms = hd * sum;
+  if (j == 0 && threadIdx.x == 0) mass[b] = ms;
   const double inv = ms > 0.0 ? kInputScale / ms : 0.0;
-  for (int r = threadIdx.x; r < n; r += 256) Fin[(int64_t)b * n + r] = (float)(fc[r] * inv);
+  const double* fc = f + off[cell0 + b] + (int64_t)j * chunk;
+  float* out = Fin + (int64_t)b * n + (int64_t)j * chunk;
+  for (int r = threadIdx.x; r < chunk; r += 256) out[r] = (float)(fc[r] * inv);
 }
 
 // target = c0^2 Q / mass^2 (FP64 cell in the batch layout -> FP32)
@@ -455,23 +616,39 @@ __global__ __launch_bounds__(256) void k_fno_denormalize(const float* __restrict
 // ---------------------------------------------------------------------------
 // launchers (sizes fixed per instantiation)
 // ---------------------------------------------------------------------------
+template <int C>
+static unsigned mix_blocks(int B, int NM) {
+  const int64_t nt = (int64_t)((B + MIX_CELLS - 1) / MIX_CELLS) * NM * C;
+  return (unsigned)((nt + 255) / 256);
+}
+
 template <int N, int K, int C>
 struct FnoOps {
   using D = FnoDims<N, K>;
   static hipError_t fwd_transform(const float* u, int nsc, cx<float>* T, cx<float>* Uh,
                                   hipStream_t st) {
-    hipLaunchKernelGGL((k_fno_fwd_slab<N, K>), dim3(nsc * N), dim3(N), 0, st, u, T);
-    const int64_t nt = (int64_t)nsc * D::PEN;
-    hipLaunchKernelGGL((k_fno_fwd_x<N, K, C>), dim3((unsigned)((nt + 63) / 64)), dim3(64), 0, st,
-                       T, nsc, Uh);
+    const int64_t nslab = (int64_t)nsc * N;
+    constexpr int SB = slabs_per_block<N>(), TP = pens_per_block<C>();
+    hipLaunchKernelGGL((k_fno_fwd_slab<N, K>), dim3((unsigned)((nslab + SB - 1) / SB)), dim3(256),
+                       0, st, u, T, nslab);
+    hipLaunchKernelGGL((k_fno_fwd_x<N, K, C>), dim3((D::PEN + TP - 1) / TP, (unsigned)(nsc / C)),
+                       dim3(256), 0, st, T, Uh);
+    return hipGetLastError();
+  }
+  static hipError_t inv_x_pass(const cx<float>* V, int nsc, cx<float>* T, hipStream_t st) {
+    constexpr int TP = pens_per_block<C>();
+    hipLaunchKernelGGL((k_fno_inv_x<N, K, C>), dim3((D::PEN + TP - 1) / TP, (unsigned)(nsc / C)),
+                       dim3(256), 0, st, V, T);
     return hipGetLastError();
   }
   static hipError_t inv_transform(const cx<float>* V, int nsc, cx<float>* T, float* out,
                                   int accumulate, hipStream_t st) {
-    const int64_t nt = (int64_t)nsc * D::PEN;
-    hipLaunchKernelGGL((k_fno_inv_x<N, K, C>), dim3((unsigned)((nt + 63) / 64)), dim3(64), 0, st,
-                       V, nsc, T);
-    hipLaunchKernelGGL((k_fno_inv_slab<N, K>), dim3(nsc * N), dim3(N), 0, st, T, out, accumulate);
+    const int64_t nslab = (int64_t)nsc * N;
+    constexpr int SB = slabs_per_block<N>(), TP = pens_per_block<C>();
+    hipLaunchKernelGGL((k_fno_inv_x<N, K, C>), dim3((D::PEN + TP - 1) / TP, (unsigned)(nsc / C)),
+                       dim3(256), 0, st, V, T);
+    hipLaunchKernelGGL((k_fno_inv_slab<N, K>), dim3((unsigned)((nslab + SB - 1) / SB)), dim3(256),
+                       0, st, T, out, nslab, accumulate);
     return hipGetLastError();
   }
 };
@@ -488,13 +665,13 @@ static hipError_t fno_forward_t(const FnoArgs& a, hipStream_t st) {
   for (int l = 0; l < a.L; ++l) {
     hipError_t e = O::fwd_transform(a.u[l], B * C, a.T, a.Uh[l], st);
     if (e != hipSuccess) return e;
-    const int64_t nbmc = (int64_t)B * D::NM * C;
-    hipLaunchKernelGGL((k_fno_mix2<C>), dim3((unsigned)((nbmc + 255) / 256)), dim3(256), 0, st,
-                       a.R[l], a.Uh[l], B, D::NM, 0, 1.f / (float)n, a.V);
-    e = O::inv_transform(a.V, B * C, a.T, a.s, 0, st);
+    hipLaunchKernelGGL((k_fno_mix2<C>), dim3(mix_blocks<C>(B, D::NM)), dim3(256), 0, st, a.R[l],
+                       a.Uh[l], B, D::NM, 0, 1.f / (float)n, a.V);
+    e = O::inv_x_pass(a.V, B * C, a.T, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fno_pointwise<C>), dim3(gb), dim3(256), 0, st, a.u[l], a.s, B, n,
-                       a.W[l], a.bias[l], l + 1 < a.L ? 1 : 0, a.h[l], a.u[l + 1]);
+    hipLaunchKernelGGL((k_fno_inv_slab_pointwise<N, K, C>), dim3(N, (unsigned)B), dim3(C * N), 0,
+                       st, a.T, a.u[l], a.W[l], a.bias[l], l + 1 < a.L ? 1 : 0,
+                       a.store_h ? a.h[l] : nullptr, a.u[l + 1]);
   }
   hipLaunchKernelGGL((k_fno_proj<C>), dim3(gb), dim3(256), 0, st, a.u[a.L], B, n, a.Wp, a.bp, a.y);
   return hipGetLastError();
@@ -504,12 +681,14 @@ template <int C>
 static hipError_t dense_grad(int mode, const float* act, const float* g, int B, int n, float* part,
                              int part_blocks, float* out, hipStream_t st) {
   const int64_t total = (int64_t)B * n;
-  const int npb = (int)((total + part_blocks - 1) / part_blocks);
+  // points per block: a whole number of tiles
+  const int64_t per = (total + part_blocks - 1) / part_blocks;
+  const int npb = (int)((per + DG_TILE - 1) / DG_TILE * DG_TILE);
   hipLaunchKernelGGL((k_fno_dense_partial<C>), dim3(part_blocks), dim3(256), 0, st, mode, act, g,
                      B, n, npb, part);
   const int nvals = mode == 0 ? C * C + C : (mode == 1 ? 2 * C : C + 1);
-  hipLaunchKernelGGL((k_fno_dense_final<C>), dim3((nvals + 255) / 256), dim3(256), 0, st, part,
-                     part_blocks, nvals, out);
+  hipLaunchKernelGGL((k_fno_dense_final<C>), dim3(nvals), dim3(256), 0, st, part, part_blocks,
+                     out);
   return hipGetLastError();
 }
 
@@ -537,12 +716,11 @@ static hipError_t fno_backward_t(const FnoArgs& args, hipStream_t st) {
     // spectral part: Gv = truncated DFT(dh); dR = sum_b Gv conj(Uh); Gu = conj(R)^T Gv
     e = O::fwd_transform(a.dh, B * C, a.T, a.V, st);
     if (e != hipSuccess) return e;
-    const int64_t nmcc = (int64_t)D::NM * C * C;
-    hipLaunchKernelGGL((k_fno_dR<C>), dim3((unsigned)((nmcc + 255) / 256)), dim3(256), 0, st, a.V,
+    const int64_t nmc = (int64_t)D::NM * C;
+    hipLaunchKernelGGL((k_fno_dR<C>), dim3((unsigned)((nmc + 255) / 256)), dim3(256), 0, st, a.V,
                        a.Uh[l], B, D::NM, 1.f / (float)n, a.gR[l]);
-    const int64_t nbmc = (int64_t)B * D::NM * C;
-    hipLaunchKernelGGL((k_fno_mix2<C>), dim3((unsigned)((nbmc + 255) / 256)), dim3(256), 0, st,
-                       a.R[l], a.V, B, D::NM, 1, 1.f / (float)n, a.V2);
+    hipLaunchKernelGGL((k_fno_mix2<C>), dim3(mix_blocks<C>(B, D::NM)), dim3(256), 0, st, a.R[l],
+                       a.V, B, D::NM, 1, 1.f / (float)n, a.V2);
     // du_in = pointwise part + Re IDFT(scatter(Gu))
     e = O::inv_transform(a.V2, B * C, a.T, a.du2, 1, st);
     if (e != hipSuccess) return e;
@@ -583,8 +761,12 @@ hipError_t fno_adam(float* p, const float* g, float* m, float* v, int64_t np, fl
 }
 
 hipError_t fno_normalize(const double* f, const int64_t* off, int64_t cell0, int n, double hd,
-                         int B, float* Fin, double* mass, hipStream_t st) {
-  hipLaunchKernelGGL(k_fno_normalize, dim3(B), dim3(256), 0, st, f, off, cell0, n, hd, Fin, mass);
+                         int B, double* part, float* Fin, double* mass, hipStream_t st) {
+  if (n % RED_CHUNKS) return hipErrorInvalidValue;
+  const dim3 grid(RED_CHUNKS, (unsigned)B);
+  hipLaunchKernelGGL(k_fno_mass_partial, grid, dim3(256), 0, st, f, off, cell0, n, part);
+  hipLaunchKernelGGL(k_fno_normalize, grid, dim3(256), 0, st, f, off, cell0, n, hd, part, Fin,
+                     mass);
   return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ struct ec_surrogate {
   FnoArgs a;
   float* d_Fin = nullptr;
   double* d_mass = nullptr;
+  double* d_red = nullptr;      // [max_batch][RED_CHUNKS][6] partial sums of the reductions
   double* d_screen = nullptr;   // [cells][4]: P, mass, momentum, energy residual
   int32_t* d_flag = nullptr;
   double* d_fc = nullptr;       // compact fallback cells (owned batch layout)
@@ -120,19 +121,22 @@ __global__ __launch_bounds__(256) void k_screen(const double* __restrict__ f,
 // never moves the prediction farther from it in the 2-norm.  Before
 // projecting, the raw prediction's residuals |sum Q| / sum|Q|,
 // |sum Q v| / (L sum|Q|) and |sum Q |v|^2| / (3 L^2 sum|Q|) go to
-// out[c*4 + 1..3] for the screen.  One block per cell of cells
-// cell0 .. cell0 + gridDim.x - 1.
-__global__ __launch_bounds__(256) void k_project(double* __restrict__ Q,
-                                                 const int64_t* __restrict__ off, int64_t cell0,
-                                                 int N, double L, double* __restrict__ out) {
-  __shared__ double red[6][256];
-  __shared__ double mean;
-  const int64_t c = cell0 + blockIdx.x;
-  double* qc = Q + off[c];
-  const int n = N * N * N;
+// out[c*4 + 1..3] for the screen.  Grid (RED_CHUNKS, cells cell0 ..): the
+// first kernel writes six partial sums per chunk, the second adds them in a
+// fixed order and projects its chunk.
+constexpr int NMOM = 6;
+
+__global__ __launch_bounds__(256) void k_project_partial(const double* __restrict__ Q,
+                                                         const int64_t* __restrict__ off,
+                                                         int64_t cell0, int N, double L,
+                                                         double* __restrict__ part) {
+  __shared__ double red[NMOM][256];
+  const int b = blockIdx.y, j = blockIdx.x;
+  const int n = N * N * N, chunk = n / RED_CHUNKS;
+  const double* qc = Q + off[cell0 + b];
   const double h = 2.0 * L / N;
-  double a[6] = {0, 0, 0, 0, 0, 0};
-  for (int r = threadIdx.x; r < n; r += 256) {
+  double a[NMOM] = {0, 0, 0, 0, 0, 0};
+  for (int r = j * chunk + threadIdx.x; r < (j + 1) * chunk; r += 256) {
     const int ix = r / (N * N), iy = (r / N) % N, iz = r % N;
     const double vx = -L + ix * h, vy = -L + iy * h, vz = -L + iz * h;
     const double q = qc[r];
@@ -144,25 +148,39 @@ __global__ __launch_bounds__(256) void k_project(double* __restrict__ Q,
     a[5] += fabs(q);
   }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = a[k];
+  for (int k = 0; k < NMOM; ++k) red[k][threadIdx.x] = a[k];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
 #pragma unroll
-      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      for (int k = 0; k < NMOM; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const double sabs = red[5][0] > 0.0 ? red[5][0] : 1e-300;
+  if (threadIdx.x < NMOM)
+    part[((int64_t)b * RED_CHUNKS + j) * NMOM + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_project(double* __restrict__ Q,
+                                                 const int64_t* __restrict__ off, int64_t cell0,
+                                                 int N, double L, const double* __restrict__ part,
+                                                 double* __restrict__ out) {
+  const int b = blockIdx.y, j = blockIdx.x;
+  const int n = N * N * N, chunk = n / RED_CHUNKS;
+  double m[NMOM] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < RED_CHUNKS; ++k)
+#pragma unroll
+    for (int q = 0; q < NMOM; ++q) m[q] += part[((int64_t)b * RED_CHUNKS + k) * NMOM + q];
+  const int64_t c = cell0 + b;
+  if (j == 0 && threadIdx.x == 0) {
+    const double sabs = m[5] > 0.0 ? m[5] : 1e-300;
     double* o = out + c * 4;
-    o[1] = fabs(red[0][0]) / sabs;
-    o[2] = sqrt(red[1][0] * red[1][0] + red[2][0] * red[2][0] + red[3][0] * red[3][0]) / (sabs * L);
-    o[3] = fabs(red[4][0]) / (3.0 * L * L * sabs);
-    mean = red[0][0] / n;
+    o[1] = fabs(m[0]) / sabs;
+    o[2] = sqrt(m[1] * m[1] + m[2] * m[2] + m[3] * m[3]) / (sabs * L);
+    o[3] = fabs(m[4]) / (3.0 * L * L * sabs);
   }
-  __syncthreads();
-  const double m = mean;
-  for (int r = threadIdx.x; r < n; r += 256) qc[r] -= m;
+  const double mean = m[0] / n;
+  double* qc = Q + off[c];
+  for (int r = j * chunk + threadIdx.x; r < (j + 1) * chunk; r += 256) qc[r] -= mean;
 }
 
 // gather cells idx[j] of (f, off) into the compact layout (cell j at j * n)
@@ -211,15 +229,19 @@ int forward_batch_cells(ec_surrogate* s, const ec_batch* batch, const double* f,
                         int64_t cell0, int B, hipStream_t st) {
   const double L = plan_L(batch_group_plan(batch, 0));
   const double h = 2.0 * L / s->N;
-  SCHK(fno_normalize(f, batch_offsets_dev(batch), cell0, (int)s->n, h * h * h, B, s->d_Fin,
-                     s->d_mass, st));
+  SCHK(fno_normalize(f, batch_offsets_dev(batch), cell0, (int)s->n, h * h * h, B, s->d_red,
+                     s->d_Fin, s->d_mass, st));
   FnoArgs a = s->a;
   a.B = B;
   a.Fin = s->d_Fin;
+  a.store_h = false;
   SCHK(fno_forward(a, st));
   SCHK(fno_denormalize(a.y, s->d_mass, batch_offsets_dev(batch), cell0, (int)s->n, B, Q, st));
-  hipLaunchKernelGGL(k_project, dim3((unsigned)B), dim3(256), 0, st, Q, batch_offsets_dev(batch),
-                     cell0, s->N, L, s->d_screen);
+  const dim3 grid(RED_CHUNKS, (unsigned)B);
+  hipLaunchKernelGGL(k_project_partial, grid, dim3(256), 0, st, Q, batch_offsets_dev(batch), cell0,
+                     s->N, L, s->d_red);
+  hipLaunchKernelGGL(k_project, grid, dim3(256), 0, st, Q, batch_offsets_dev(batch), cell0, s->N, L,
+                     s->d_red, s->d_screen);
   SCHK(hipGetLastError());
   return EC_OK;
 }
@@ -295,7 +317,6 @@ int ec_surrogate_create(int N, int modes, int channels, int layers, uint64_t see
       a.h[l] = (float*)A(act);
       a.Uh[l] = (cx<float>*)A(mod);
     }
-    a.s = (float*)A(act);
     a.T = (cx<float>*)A(T);
     a.V = (cx<float>*)A(mod);
     a.V2 = (cx<float>*)A(mod);
@@ -305,10 +326,11 @@ int ec_surrogate_create(int N, int modes, int channels, int layers, uint64_t see
     a.du2 = (float*)A(act);
     a.dh = (float*)A(act);
     a.loss_b = (double*)A((size_t)B * sizeof(double));
-    a.part_blocks = 512;
+    a.part_blocks = 1024;
     a.part = (float*)A((size_t)a.part_blocks * (C * C + C) * sizeof(float));
     s->d_Fin = (float*)A((size_t)B * s->n * sizeof(float));
     s->d_mass = (double*)A((size_t)B * sizeof(double));
+    s->d_red = (double*)A((size_t)B * RED_CHUNKS * NMOM * sizeof(double));
     if (!ok) { ec_surrogate_destroy(s); return set_error(EC_ERR_OOM, "surrogate buffers"); }
     bind_params(s);
     if (hipMemcpy(s->d_p, p.data(), P, hipMemcpyHostToDevice) != hipSuccess ||
@@ -370,6 +392,7 @@ int ec_surrogate_forward(ec_surrogate* s, const float* Fin, float* y, int B, voi
     FnoArgs a = s->a;
     a.B = B;
     a.Fin = Fin;
+    a.store_h = false;
     SCHK(fno_forward(a, st));
     SCHK(hipMemcpyAsync(y, a.y, (size_t)B * s->n * sizeof(float), hipMemcpyDeviceToDevice, st));
     return EC_OK;
@@ -417,8 +440,8 @@ int ec_surrogate_prepare(ec_surrogate* s, const ec_batch* batch, const double* f
     hipStream_t st = (hipStream_t)stream;
     const double L = plan_L(batch_group_plan(batch, 0));
     const double h = 2.0 * L / s->N;
-    SCHK(fno_normalize(f, batch_offsets_dev(batch), cell0, (int)s->n, h * h * h, B, Fin,
-                       s->d_mass, st));
+    SCHK(fno_normalize(f, batch_offsets_dev(batch), cell0, (int)s->n, h * h * h, B, s->d_red,
+                       Fin, s->d_mass, st));
     if (Q && target)
       SCHK(fno_target(Q, batch_offsets_dev(batch), cell0, (int)s->n, B, s->d_mass, target, st));
     return EC_OK;
