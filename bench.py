@@ -469,6 +469,17 @@ def main():
                          "roofline": roofline(profb, flops, PEAK_FP32, "bf16x3")}
     if t1_64 is not None:
         out["single_cell"] = {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6}
+    # the device as it runs: vector FMA throughput measured by ec_valu_probe,
+    # beside the published peaks that `roofline.peak` uses
+    log("bench: vector-ALU probe")
+    meas64 = E.ec_valu_probe(E.EC_FP64)
+    out["roofline"]["measured_peak"] = round(meas64, 2)
+    out["roofline"]["frac_of_measured"] = round(out["roofline"]["achieved"] / meas64, 4)
+    if ev32 is not None:
+        meas32 = E.ec_valu_probe(E.EC_FP32)
+        r32 = out["fp32"]["roofline"]
+        r32["measured_peak_unpacked"] = round(meas32, 2)
+        r32["frac_of_measured_unpacked"] = round(r32["achieved"] / meas32, 4)
     if not args.skip_relax:
         log("bench: mixed-N relaxation leg (200 graph-replayed FE steps)")
         out["relaxation"] = relaxation_leg(E, torch)

@@ -316,6 +316,18 @@ int ec_profile_read(ec_batch* batch, double* ms, int64_t* launches, int64_t* cel
  */
 int ec_copy(const double* src, double* dst, int64_t n, void* hip_stream);
 
+/*
+ * ec_valu_probe -- measured vector-ALU throughput of the current device, for
+ * rooflines against the device as it runs: 8192 blocks x 256 threads, each
+ * with 16 independent fused multiply-add chains of 2048 steps (2 flops per
+ * step), two warm-up launches, then the fastest of five launches timed with
+ * HIP events on hip_stream; the call synchronizes on them.  precision: EC_FP64 or
+ * EC_FP32 (FP32 arithmetic is unpacked in this library, so its rate is not
+ * the packed-FP32 peak).  *tflops receives TFLOP/s.  Allocates and frees 8
+ * bytes of device memory.
+ */
+int ec_valu_probe(int precision, double* tflops, void* hip_stream);
+
 /* ---- learned surrogate ---------------------------------------------------
  * A Fourier neural operator that predicts c0^2 Q / mass^2 from c0 F / mass
  * on the N^3 grid (Q is quadratic in F; c0 = (2 pi)^{3/2} puts the peak of a

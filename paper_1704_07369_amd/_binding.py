@@ -66,6 +66,7 @@ _SIGS = {
     "ec_batch_get_schedule": ([_vp, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
                                ctypes.POINTER(_c_int)], _c_int),
     "ec_copy": ([_vp, _vp, _c_i64, _vp], _c_int),
+    "ec_valu_probe": ([_c_int, ctypes.POINTER(_c_double), _vp], _c_int),
     "ec_autotune": ([_vp, _vp, _vp, ctypes.c_char_p, _c_int, _vp], _c_int),
     "ec_surrogate_create": ([_c_int, _c_int, _c_int, _c_int, ctypes.c_uint64, _c_int,
                              ctypes.POINTER(_vp)], _c_int),
@@ -272,6 +273,12 @@ def ec_profile_read(batch, n_groups):
 
 def ec_copy(src, dst, n, stream=None):
     return _check(lib().ec_copy(_ptr(src), _ptr(dst), n, _stream(stream)))
+
+
+def ec_valu_probe(precision=EC_FP64, stream=None):
+    t = _c_double()
+    _check(lib().ec_valu_probe(precision, ctypes.byref(t), _stream(stream)))
+    return t.value
 
 
 def ec_autotune(batch, f, Q, cache_path=None, flags=0, stream=None):

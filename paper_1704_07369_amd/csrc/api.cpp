@@ -782,6 +782,46 @@ int ec_copy(const double* src, double* dst, int64_t n, void* stream) {
   return EC_OK;
 }
 
+int ec_valu_probe(int precision, double* tflops, void* stream) {
+  return guarded([&]() -> int {
+    if (!tflops || (precision != EC_FP64 && precision != EC_FP32))
+      return fail(EC_ERR_ARG, "bad probe arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const int blocks = 8192, iters = 2048;
+    void* sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (sink) (void)hipFree(sink);
+    };
+    if (hipMalloc(&sink, sizeof(double)) != hipSuccess) return fail(EC_ERR_OOM, "probe sink");
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      cleanup();
+      return fail(EC_ERR_DEVICE, "probe events");
+    }
+    // two warm-up launches, then the fastest of five timed ones (the clock
+    // settles under load)
+    hipError_t e = launch_valu_probe(precision, blocks, iters, sink, st);
+    if (e == hipSuccess) e = launch_valu_probe(precision, blocks, iters, sink, st);
+    float ms = 0.f;
+    for (int rep = 0; rep < 5 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(e0, st);
+      if (e == hipSuccess) e = launch_valu_probe(precision, blocks, iters, sink, st);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (e == hipSuccess && (rep == 0 || t < ms)) ms = t;
+    }
+    cleanup();
+    if (e != hipSuccess) return fail(EC_ERR_DEVICE, hipGetErrorString(e));
+    const double flops = 2.0 * blocks * 256.0 * iters * valu_probe_chains();
+    *tflops = ms > 0.f ? flops / (ms * 1e-3) / 1e12 : 0.0;
+    return EC_OK;
+  });
+}
+
 int ec_profile(ec_batch* b, int enable) {
   if (!b) return fail(EC_ERR_ARG, "batch is null");
   b->profiling = enable != 0;

@@ -49,6 +49,10 @@ hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
                            int64_t step_stride, const int* step_cap, hipStream_t s);
 
 hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s);
+// blocks x 256 threads, each valu_probe_chains() FMA chains of iters steps;
+// precision 0: FP64, 1: FP32; sink: one element of device memory
+hipError_t launch_valu_probe(int precision, int blocks, int iters, void* sink, hipStream_t s);
+int valu_probe_chains();
 // out = a x + b y over the n points of each of the first ncells cells
 hipError_t launch_axpby_cells(const double* x, const double* y, double* out, double a, double b,
                               const int64_t* off, const int* cell_n, int64_t ncells,

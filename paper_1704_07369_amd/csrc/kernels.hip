@@ -345,6 +345,39 @@ hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Vector-ALU throughput probe: every thread runs VP_CHAINS independent FMA
+// chains of `iters` steps (2 flops each).  x, y come in at run time and the
+// result is stored only in a case that does not occur for the values used, so
+// the chains are neither folded nor removed.
+constexpr int VP_CHAINS = 16;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_valu_probe(R x, R y, int iters, R* __restrict__ sink) {
+  R a[VP_CHAINS];
+#pragma unroll
+  for (int k = 0; k < VP_CHAINS; ++k) a[k] = (R)(threadIdx.x + k);
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int k = 0; k < VP_CHAINS; ++k) a[k] = fma(a[k], x, y);
+  }
+  R s = 0;
+#pragma unroll
+  for (int k = 0; k < VP_CHAINS; ++k) s += a[k];
+  if (s == (R)-1.25e30) sink[0] = s;
+}
+
+hipError_t launch_valu_probe(int precision, int blocks, int iters, void* sink, hipStream_t s) {
+  if (precision == 0)
+    hipLaunchKernelGGL(k_valu_probe<double>, dim3(blocks), dim3(256), 0, s, 0.999999, 1e-7, iters,
+                       (double*)sink);
+  else
+    hipLaunchKernelGGL(k_valu_probe<float>, dim3(blocks), dim3(256), 0, s, 0.999999f, 1e-7f, iters,
+                       (float*)sink);
+  return hipGetLastError();
+}
+
+int valu_probe_chains() { return VP_CHAINS; }
+
 // out = a x + b y over the n points of every cell (one block per cell; out may
 // alias x or y: each point is read and written by one thread)
 __global__ __launch_bounds__(256) void k_axpby_cells(const double* x, const double* y, double* out,
