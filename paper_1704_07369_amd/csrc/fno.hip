@@ -52,20 +52,39 @@ constexpr int slabs_per_block() { return 256 / N; }
 template <int C>
 constexpr int pens_per_block() { return 256 / C; }
 
+// The lifted input u0[b][c] = Wl[c] F~[b] + bl[c], formed where it is read
+// (inference never stores u0)
+struct LiftIn {
+  const float* Fin = nullptr;   // [B][n]; null: read the stored activation
+  const float* Wl = nullptr;
+  const float* bl = nullptr;
+};
+
 // truncated forward transform, slab pass: real u[s][x][y][z] -> T[s][x][ky][kz]
+// (lift.Fin set: u = the lifted input, s = b*C + c)
 template <int N, int K>
 __global__ __launch_bounds__(256) void k_fno_fwd_slab(const float* __restrict__ u,
-                                                      cx<float>* __restrict__ T, int64_t nslab) {
+                                                      cx<float>* __restrict__ T, int64_t nslab,
+                                                      LiftIn lift, int C) {
   using D = FnoDims<N, K>;
   constexpr int SB = slabs_per_block<N>();
   __shared__ cx<float> lds[SB][N][K + 1];
   const int ls = threadIdx.x / N, i = threadIdx.x % N;
   const int64_t slab0 = (int64_t)blockIdx.x * SB;
   if (slab0 + ls < nslab) {                       // thread (ls, i): line y = i of slab ls
-    const float* us = u + (slab0 + ls) * N * N;
     cx<float> v[N];
+    if (lift.Fin) {
+      const int64_t sc = (slab0 + ls) / N;        // s = b*C + c
+      const int x = (int)((slab0 + ls) % N);
+      const float* fs = lift.Fin + (sc / C) * D::n + (int64_t)x * N * N;
+      const float w = lift.Wl[sc % C], c0 = lift.bl[sc % C];
 #pragma unroll
-    for (int z = 0; z < N; ++z) v[z] = {us[i * N + z], 0.f};
+      for (int z = 0; z < N; ++z) v[z] = {w * fs[i * N + z] + c0, 0.f};
+    } else {
+      const float* us = u + (slab0 + ls) * N * N;
+#pragma unroll
+      for (int z = 0; z < N; ++z) v[z] = {us[i * N + z], 0.f};
+    }
     fft_line<N, -1>(v);
 #pragma unroll
     for (int kz = 0; kz < K; ++kz) lds[ls][i][kz] = v[kz];
@@ -280,12 +299,16 @@ __global__ __launch_bounds__(256) void k_fno_lift(const float* __restrict__ Fin,
 // Forward layer tail, fused: the inverse slab pass of the spectral branch for
 // the slab x of every channel of cell b (grid (x, b), C N threads), then
 // h = W u + bias + s, uo = GELU(h) (or h) at the slab's points, so that the
-// spectral branch s never goes through global memory.  h is stored only when
-// it is non-null (the backward pass needs it).
+// spectral branch s never goes through global memory.  h and uo are stored
+// only when non-null; lift.Fin set: u is the lifted input formed here; yout
+// set (last layer): also the projection yout = sum_c Wp[c] uo[c] + bp; Tnext
+// set: also the next layer's forward slab pass of uo into Tnext.
 template <int N, int K, int C>
 __global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
-    const cx<float>* __restrict__ T, const float* __restrict__ u, const float* __restrict__ W,
-    const float* __restrict__ bias, int act, float* __restrict__ h, float* __restrict__ uo) {
+    const cx<float>* T, const float* __restrict__ u, LiftIn lift,
+    const float* __restrict__ W, const float* __restrict__ bias, int act, float* __restrict__ h,
+    float* __restrict__ uo, const float* __restrict__ Wp, const float* __restrict__ bp,
+    float* __restrict__ yout, cx<float>* Tnext) {   // T and Tnext may alias
   using D = FnoDims<N, K>;
   constexpr int NT = C * N, LN = N + 1, n = D::n;
   constexpr int CBYTES = (int)sizeof(cx<float>) * C * N * (K + 1);
@@ -319,36 +342,53 @@ __global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
 #pragma unroll
   for (int z = 0; z < N; ++z) rl[c][i][z] = v[z].x;
   __syncthreads();
-  for (int q = threadIdx.x; q < N * N; q += NT) {   // points (y, z) of the slab
-    const int y = q / N, z = q % N;
+  for (int q = threadIdx.x; q < N * N; q += NT) {   // points (yy, zz) of the slab
+    const int yy = q / N, zz = q % N;
     const int64_t r = (int64_t)x * N * N + q;
     float in[C];
+    if (lift.Fin) {
+      const float fv = lift.Fin[b * n + r];
 #pragma unroll
-    for (int k = 0; k < C; ++k) in[k] = u[(b * C + k) * n + r];
+      for (int k = 0; k < C; ++k) in[k] = lift.Wl[k] * fv + lift.bl[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < C; ++k) in[k] = u[(b * C + k) * n + r];
+    }
+    float py = yout ? bp[0] : 0.f;
 #pragma unroll
     for (int o = 0; o < C; ++o) {
-      float acc = bias[o] + rl[o][y][z];
+      float acc = bias[o] + rl[o][yy][zz];
 #pragma unroll
       for (int k = 0; k < C; ++k) acc += W[o * C + k] * in[k];
       if (h) h[(b * C + o) * n + r] = acc;
-      uo[(b * C + o) * n + r] = act ? gelu(acc) : acc;
+      const float out = act ? gelu(acc) : acc;
+      if (uo) uo[(b * C + o) * n + r] = out;
+      if (yout) py += Wp[o] * out;               // the projection sum_c Wp[c] u[c] + bp
+      if (Tnext) rl[o][yy][zz] = out;            // this thread's own entries of s
     }
+    if (yout) yout[b * n + r] = py;
   }
-}
-
-// y[b][r] = sum_c Wp[c] u[b][c][r] + bp
-template <int C>
-__global__ __launch_bounds__(256) void k_fno_proj(const float* __restrict__ u, int B, int n,
-                                                  const float* __restrict__ Wp,
-                                                  const float* __restrict__ bp,
-                                                  float* __restrict__ y) {
-  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (gid >= (int64_t)B * n) return;
-  const int64_t b = gid / n, r = gid % n;
-  float acc = bp[0];
+  if (!Tnext) return;
+  // the next layer's forward slab pass of the slab x of every channel, from
+  // the outputs held in LDS; Tnext may be T itself (this block's slabs only)
+  __syncthreads();
 #pragma unroll
-  for (int c = 0; c < C; ++c) acc += Wp[c] * u[(b * C + c) * n + r];
-  y[gid] = acc;
+  for (int z = 0; z < N; ++z) v[z] = {rl[c][i][z], 0.f};   // thread (c, i): line y = i
+  fft_line<N, -1>(v);
+  __syncthreads();                                // every read of the outputs is done
+#pragma unroll
+  for (int kz = 0; kz < K; ++kz) lds[c][i][kz] = v[kz];
+  __syncthreads();
+  for (int t = threadIdx.x; t < C * K; t += NT) {   // (channel, kz column) items
+    const int cc = t / K, col = t % K;
+    cx<float> w[N];
+#pragma unroll
+    for (int y = 0; y < N; ++y) w[y] = lds[cc][y][col];
+    fft_line<N, -1>(w);
+    cx<float>* Ts = Tnext + ((b * C + cc) * N + x) * D::PEN;
+#pragma unroll
+    for (int m = 0; m < D::KY; ++m) Ts[m * K + col] = w[kidx<N, K>(m)];
+  }
 }
 
 // per-sample relative squared error and its gradient:
@@ -626,11 +666,17 @@ template <int N, int K, int C>
 struct FnoOps {
   using D = FnoDims<N, K>;
   static hipError_t fwd_transform(const float* u, int nsc, cx<float>* T, cx<float>* Uh,
-                                  hipStream_t st) {
+                                  hipStream_t st, LiftIn lift = LiftIn()) {
     const int64_t nslab = (int64_t)nsc * N;
     constexpr int SB = slabs_per_block<N>(), TP = pens_per_block<C>();
     hipLaunchKernelGGL((k_fno_fwd_slab<N, K>), dim3((unsigned)((nslab + SB - 1) / SB)), dim3(256),
-                       0, st, u, T, nslab);
+                       0, st, u, T, nslab, lift, C);
+    hipLaunchKernelGGL((k_fno_fwd_x<N, K, C>), dim3((D::PEN + TP - 1) / TP, (unsigned)(nsc / C)),
+                       dim3(256), 0, st, T, Uh);
+    return hipGetLastError();
+  }
+  static hipError_t fwd_x_pass(const cx<float>* T, int nsc, cx<float>* Uh, hipStream_t st) {
+    constexpr int TP = pens_per_block<C>();
     hipLaunchKernelGGL((k_fno_fwd_x<N, K, C>), dim3((D::PEN + TP - 1) / TP, (unsigned)(nsc / C)),
                        dim3(256), 0, st, T, Uh);
     return hipGetLastError();
@@ -661,19 +707,34 @@ static hipError_t fno_forward_t(const FnoArgs& a, hipStream_t st) {
   const int n = D::n;
   const int64_t bn = (int64_t)B * n;
   const unsigned gb = (unsigned)((bn + 255) / 256);
-  hipLaunchKernelGGL((k_fno_lift<C>), dim3(gb), dim3(256), 0, st, a.Fin, B, n, a.Wl, a.bl, a.u[0]);
+  // training keeps every activation for the backward pass; inference forms the
+  // lifted input where it is read and stores neither u0 nor the last layer's u
+  const bool keep = a.store_h;
+  LiftIn lift;
+  if (keep) {
+    hipLaunchKernelGGL((k_fno_lift<C>), dim3(gb), dim3(256), 0, st, a.Fin, B, n, a.Wl, a.bl,
+                       a.u[0]);
+  } else {
+    lift.Fin = a.Fin;
+    lift.Wl = a.Wl;
+    lift.bl = a.bl;
+  }
   for (int l = 0; l < a.L; ++l) {
-    hipError_t e = O::fwd_transform(a.u[l], B * C, a.T, a.Uh[l], st);
+    const LiftIn li = l == 0 ? lift : LiftIn();
+    const bool last = l + 1 == a.L;
+    // the slab pass of layers l > 0 ran in the previous layer's last kernel
+    hipError_t e = l == 0 ? O::fwd_transform(a.u[l], B * C, a.T, a.Uh[l], st, li)
+                          : O::fwd_x_pass(a.T, B * C, a.Uh[l], st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fno_mix2<C>), dim3(mix_blocks<C>(B, D::NM)), dim3(256), 0, st, a.R[l],
                        a.Uh[l], B, D::NM, 0, 1.f / (float)n, a.V);
     e = O::inv_x_pass(a.V, B * C, a.T, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fno_inv_slab_pointwise<N, K, C>), dim3(N, (unsigned)B), dim3(C * N), 0,
-                       st, a.T, a.u[l], a.W[l], a.bias[l], l + 1 < a.L ? 1 : 0,
-                       a.store_h ? a.h[l] : nullptr, a.u[l + 1]);
+                       st, a.T, a.u[l], li, a.W[l], a.bias[l], last ? 0 : 1,
+                       keep ? a.h[l] : nullptr, keep || !last ? a.u[l + 1] : nullptr, a.Wp, a.bp,
+                       last ? a.y : nullptr, last ? nullptr : a.T);
   }
-  hipLaunchKernelGGL((k_fno_proj<C>), dim3(gb), dim3(256), 0, st, a.u[a.L], B, n, a.Wp, a.bp, a.y);
   return hipGetLastError();
 }
 
