@@ -105,8 +105,10 @@ __device__ __forceinline__ void gather_store(const cx<R> (&g)[P], const cx<R> (&
   constexpr int LD = N + 1;
   cx<R> SA = {(R)0, (R)0}, SB = {(R)0, (R)0};
   accum_roots<P, S>(g, fv, SA, SB);
-  vol[(a * N + kk) * LD + bq] = cmul(tw, cx<R>{SA.x - SB.y, SA.y + SB.x});
-  if (kk > 0) vol[(am * N + (N - kk)) * LD + bm] = cmul(twc, cx<R>{SA.x + SB.y, SB.x - SA.y});
+  const cx<R> zp = {SA.x - SB.y, SA.y + SB.x}, zm = {SA.x + SB.y, SB.x - SA.y};
+  // s = 0: the twiddle is exp(0) = 1
+  vol[(a * N + kk) * LD + bq] = S == 0 ? zp : cmul(tw, zp);
+  if (kk > 0) vol[(am * N + (N - kk)) * LD + bm] = S == 0 ? zm : cmul(twc, zm);
 }
 
 template <typename R, int N, int P, int C, int S>
@@ -341,8 +343,10 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
       const int kk = k2 + u;
       cx<R> SA = {(R)0, (R)0}, SB = {(R)0, (R)0};
       accum_roots<P, S>(gl[u], fl[u], SA, SB);
-      v[kk] = cmul(tw, cx<R>{SA.x - SB.y, SA.y + SB.x});
-      if (kk > 0) v[N - kk] = lane_read(cmul(twc, cx<R>{SA.x + SB.y, SB.x - SA.y}), partner4);
+      const cx<R> zp = {SA.x - SB.y, SA.y + SB.x}, zm = {SA.x + SB.y, SB.x - SA.y};
+      // s = 0: the twiddle is exp(0) = 1
+      v[kk] = S == 0 ? zp : cmul(tw, zp);
+      if (kk > 0) v[N - kk] = lane_read(S == 0 ? zm : cmul(twc, zm), partner4);
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the next group's loads behind this group
   }
