@@ -114,9 +114,9 @@ def sampled_error(E, b, Q, cells, cell_ids, oplan, efm, npts=64):
 # profiles/collide_n32_m32_default_counters.md; keyed by (kernel, precision,
 # cells per launch) and valid for that code only (re-measure after changing it)
 MEASURED_TRAFFIC = {
-    ("k_fused", "f64", 1024): (2 * 2593608 + 262144) * 1024,
-    ("k_fused", "f32", 512): (2 * 623719 + 131072) * 1024,
-    ("k_pencil", "bf16x3", 1024): (2 * 240075 + 8650752) * 1024,
+    ("k_fused", "f64", 1024): (2 * 2705696 + 262144) * 1024,
+    ("k_fused", "f32", 512): (2 * 620835 + 131072) * 1024,
+    ("k_pencil", "bf16x3", 1024): (2 * 236649 + 8650752) * 1024,
 }
 
 
