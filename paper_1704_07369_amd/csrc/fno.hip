@@ -392,17 +392,21 @@ __global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
 }
 
 // per-sample relative squared error and its gradient:
-// loss_b = sum_r (y - t)^2 / (sum_r t^2 + eps);  dy = 2 (y - t) / (B (sum t^2 + eps))
-// one block per sample
-__global__ __launch_bounds__(256) void k_fno_loss(const float* __restrict__ y,
-                                                  const float* __restrict__ t, int B, int n,
-                                                  float* __restrict__ dy, double* __restrict__ loss_b) {
+// loss_b = sum_r (y - t)^2 / (sum_r t^2 + eps);  dy = 2 (y - t) / (B (sum t^2 + eps)).
+// Two passes over grid (RED_CHUNKS, B): sums of (y - t)^2 and t^2 over each
+// chunk of a sample, then every block adds its sample's partials in a fixed
+// order and writes dy over its chunk.  part: 2 RED_CHUNKS B doubles.
+__global__ __launch_bounds__(256) void k_fno_loss_partial(const float* __restrict__ y,
+                                                          const float* __restrict__ t, int n,
+                                                          double* __restrict__ part) {
   __shared__ double red[2][256];
-  const int b = blockIdx.x;
+  const int b = blockIdx.y, j = blockIdx.x;
+  const int chunk = n / RED_CHUNKS;
+  const int64_t base = (int64_t)b * n + (int64_t)j * chunk;
   double se = 0.0, st = 0.0;
-  for (int r = threadIdx.x; r < n; r += 256) {
-    const double e = (double)y[(int64_t)b * n + r] - (double)t[(int64_t)b * n + r];
-    const double tv = t[(int64_t)b * n + r];
+  for (int r = threadIdx.x; r < chunk; r += 256) {
+    const double e = (double)y[base + r] - (double)t[base + r];
+    const double tv = t[base + r];
     se += e * e;
     st += tv * tv;
   }
@@ -416,11 +420,26 @@ __global__ __launch_bounds__(256) void k_fno_loss(const float* __restrict__ y,
     }
     __syncthreads();
   }
-  const double den = red[1][0] + 1e-30;
-  if (threadIdx.x == 0) loss_b[b] = red[0][0] / den;
+  if (threadIdx.x < 2) part[((int64_t)b * RED_CHUNKS + j) * 2 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void k_fno_loss(const float* __restrict__ y,
+                                                  const float* __restrict__ t, int B, int n,
+                                                  const double* __restrict__ part,
+                                                  float* __restrict__ dy,
+                                                  double* __restrict__ loss_b) {
+  const int b = blockIdx.y, j = blockIdx.x;
+  const int chunk = n / RED_CHUNKS;
+  double se = 0.0, st = 0.0;
+  for (int k = 0; k < RED_CHUNKS; ++k) {
+    se += part[((int64_t)b * RED_CHUNKS + k) * 2];
+    st += part[((int64_t)b * RED_CHUNKS + k) * 2 + 1];
+  }
+  const double den = st + 1e-30;
+  if (j == 0 && threadIdx.x == 0) loss_b[b] = se / den;
   const float sc = (float)(2.0 / ((double)B * den));
-  for (int r = threadIdx.x; r < n; r += 256)
-    dy[(int64_t)b * n + r] = sc * (y[(int64_t)b * n + r] - t[(int64_t)b * n + r]);
+  const int64_t base = (int64_t)b * n + (int64_t)j * chunk;
+  for (int r = threadIdx.x; r < chunk; r += 256) dy[base + r] = sc * (y[base + r] - t[base + r]);
 }
 
 // backward of the projection: du[b][c][r] = Wp[c] dy[b][r]
@@ -506,23 +525,41 @@ __global__ __launch_bounds__(256) void k_fno_dense_partial(int mode, const float
   }
   double acc[2] = {0.0, 0.0};
   const int64_t p0 = (int64_t)blockIdx.x * npb;
-  for (int64_t t0 = p0; t0 < p0 + npb && t0 < total; t0 += DG_TILE) {
+  const int64_t p1 = min(p0 + (int64_t)npb, total);
+  // this thread's share of a tile: entries e = threadIdx.x + 256 q of the
+  // (gr + ar) x DG_TILE rows, loaded one tile ahead
+  constexpr int PRE = (2 * C * DG_TILE + 255) / 256;
+  float pre[PRE];
+  auto load_tile = [&](int64_t t0) {
     const int64_t b = t0 / n, r0 = t0 % n;
-    __syncthreads();                              // the previous tile is consumed
-    for (int e = threadIdx.x; e < (gr + ar) * DG_TILE; e += 256) {
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+      const int e = threadIdx.x + 256 * q;
       const int row = e / DG_TILE, p = e % DG_TILE;
-      const bool in = t0 + p < total;
-      if (row < gr) {
-        // mode 2: G row 0 = dy[b][r]; otherwise G rows = g[b][c][r]
-        const int64_t gx = mode == 2 ? t0 + p : (b * C + row) * n + r0 + p;
-        G[row][p] = in ? g[gx] : 0.f;
-      } else {
-        const int ra = row - gr;
-        const int64_t ax = mode == 1 ? t0 + p : (b * C + ra) * n + r0 + p;
-        A[ra][p] = in ? a[ax] : 0.f;
+      float v = 0.f;
+      if (row < gr + ar && t0 + p < total) {
+        if (row < gr) {
+          // mode 2: G row 0 = dy[b][r]; otherwise G rows = g[b][c][r]
+          v = g[mode == 2 ? t0 + p : (b * C + row) * n + r0 + p];
+        } else {
+          v = a[mode == 1 ? t0 + p : (b * C + (row - gr)) * n + r0 + p];
+        }
       }
+      pre[q] = v;
+    }
+  };
+  if (p0 < p1) load_tile(p0);
+  for (int64_t t0 = p0; t0 < p1; t0 += DG_TILE) {
+    __syncthreads();                              // the previous tile is consumed
+#pragma unroll
+    for (int q = 0; q < PRE; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int row = e / DG_TILE, p = e % DG_TILE;
+      if (row < gr) G[row][p] = pre[q];
+      else if (row < gr + ar) A[row - gr][p] = pre[q];
     }
     __syncthreads();
+    if (t0 + DG_TILE < p1) load_tile(t0 + DG_TILE);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (gi[k] < 0) continue;
@@ -764,7 +801,14 @@ static hipError_t fno_backward_t(const FnoArgs& args, hipStream_t st) {
   const unsigned gb = (unsigned)((bn + 255) / 256);
   hipError_t e;
   // loss and projection
-  hipLaunchKernelGGL(k_fno_loss, dim3(B), dim3(256), 0, st, a.y, a.target, B, n, a.dy, a.loss_b);
+  {
+    // the dense-gradient scratch is free until the first dense_grad below
+    double* lp = reinterpret_cast<double*>(a.part);
+    const dim3 grid(RED_CHUNKS, (unsigned)B);
+    hipLaunchKernelGGL(k_fno_loss_partial, grid, dim3(256), 0, st, a.y, a.target, n, lp);
+    hipLaunchKernelGGL(k_fno_loss, grid, dim3(256), 0, st, a.y, a.target, B, n, lp, a.dy,
+                       a.loss_b);
+  }
   e = dense_grad<C>(2, a.u[a.L], a.dy, B, n, a.part, a.part_blocks, a.gWp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fno_proj_bwd<C>), dim3(gb), dim3(256), 0, st, a.dy, B, n, a.Wp, a.du);

@@ -326,7 +326,7 @@ int ec_surrogate_create(int N, int modes, int channels, int layers, uint64_t see
     a.du2 = (float*)A(act);
     a.dh = (float*)A(act);
     a.loss_b = (double*)A((size_t)B * sizeof(double));
-    a.part_blocks = 1024;
+    a.part_blocks = 2048;
     a.part = (float*)A((size_t)a.part_blocks * (C * C + C) * sizeof(float));
     s->d_Fin = (float*)A((size_t)B * s->n * sizeof(float));
     s->d_mass = (double*)A((size_t)B * sizeof(double));
