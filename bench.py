@@ -393,9 +393,9 @@ def main():
                     help="also run ec_copy on a buffer of this size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): cells are independent, "
-              "the multi-GPU split is a design note in DESIGN.md, not a measured path.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): cells are independent "
+              "and would be split across GPUs by cost with no exchange per step, but that "
+              "split is not implemented or measured here.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np  # noqa: F401

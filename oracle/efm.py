@@ -29,8 +29,8 @@ What it computes (citations are to the paper, arXiv 1704.07369):
   the discrete H-functional of Theorem 1;
 * forward Euler and the SSP-RK3 step (section 4.1), BKW closed forms.
 
-Readings of the paper (all fixed by reproducing Table 2 to every printed digit,
-or stated where the paper is silent) are documented in the design doc; in short:
+Readings of the paper (fixed by reproducing Table 2 to every printed digit, or
+chosen where the paper is silent), in short:
 the even-N filter is eq. JacksonFilter2 evaluated with n = N/2; the 2D nodes
 are theta_t = t*pi/(2M), t = 0..2M-1; the 3D nodes are a hemisphere product
 rule (Gauss-Legendre in cos(theta) folded onto [0,1], uniform azimuth).
@@ -652,7 +652,7 @@ def kernel_matrix(plan: Plan, symmetrise: bool = True) -> np.ndarray:
 def G_sigma(plan: Plan, symmetrise: bool = True) -> np.ndarray:
     """G(a, b) = sum_{i,j in K} B^s(i,j) E_{-i}(h a) E_{-j}(h b) on grid index
     differences a, b (section 3.2.1, eq. G and section 3.2.2, eq. tildeG without
-    the 1/N^{2d} factor; see the normalisation reading in the design doc)."""
+    the 1/N^{2d} factor, which the caller applies)."""
     kl = mode_grid(plan.N, plan.d)
     h = plan.h
     idx = np.arange(plan.N)            # index differences a in [0, N), offset a*h
