@@ -143,9 +143,8 @@ __device__ __forceinline__ void gather_term(const cx<R>* __restrict__ Gt,
     for (int u = 0; u < GP; ++u) {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const int idx = ((a + NP * j) * N + k2 + u) * N + bq;
-        gl[u][j] = Gt[idx];
-        fl[u][j] = Fc[idx];
+        gl[u][j] = Gt[((a + NP * j) * N + k2 + u) * N + bq];
+        fl[u][j] = Fc[((a + NP * j) * (N / 2) + k2 + u) * N + bq];   // half-space layout
       }
     }
 #pragma unroll
@@ -229,7 +228,7 @@ __global__ __launch_bounds__(N / P * N) void k_fused(
   const cx<R> tw = unit_root<N, R>((a * s) % N);
   const int am = (NP - a) % NP, bm = (N - bq) % N;   // mirror of (a, bq)
 
-  const cx<R>* Fc = Fh + (int64_t)cc * n;
+  const cx<R>* Fc = Fh + (int64_t)cc * (n / 2);   // half-space spectrum [k0][k2 < N/2][k1]
   const int64_t base = off[cell0 + cc];
   const double* fc = f + base;
   // this thread's half-space inputs of Fh (the first C planes), the same for
@@ -240,7 +239,7 @@ __global__ __launch_bounds__(N / P * N) void k_fused(
 #pragma unroll
   for (int k2 = 0; k2 < C; ++k2) {
 #pragma unroll
-    for (int j = 0; j < P; ++j) fh[k2][j] = Fc[((a + NP * j) * N + k2) * N + bq];
+    for (int j = 0; j < P; ++j) fh[k2][j] = Fc[((a + NP * j) * (N / 2) + k2) * N + bq];
   }
   double acc[P][NP];
   // the loss term (last table entry) first, outside the loop, so that the
@@ -484,9 +483,9 @@ void k_fused_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
 template <typename R, int N, int P, bool COL>
 static hipError_t launch_fused_t(const ChunkArgs& a, hipStream_t st) {
   cx<R>* W = (cx<R>*)a.W;
-  // the column form reads only the half space k2 < N/2 of the spectrum
-  constexpr int KZ = COL ? N / 2 : N;
-  hipError_t e = launch_fwd(a, st, COL);
+  // both forms read only the half space k2 < N/2 of the spectrum
+  constexpr int KZ = N / 2;
+  hipError_t e = launch_fwd(a, st, true);
   if (e != hipSuccess) return e;
   if (a.ev) (void)hipEventRecord(a.ev[1], st);
   const int64_t pencils = (int64_t)a.ncells * KZ * N;

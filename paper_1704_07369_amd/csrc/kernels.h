@@ -32,7 +32,7 @@ struct ChunkArgs {
 hipError_t launch_chunk(const ChunkArgs& a, hipStream_t s);
 
 // k_fwd only (3D, N in 16, 24, 32, 64): W[cell][x][k2][k1] = 2D transform of
-// every x slab; half (N = 32 only): only k2 < N/2, W[cell][x][k2 < N/2][k1].
+// every x slab; half (N = 16, 24, 32): only k2 < N/2, W[cell][x][k2 < N/2][k1].
 // Records a.ev[0] before it when a.ev is set.
 hipError_t launch_fwd(const ChunkArgs& a, hipStream_t s, bool half = false);
 

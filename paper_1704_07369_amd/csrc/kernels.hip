@@ -228,8 +228,8 @@ static hipError_t launch_fwd_t(const ChunkArgs& a, hipStream_t st) {
 template <typename R>
 static hipError_t launch_fwd_r(const ChunkArgs& a, bool half, hipStream_t st) {
   switch (a.N) {
-    case 16: return launch_fwd_t<R, 16, 16>(a, st);
-    case 24: return launch_fwd_t<R, 24, 24>(a, st);
+    case 16: return half ? launch_fwd_t<R, 16, 8>(a, st) : launch_fwd_t<R, 16, 16>(a, st);
+    case 24: return half ? launch_fwd_t<R, 24, 12>(a, st) : launch_fwd_t<R, 24, 24>(a, st);
     case 32: return half ? launch_fwd_t<R, 32, 16>(a, st) : launch_fwd_t<R, 32, 32>(a, st);
     case 64: return launch_fwd_t<R, 64, 64>(a, st);
     default: return hipErrorInvalidValue;
@@ -237,7 +237,7 @@ static hipError_t launch_fwd_r(const ChunkArgs& a, bool half, hipStream_t st) {
 }
 
 hipError_t launch_fwd(const ChunkArgs& a, hipStream_t st, bool half) {
-  if (a.d != 3 || (half && a.N != 32)) return hipErrorInvalidValue;
+  if (a.d != 3 || (half && a.N != 16 && a.N != 24 && a.N != 32)) return hipErrorInvalidValue;
   return a.precision != 0 ? launch_fwd_r<float>(a, half, st) : launch_fwd_r<double>(a, half, st);
 }
 
