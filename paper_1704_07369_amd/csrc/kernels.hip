@@ -103,6 +103,66 @@ __global__ __launch_bounds__(PENCIL_BS) void k_pencil(
   }
 }
 
+// The same x pass for FP64 pencils of N0 = 64, two threads per pencil (a
+// 64-point line of FP64 complex values does not fit in a thread's registers
+// next to the transform's temporaries).  One radix-2 step by decimation in
+// frequency splits every 64-point DFT into two 32-point ones:
+//   X(2m)   = DFT32[v(k) + v(k + 32)](m),
+//   X(2m+1) = DFT32[(v(k) - v(k + 32)) w^k](m),   w = exp(+-2 pi i / 64);
+// thread h of the pair transforms the sequence h and owns the outputs 2m + h.
+constexpr int PAIR_PENCILS = PENCIL_BS / 2;
+
+// the radix-2 step for one k: thread h keeps v(k) + v(k + 32) (h = 0) or
+// (v(k) - v(k + 32)) w^k (h = 1)
+template <int SIGN, typename R>
+__device__ __forceinline__ cx<R> dif2(cx<R> lo, cx<R> hi, int h, int k) {
+  return h ? twiddle<64, SIGN>(csub(lo, hi), k) : cadd(lo, hi);
+}
+
+template <typename R, int N>
+__global__ __launch_bounds__(PENCIL_BS) void k_pencil_pair64(
+    const cx<R>* __restrict__ W, const cx<R>* __restrict__ G, int J, int ncells,
+    cx<R>* __restrict__ Z) {
+  constexpr int N0 = 64;
+  constexpr int P = N * N;
+  __shared__ cx<R> fh[N0][PAIR_PENCILS];
+  const int h = threadIdx.x & 1, lp = threadIdx.x >> 1;
+  const int64_t gid = (int64_t)blockIdx.x * PAIR_PENCILS + lp;
+  const bool active = gid < (int64_t)ncells * P;
+  const int cc = active ? (int)(gid / P) : 0;
+  const int p = active ? (int)(gid % P) : 0;
+  cx<R> u[32];
+  {
+    const cx<R>* Wc = W + (int64_t)cc * N0 * P + p;
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      u[k] = dif2<-1>(Wc[(int64_t)k * P], Wc[(int64_t)(k + 32) * P], h, k);
+  }
+  fft_line<32, -1>(u);                      // along x: Fh(2m + h, p), unnormalised
+#pragma unroll
+  for (int m = 0; m < 32; ++m) fh[2 * m + h][lp] = u[m];
+  __syncthreads();                          // both halves of every pencil are in LDS
+  for (int j = 0; j < J; ++j) {
+    const cx<R>* Gj = G + ((int64_t)j * N0 * P) + p;
+    // groups of 8 k: a group's 16 table loads are in flight together, the
+    // next group's stay behind it (all 64 at once would not fit next to u)
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 8) {
+#pragma unroll
+      for (int k = k0; k < k0 + 8; ++k)
+        u[k] = dif2<+1>(cmul(Gj[(int64_t)k * P], fh[k][lp]),
+                        cmul(Gj[(int64_t)(k + 32) * P], fh[k + 32][lp]), h, k);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    fft_line<32, +1>(u);
+    if (active) {
+      cx<R>* Zj = Z + ((int64_t)cc * J + j) * N0 * P + p;
+#pragma unroll
+      for (int m = 0; m < 32; ++m) Zj[(int64_t)(2 * m + h) * P] = u[m];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // slabs: per term inverse 2D transform, FP64 gain accumulation, loss, combine
 // ---------------------------------------------------------------------------
@@ -177,6 +237,11 @@ static hipError_t launch_chunk_t(const ChunkArgs& a, hipStream_t st) {
     if (a.precision == 2) {
       hipError_t e = launch_pencil_bf16(W, G, a.J, a.ncells, Z, N, st);
       if (e != hipSuccess) return e;
+    } else if constexpr (N0 == 64 && sizeof(R) == 8) {
+      const int64_t pencils = (int64_t)a.ncells * N * N;
+      const int pblocks = (int)((pencils + PAIR_PENCILS - 1) / PAIR_PENCILS);
+      hipLaunchKernelGGL((k_pencil_pair64<R, N>), dim3(pblocks), dim3(PENCIL_BS), 0, st,
+                         W, G, a.J, a.ncells, Z);
     } else {
       const int64_t pencils = (int64_t)a.ncells * N * N;
       const int pblocks = (int)((pencils + PENCIL_BS - 1) / PENCIL_BS);
