@@ -207,18 +207,25 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
  * EC_SCHED_LINES (3D, N = 64, 128; FP64): every axis by line FFTs in LDS,
  * one term at a time through device memory (per cell of a pass: spectrum and
  * term volume, complex FP64, and an FP64 accumulator, 40 N^3 bytes); the only
- * schedule of 128^3 grids, whose plans are FP64 only.
+ * schedule of 128^3 grids, whose plans are FP64 only.  EC_SCHED_TERMS (3D,
+ * N = 32; FP64 and FP32; splits 2, 4): the fused schedule's column kernel
+ * run with one workgroup per (cell, term, residue class), each writing its
+ * term's products to device memory (J N^3 FP64 values per cell of a pass),
+ * then a kernel that sums them per point in the fused kernel's order; for
+ * small batches, whose latency is then about one term's.
  * 0 for cells_per_pass or term_groups selects the default (chosen from the
  * cache size); the autotuner picks measured values.  A new batch starts with
  * the fused schedule where it exists and the group has at least 32 cells,
- * with the pipelined schedule (3D, N <= 32) for smaller groups, and with the
- * two-pass schedule otherwise.  Reallocates the workspace (synchronises
- * the device); call it outside graph capture.
+ * with the term-parallel schedule (32^3) or the pipelined schedule (3D,
+ * N <= 32) for smaller groups, and with the two-pass schedule otherwise.
+ * Reallocates the workspace (synchronises the device); call it outside
+ * graph capture.
  */
 #define EC_SCHED_PIPELINE 0
 #define EC_SCHED_TWO_PASS 1
 #define EC_SCHED_FUSED 2
 #define EC_SCHED_LINES 3
+#define EC_SCHED_TERMS 4
 int ec_batch_set_schedule(ec_batch* batch, int group, int mode, int cells_per_pass,
                           int term_groups);
 int ec_batch_get_schedule(const ec_batch* batch, int group, int* mode, int* cells_per_pass,

@@ -21,7 +21,7 @@ EC_KERNEL_MAXWELL, EC_KERNEL_HARD_SPHERE, EC_KERNEL_VHS = 0, 1, 2
 EC_TRUNC_BOX, EC_TRUNC_BALL = 0, 1
 EC_FP64, EC_FP32, EC_BF16X3 = 0, 1, 2
 EC_NMON = 7
-EC_SCHED_PIPELINE, EC_SCHED_TWO_PASS, EC_SCHED_FUSED, EC_SCHED_LINES = 0, 1, 2, 3
+EC_SCHED_PIPELINE, EC_SCHED_TWO_PASS, EC_SCHED_FUSED, EC_SCHED_LINES, EC_SCHED_TERMS = 0, 1, 2, 3, 4
 EC_PROF_KERNELS = 6
 EC_TUNE_REMEASURE = 1
 PROF_KERNEL_NAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe", "k_fwdx", "k_fused"]

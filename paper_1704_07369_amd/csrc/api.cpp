@@ -134,7 +134,16 @@ void default_schedule(BatchGroup& g, int precision) {
   if (g.mode == EC_SCHED_FUSED && (T.d != 3 || fused_default_split(T.N, precision) == 0))
     g.mode = EC_SCHED_TWO_PASS;
   if (g.mode == EC_SCHED_PIPELINE && T.N > 32) g.mode = EC_SCHED_TWO_PASS;   // register lines <= 32
-  if (T.d == 3 && g.mode == EC_SCHED_FUSED) {
+  if (g.mode == EC_SCHED_TERMS && (T.d != 3 || !terms_supported(T.N, precision, 2)))
+    g.mode = EC_SCHED_PIPELINE;
+  if (T.d == 3 && g.mode == EC_SCHED_TERMS) {
+    // per cell: the half spectrum and J N^3 FP64 term partials; keep a pass
+    // under ~2 GiB of partials
+    const double per_cell = (double)T.J * T.n * 8.0;
+    const int64_t c = (int64_t)std::max(1.0, std::floor(2.0 * 1073741824.0 / per_cell));
+    g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, count));
+    g.G = 2;
+  } else if (T.d == 3 && g.mode == EC_SCHED_FUSED) {
     // one spectrum per cell of workspace; 2048 cells keep >= 2048 workgroups busy
     g.chunk = (int)std::min<int64_t>(2048, count);
     g.G = fused_default_split(T.N, precision);
@@ -178,6 +187,7 @@ void default_schedule(BatchGroup& g, int precision) {
 bool use_pipe(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_PIPELINE; }
 bool use_fused(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_FUSED; }
 bool use_lines(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_LINES; }
+bool use_terms(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_TERMS; }
 bool fp32_tables(int precision) { return precision != EC_FP64; }
 
 size_t group_ws_bytes(const BatchGroup& g, int precision) {
@@ -185,6 +195,7 @@ size_t group_ws_bytes(const BatchGroup& g, int precision) {
   const size_t cs = csize(precision);
   const size_t n = (size_t)T.n;
   if (use_fused(g)) return (size_t)g.chunk * n * cs + 256;
+  if (use_terms(g)) return (size_t)g.chunk * n * cs + 256 + (size_t)g.chunk * T.J * n * 8 + 256;
   if (use_lines(g)) return (size_t)g.chunk * n * 16 + 256 + (size_t)g.chunk * n * 24 + 256;
   if (use_pipe(g))
     return 2 * ((size_t)g.chunk * n * cs + (size_t)g.chunk * T.J * n * cs +
@@ -337,10 +348,40 @@ int run_group_fused(ec_batch* b, int gi, const double* f, double* Q, double dt, 
   return EC_OK;
 }
 
+int run_group_terms(ec_batch* b, int gi, const double* f, double* Q, double dt, hipStream_t s,
+                    bool profile) {
+  const BatchGroup& g = b->groups[gi];
+  const HostTables& T = g.plan->host;
+  const size_t cs = csize(b->precision);
+  char* W = align256((char*)b->d_ws);
+  char* Zp = align256(W + (size_t)g.chunk * T.n * cs);
+  for (int64_t c0 = 0; c0 < g.count; c0 += g.chunk) {
+    ChunkArgs a;
+    a.N = T.N; a.d = T.d; a.precision = b->precision; a.J = T.J;
+    a.gamma = fp32_tables(b->precision) ? g.plan->d_gamma32 : g.plan->d_gamma64;
+    a.W = W; a.Z = Zp;
+    a.f = f; a.Q = Q; a.off = b->d_off;
+    a.cell0 = g.first + c0;
+    a.ncells = (int)std::min<int64_t>(g.chunk, g.count - c0);
+    a.dt = dt;
+    ProfRec rec{};
+    if (profile) {
+      rec.group = gi; rec.ncells = a.ncells; rec.kind = 2;
+      int rc = take_events(b, rec);
+      if (rc) return rc;
+      a.ev = rec.ev;
+    }
+    HIPCHK(launch_terms(a, g.G, s));
+    if (profile) b->prof.push_back(rec);
+  }
+  return EC_OK;
+}
+
 int run_group(ec_batch* b, int gi, const double* f, double* Q, double dt, hipStream_t s,
               bool profile) {
   const BatchGroup& g = b->groups[gi];
   if (use_fused(g)) return run_group_fused(b, gi, f, Q, dt, s, profile);
+  if (use_terms(g)) return run_group_terms(b, gi, f, Q, dt, s, profile);
   if (use_pipe(g)) return run_group_pipe(b, gi, f, Q, dt, s, profile);
   return run_group_two_pass(b, gi, f, Q, dt, s, profile);
 }
@@ -500,9 +541,10 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
       bg.count = counts[g];
       bg.first = cell;
       // the fused schedule runs P workgroups per cell: below a few dozen cells
-      // the pipelined schedule (term groups spread one cell over many
-      // workgroups) fills more CUs; both fall back to two-pass where absent
-      bg.mode = counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_PIPELINE;
+      // the term-parallel form (J P workgroups per cell; N = 32) or else the
+      // pipelined schedule (term groups spread one cell over many workgroups)
+      // fills more CUs; they fall back to two-pass where absent
+      bg.mode = counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_TERMS;
       default_schedule(bg, precision);
       const HostTables& T = plans[g]->host;
       const double hd = std::pow(2.0 * T.L / T.N, T.d);
@@ -571,9 +613,12 @@ int ec_batch_set_schedule(ec_batch* b, int group, int mode, int cells_per_pass, 
   return guarded([&]() -> int {
     if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
     if (mode != EC_SCHED_PIPELINE && mode != EC_SCHED_TWO_PASS && mode != EC_SCHED_FUSED &&
-        mode != EC_SCHED_LINES)
+        mode != EC_SCHED_LINES && mode != EC_SCHED_TERMS)
       return fail(EC_ERR_ARG, "bad mode");
     BatchGroup& g = b->groups[group];
+    if (mode == EC_SCHED_TERMS &&
+        (g.plan->host.d != 3 || !terms_supported(g.plan->host.N, b->precision, 2)))
+      return fail(EC_ERR_UNSUPPORTED, "the term-parallel schedule needs 3D cells of N = 32 in FP64 or FP32");
     if (mode == EC_SCHED_LINES && !lines_supported(g.plan->host, b->precision))
       return fail(EC_ERR_UNSUPPORTED, "the lines schedule needs 3D cells of N = 64 or 128 in FP64");
     if (mode != EC_SCHED_LINES && is_large3d_only(g.plan->host))
@@ -586,6 +631,11 @@ int ec_batch_set_schedule(ec_batch* b, int group, int mode, int cells_per_pass, 
     if (term_groups > 0 && use_fused(g)) {
       if (!fused_supported(g.plan->host.N, b->precision, term_groups))
         return fail(EC_ERR_UNSUPPORTED, "unsupported x split for the fused schedule");
+      g.G = term_groups;
+    }
+    if (term_groups > 0 && use_terms(g)) {
+      if (!terms_supported(g.plan->host.N, b->precision, term_groups))
+        return fail(EC_ERR_UNSUPPORTED, "unsupported x split for the term-parallel schedule");
       g.G = term_groups;
     }
     drop_graph(b);
@@ -604,9 +654,11 @@ int ec_batch_get_schedule(const ec_batch* b, int group, int* mode, int* cells_pe
   if (!b || group < 0 || group >= (int)b->groups.size()) return fail(EC_ERR_ARG, "bad group");
   const BatchGroup& g = b->groups[group];
   if (mode)
-    *mode = use_fused(g) ? EC_SCHED_FUSED
-                         : (use_pipe(g) ? EC_SCHED_PIPELINE
-                                        : (use_lines(g) ? EC_SCHED_LINES : EC_SCHED_TWO_PASS));
+    *mode = use_fused(g)   ? EC_SCHED_FUSED
+            : use_terms(g) ? EC_SCHED_TERMS
+            : use_pipe(g)  ? EC_SCHED_PIPELINE
+            : use_lines(g) ? EC_SCHED_LINES
+                           : EC_SCHED_TWO_PASS;
   if (cells_per_pass) *cells_per_pass = g.chunk;
   if (term_groups) *term_groups = g.G;
   return EC_OK;
@@ -682,6 +734,7 @@ int apply_sched(ec_batch* b, int gi, const Sched& s) {
   if (s.chunk > 0) g.chunk = (int)std::min<int64_t>(s.chunk, count);
   if (s.G > 0 && use_pipe(g)) g.G = std::min(s.G, g.plan->host.J);
   if (s.G > 0 && use_fused(g) && fused_supported(g.plan->host.N, b->precision, s.G)) g.G = s.G;
+  if (s.G > 0 && use_terms(g) && terms_supported(g.plan->host.N, b->precision, s.G)) g.G = s.G;
   return alloc_workspaces(b);
 }
 
@@ -751,6 +804,13 @@ int ec_autotune(ec_batch* b, const double* f, double* Q, const char* cache_path,
               for (auto& x : cand) dup |= (x.mode == sc.mode && x.chunk == sc.chunk && x.G == sc.G);
               if (!dup) cand.push_back(sc);
             }
+      }
+      if (T.d == 3 && terms_supported(T.N, b->precision, 2) && count < 256) {
+        BatchGroup probe = g;
+        probe.mode = EC_SCHED_TERMS;
+        default_schedule(probe, b->precision);
+        for (int P : {2, 4})
+          cand.push_back(Sched{EC_SCHED_TERMS, probe.chunk, P});
       }
       if (T.d == 3 && T.N <= 32) {
         for (int c : {4, 6, 8, 12, 16, 24})

@@ -479,6 +479,107 @@ void k_fused_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
   }
 }
 
+// Term-parallel form of the column kernel for small batches: one workgroup
+// per (cell, term, x residue s) runs that single term (the same run_term_col)
+// and writes its products, or for the loss term -F l, to part[cell][term][n];
+// k_terms_reduce then sums them per point in the fused kernel's order (loss,
+// then the terms in order).  A batch of a few cells fills J P workgroups per
+// cell instead of P, so the latency is about that of one term.
+template <typename R, int N, int P>
+__global__ __launch_bounds__(N / P * N) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_terms_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int J,
+                 const double* f, const int64_t* __restrict__ off, int64_t cell0, int ncells,
+                 double* __restrict__ part) {
+  static_assert(N == 32, "one half-wave per (plane, column) line");
+  constexpr int NP = N / P, T = NP * N, LD = N + 1, n = N * N * N;
+  __shared__ R buf[NP * N * LD];
+  const int blk = blockIdx.x;
+  const int s = (blk / 8) % P;
+  const int cc = (blk / (8 * P)) * 8 + blk % 8;
+  if (cc >= ncells) return;             // whole workgroup
+  const int term = blockIdx.y;
+  const int th = threadIdx.x;
+  const int w = th / 64, h = (th / 32) % 2, bq = th % 32;
+  const int a = h == 0 ? w : (w == 0 ? NP / 2 : NP - w);
+  const int bm = (N - bq) % N;
+  const int partner4 = 4 * ((w == 0 ? h : 1 - h) * 32 + bm);
+  const cx<R> tw = unit_root<N, R>((a * s) % N);
+  const cx<R>* Fc = Fh + (int64_t)cc * (n / 2);
+  const double* fc = f + off[cell0 + cc];
+  double acc[P][NP];
+  if (term == J - 1) {
+    run_term_col<R, N, P, true>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4, tw, buf, fc,
+                                acc);
+  } else {
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) acc[p][q] = 0.0;
+    run_term_col<R, N, P, false>(s, G + (int64_t)term * n, Fc, a, bq, partner4, tw, buf, fc,
+                                 acc);
+  }
+  double* pc = part + ((int64_t)cc * J + term) * n;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int line = th + T * p;
+    const int y = line / N, z = line % N;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) pc[((P * q + s) * N + y) * N + z] = acc[p][q];
+  }
+}
+
+// Q = sum of the term partials in the fused kernel's order (the loss term's
+// -F l first); Euler update when dt != 0
+__global__ __launch_bounds__(256) void k_terms_reduce(const double* __restrict__ part, int J,
+                                                      int n, const double* f,
+                                                      const int64_t* __restrict__ off,
+                                                      int64_t cell0, int ncells, double* Q,
+                                                      double dt) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (int64_t)ncells * n) return;
+  const int64_t cc = gid / n, r = gid % n;
+  const double* pc = part + cc * J * n + r;
+  double acc = pc[(int64_t)(J - 1) * n];
+  for (int t = 0; t < J - 1; ++t) acc += pc[(int64_t)t * n];
+  const int64_t o = off[cell0 + cc] + r;
+  Q[o] = dt == 0.0 ? acc : f[o] + dt * acc;
+}
+
+template <typename R, int P>
+static hipError_t launch_terms_t(const ChunkArgs& a, hipStream_t st) {
+  constexpr int N = 32, KZ = N / 2;
+  cx<R>* W = (cx<R>*)a.W;
+  hipError_t e = launch_fwd(a, st, true);
+  if (e != hipSuccess) return e;
+  if (a.ev) (void)hipEventRecord(a.ev[1], st);
+  const int64_t pencils = (int64_t)a.ncells * KZ * N;
+  hipLaunchKernelGGL((k_fwdx<R, N, KZ>), dim3((unsigned)((pencils + 63) / 64)), dim3(64), 0, st,
+                     W, a.ncells);
+  if (a.ev) (void)hipEventRecord(a.ev[2], st);
+  const dim3 grid((unsigned)((a.ncells + 7) / 8 * 8 * P), (unsigned)a.J);
+  hipLaunchKernelGGL((k_terms_col<R, N, P>), grid, dim3(fused_threads<N, P>()), 0, st,
+                     (const cx<R>*)W, (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0, a.ncells,
+                     (double*)a.Z);
+  const int64_t pts = (int64_t)a.ncells * N * N * N;
+  hipLaunchKernelGGL(k_terms_reduce, dim3((unsigned)((pts + 255) / 256)), dim3(256), 0, st,
+                     (const double*)a.Z, a.J, N * N * N, a.f, a.off, a.cell0, a.ncells, a.Q,
+                     a.dt);
+  if (a.ev) (void)hipEventRecord(a.ev[3], st);
+  return hipGetLastError();
+}
+
+bool terms_supported(int N, int precision, int split) {
+  return N == 32 && precision != 2 && (split == 2 || split == 4);
+}
+
+hipError_t launch_terms(const ChunkArgs& a, int split, hipStream_t st) {
+  if (a.ncells <= 0) return hipSuccess;
+  if (a.d != 3 || !terms_supported(a.N, a.precision, split) || !a.Z) return hipErrorInvalidValue;
+  if (a.precision == 0)
+    return split == 2 ? launch_terms_t<double, 2>(a, st) : launch_terms_t<double, 4>(a, st);
+  return split == 2 ? launch_terms_t<float, 2>(a, st) : launch_terms_t<float, 4>(a, st);
+}
+
 // k_fwd, k_fwdx, then the fused kernel (COL: the column form)
 template <typename R, int N, int P, bool COL>
 static hipError_t launch_fused_t(const ChunkArgs& a, hipStream_t st) {

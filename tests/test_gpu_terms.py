@@ -1,0 +1,86 @@
+"""The term-parallel schedule (EC_SCHED_TERMS, 32^3): one workgroup per
+(cell, term, x residue class) writes its term's products, a second kernel
+sums them per point in the fused kernel's order.
+
+- against the fused schedule on the same inputs: the same sums of the same
+  FP64 products, so agreement to 1e-14 of the gain in FP64 and FP32 (only
+  the contraction of the last product into its sum may differ);
+- against the CPU oracle at sampled points (the 16 largest-F points among
+  them): FP64 1e-12, FP32 1e-5 of the gain's scale;
+- ragged passes (chunk below the cell count), splits 2 and 4, a single cell;
+- three forward-Euler steps replayed from the captured graph equal three
+  steps of the fused schedule."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import efm
+from tests.gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+E = pytest.importorskip("paper_1704_07369_amd")
+N, R, L, M = 32, 6.0, 8.0, 32
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+def _cells(n, seed):
+    return [synth.sample_mixture(synth.mixture_anisotropic(seed + i, 3), N, L) for i in range(n)]
+
+
+def _run(plan, cells, prec, mode, chunk, split, steps=0):
+    import torch
+    b = E.Batch([plan], [len(cells)], prec)
+    b.set_schedule(0, mode, chunk, split)
+    f = to_dev(E.pack(b, cells))
+    Q = torch.full_like(f, float("nan"))
+    b.collide(f, Q)
+    if steps:
+        b.step(f, 0.01, steps, None)
+    torch.cuda.synchronize()
+    return E.unpack(b, Q.cpu().numpy()), E.unpack(b, f.cpu().numpy()), b.get_schedule(0)
+
+
+@pytest.mark.parametrize("prec,split,chunk,ncell", [
+    (0, 2, 0, 1), (0, 2, 2, 3), (0, 4, 0, 2), (1, 2, 0, 1), (1, 4, 3, 5),
+])
+def test_terms_match_fused_and_oracle(prec, split, chunk, ncell):
+    say(f"case term-parallel 32^3 precision={prec} split={split} chunk={chunk} cells={ncell}")
+    plan = E.Plan(N, 3, L, M, R=R)
+    cells = _cells(ncell, 8100 + 10 * split + ncell)
+    qt, ft, sched = _run(plan, cells, prec, E.EC_SCHED_TERMS, chunk, split, steps=3)
+    qf, ff, _ = _run(plan, cells, prec, E.EC_SCHED_FUSED, 0, split, steps=3)
+    say(f"  schedule {sched}")
+    assert sched[0] == E.EC_SCHED_TERMS and sched[2] == split
+    op = efm.make_plan(N, 3, L, M, R=R)
+    rng = np.random.default_rng(prec + split)
+    for c in range(ncell):
+        assert np.all(np.isfinite(qt[c]))
+        scale = np.abs(qf[c]).max()
+        d_fused = np.abs(qt[c] - qf[c]).max() / scale
+        d_step = np.abs(ft[c] - ff[c]).max() / np.abs(ff[c]).max()
+        idx = np.unique(np.concatenate([np.argsort(cells[c].ravel())[-16:],
+                                        rng.choice(N ** 3, 48, replace=False)]))
+        q, qp, _, _ = efm.collide_points(op, cells[c], idx)
+        err = np.abs(qt[c].ravel()[idx] - q).max() / np.abs(qp).max()
+        say(f"  cell {c}: vs fused {d_fused:.2e}, 3 steps vs fused {d_step:.2e}, "
+            f"vs oracle {err:.2e}")
+        assert d_fused <= 1e-14 and d_step <= 1e-14
+        assert err <= TOL[prec]
+
+
+def test_terms_is_the_small_batch_default_and_validated():
+    say("case term-parallel default and rejections")
+    plan = E.Plan(N, 3, L, M, R=R)
+    b = E.Batch([plan], [4], E.EC_FP64)
+    assert b.get_schedule(0)[0] == E.EC_SCHED_TERMS
+    with pytest.raises(E.EcError):
+        b.set_schedule(0, E.EC_SCHED_TERMS, 0, 3)
+    p16 = E.Plan(16, 3, L, M, R=R)
+    b16 = E.Batch([p16], [2], E.EC_FP64)
+    assert b16.get_schedule(0)[0] == E.EC_SCHED_PIPELINE
+    with pytest.raises(E.EcError):
+        b16.set_schedule(0, E.EC_SCHED_TERMS, 0, 0)
+    bb = E.Batch([plan], [2], E.EC_BF16X3)
+    with pytest.raises(E.EcError):
+        bb.set_schedule(0, E.EC_SCHED_TERMS, 0, 0)
