@@ -133,9 +133,9 @@ void default_schedule(BatchGroup& g, int precision) {
   if (g.mode == EC_SCHED_LINES && !lines_supported(T, precision)) g.mode = EC_SCHED_TWO_PASS;
   if (g.mode == EC_SCHED_FUSED && (T.d != 3 || fused_default_split(T.N, precision) == 0))
     g.mode = EC_SCHED_TWO_PASS;
-  if (g.mode == EC_SCHED_PIPELINE && T.N > 32) g.mode = EC_SCHED_TWO_PASS;   // register lines <= 32
   if (g.mode == EC_SCHED_TERMS && (T.d != 3 || !terms_supported(T.N, precision, 2)))
     g.mode = EC_SCHED_PIPELINE;
+  if (g.mode == EC_SCHED_PIPELINE && T.N > 32) g.mode = EC_SCHED_TWO_PASS;   // register lines <= 32
   if (T.d == 3 && g.mode == EC_SCHED_TERMS) {
     // per cell: the half spectrum and J N^3 FP64 term partials; keep a pass
     // under ~2 GiB of partials

@@ -84,3 +84,16 @@ def test_terms_is_the_small_batch_default_and_validated():
     bb = E.Batch([plan], [2], E.EC_BF16X3)
     with pytest.raises(E.EcError):
         bb.set_schedule(0, E.EC_SCHED_TERMS, 0, 0)
+
+
+def test_small_batch_defaults_of_other_sizes():
+    """Groups below 32 cells of sizes without the term-parallel form keep the
+    schedule they had: pipelined up to 32^3, two-pass at 64^3 and for 2D
+    grids (whose groups always run two-pass)."""
+    say("case small-batch defaults of other sizes")
+    for N, d, want in [(16, 3, E.EC_SCHED_PIPELINE), (24, 3, E.EC_SCHED_PIPELINE),
+                       (64, 3, E.EC_SCHED_TWO_PASS), (32, 2, E.EC_SCHED_TWO_PASS)]:
+        p = E.Plan(N, d, L, 8, R=R)
+        b = E.Batch([p], [2], E.EC_FP64)
+        say(f"  N={N} d={d}: schedule {b.get_schedule(0)}")
+        assert b.get_schedule(0)[0] == want
