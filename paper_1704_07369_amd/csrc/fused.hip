@@ -540,7 +540,16 @@ __global__ __launch_bounds__(256) void k_terms_reduce(const double* __restrict__
   const int64_t cc = gid / n, r = gid % n;
   const double* pc = part + cc * J * n + r;
   double acc = pc[(int64_t)(J - 1) * n];
-  for (int t = 0; t < J - 1; ++t) acc += pc[(int64_t)t * n];
+  // loads of 8 terms in flight, added in term order
+  int t = 0;
+  for (; t + 8 <= J - 1; t += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = pc[(int64_t)(t + k) * n];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += v[k];
+  }
+  for (; t < J - 1; ++t) acc += pc[(int64_t)t * n];
   const int64_t o = off[cell0 + cc] + r;
   Q[o] = dt == 0.0 ? acc : f[o] + dt * acc;
 }
