@@ -506,6 +506,18 @@ def main():
             if bb is not None:
                 out["parity"]["bf16x3"] = sampled_error(E, bb, Qb, cells, [0, args.cells - 1],
                                                         oplan, efm)
+            # every cell of the batch against the FP64 GPU result
+            n = N ** D
+            if Q64.numel() == args.cells * n:
+                ref = Q64.view(args.cells, n)
+                den = torch.linalg.vector_norm(ref, dim=1)
+                for name, Qp in (("fp32", Q32), ("bf16x3", Qb)):
+                    if Qp is None or Qp.numel() != Q64.numel():
+                        continue
+                    r = torch.linalg.vector_norm(Qp.view(args.cells, n) - ref, dim=1) / den
+                    out["parity"][f"{name}_vs_fp64_gpu_all_cells"] = {
+                        "metric": "per-cell ||Q - Q_fp64|| / ||Q_fp64|| over all cells",
+                        "median": float(r.median()), "max": float(r.max())}
         if not args.skip_cpu:
             log("bench: CPU baseline (oracle)")
             out["cpu_baseline"] = cpu_baseline(cells, efm, oplan)
