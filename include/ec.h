@@ -266,9 +266,13 @@ int ec_entropy_prod(ec_batch* batch, const double* f, const double* Q,
  * ec_monitors -- per cell EC_NMON FP64 diagnostics of (f, Q), device array
  * out[c * EC_NMON + i]: mass h^d sum F, sum Q, h^d sum_{F>0} Q ln F,
  * eta = h^d sum_{F>0} F ln F (section 4.2), min F, the positivity error
- * epsilon = (sum|F| - sum F)/sum|F| (section 4.2), sum |Q|.
+ * epsilon = (sum|F| - sum F)/sum|F| (section 4.2), sum |Q|, the momentum
+ * h^d sum Q v (three components; the third is 0 in 2D) and the energy
+ * h^d sum Q |v|^2 of Q at the grid points v = -L + j h.  Only mass is
+ * conserved exactly by the method; momentum and energy are reported, not
+ * conserved (section 5).
  */
-#define EC_NMON 7
+#define EC_NMON 11
 #define EC_MON_MASS      0
 #define EC_MON_SUMQ      1
 #define EC_MON_ENTPROD   2
@@ -276,6 +280,8 @@ int ec_entropy_prod(ec_batch* batch, const double* f, const double* Q,
 #define EC_MON_MINF      4
 #define EC_MON_EPS       5
 #define EC_MON_SUMABSQ   6
+#define EC_MON_MOMQ      7   /* 7, 8, 9: h^d sum Q v_i */
+#define EC_MON_ENERGYQ  10
 int ec_monitors(ec_batch* batch, const double* f, const double* Q, double* out,
                 void* hip_stream);
 

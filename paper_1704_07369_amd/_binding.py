@@ -20,12 +20,13 @@ EC_ERR_ARG, EC_ERR_DEVICE, EC_ERR_OOM, EC_ERR_UNSUPPORTED, EC_ERR_DOMAIN = -1, -
 EC_KERNEL_MAXWELL, EC_KERNEL_HARD_SPHERE, EC_KERNEL_VHS = 0, 1, 2
 EC_TRUNC_BOX, EC_TRUNC_BALL = 0, 1
 EC_FP64, EC_FP32, EC_BF16X3 = 0, 1, 2
-EC_NMON = 7
+EC_NMON = 11
 EC_SCHED_PIPELINE, EC_SCHED_TWO_PASS, EC_SCHED_FUSED, EC_SCHED_LINES, EC_SCHED_TERMS = 0, 1, 2, 3, 4
 EC_PROF_KERNELS = 6
 EC_TUNE_REMEASURE = 1
 PROF_KERNEL_NAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe", "k_fwdx", "k_fused"]
-MON_NAMES = ["mass", "sumQ", "entropy_prod", "eta", "minF", "eps_pos", "sumabsQ"]
+MON_NAMES = ["mass", "sumQ", "entropy_prod", "eta", "minF", "eps_pos", "sumabsQ",
+             "momQ_x", "momQ_y", "momQ_z", "energyQ"]
 
 _c_int, _c_double, _c_i64, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_void_p
 

@@ -114,6 +114,8 @@ struct ec_batch {
   int64_t* d_off = nullptr;
   int* d_n = nullptr;
   double* d_hd = nullptr;
+  int* d_geo = nullptr;     // per cell: N, d
+  double* d_L = nullptr;    // per cell: L
   void* d_ws = nullptr;     // workspace shared by the groups (one at a time)
   size_t ws_bytes = 0;
   int* d_step = nullptr;
@@ -532,8 +534,8 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
     b->precision = precision;
     if (hipGetDevice(&b->device) != hipSuccess) { delete b; return fail(EC_ERR_DEVICE, "no HIP device"); }
     int64_t cell = 0, elem = 0;
-    std::vector<int> ns;
-    std::vector<double> hds;
+    std::vector<int> ns, geo;
+    std::vector<double> hds, Ls;
     for (int g = 0; g < n_groups; ++g) {
       if (!plans[g] || counts[g] < 0) { delete b; return fail(EC_ERR_ARG, "bad group"); }
       BatchGroup bg;
@@ -552,6 +554,9 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
         b->offsets.push_back(elem);
         ns.push_back((int)T.n);
         hds.push_back(hd);
+        geo.push_back(T.N);
+        geo.push_back(T.d);
+        Ls.push_back(T.L);
         elem += (T.n + 31) / 32 * 32;   // 256-byte aligned cells
       }
       cell += counts[g];
@@ -562,13 +567,17 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
     if (cell > 0) {
       if (hipMalloc(&b->d_off, cell * sizeof(int64_t)) != hipSuccess ||
           hipMalloc(&b->d_n, cell * sizeof(int)) != hipSuccess ||
-          hipMalloc(&b->d_hd, cell * sizeof(double)) != hipSuccess) {
+          hipMalloc(&b->d_hd, cell * sizeof(double)) != hipSuccess ||
+          hipMalloc(&b->d_geo, 2 * cell * sizeof(int)) != hipSuccess ||
+          hipMalloc(&b->d_L, cell * sizeof(double)) != hipSuccess) {
         ec_batch_destroy(b);
         return fail(EC_ERR_OOM, "batch metadata");
       }
       if (hipMemcpy(b->d_off, b->offsets.data(), cell * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess ||
           hipMemcpy(b->d_n, ns.data(), cell * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemcpy(b->d_hd, hds.data(), cell * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+          hipMemcpy(b->d_hd, hds.data(), cell * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(b->d_geo, geo.data(), 2 * cell * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(b->d_L, Ls.data(), cell * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
         ec_batch_destroy(b);
         return fail(EC_ERR_DEVICE, "upload of batch metadata failed");
       }
@@ -589,6 +598,8 @@ int ec_batch_destroy(ec_batch* b) {
   if (b->d_off) (void)hipFree(b->d_off);
   if (b->d_n) (void)hipFree(b->d_n);
   if (b->d_hd) (void)hipFree(b->d_hd);
+  if (b->d_geo) (void)hipFree(b->d_geo);
+  if (b->d_L) (void)hipFree(b->d_L);
   if (b->d_ws) (void)hipFree(b->d_ws);
   if (b->d_step) (void)hipFree(b->d_step);
   if (b->d_rk) (void)hipFree(b->d_rk);
@@ -930,7 +941,7 @@ int ec_entropy_prod(ec_batch* b, const double* f, const double* Q, double* out,
     int rc = check_batch_ptrs(b, f, Q);
     if (rc) return rc;
     if (!Q || !out) return fail(EC_ERR_ARG, "Q or out is null");
-    HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, nullptr, out,
+    HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, b->d_geo, b->d_L, 0, b->n_cells, nullptr, out,
                            n_nonpos, nullptr, nullptr, 0, nullptr, (hipStream_t)stream));
     return EC_OK;
   });
@@ -941,7 +952,7 @@ int ec_monitors(ec_batch* b, const double* f, const double* Q, double* out, void
     int rc = check_batch_ptrs(b, f, Q);
     if (rc) return rc;
     if (!out) return fail(EC_ERR_ARG, "out is null");
-    HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, out, nullptr,
+    HIPCHK(launch_monitors(f, Q, b->d_off, b->d_n, b->d_hd, b->d_geo, b->d_L, 0, b->n_cells, out, nullptr,
                            nullptr, nullptr, nullptr, 0, nullptr, (hipStream_t)stream));
     return EC_OK;
   });
@@ -975,7 +986,7 @@ int record_step(ec_batch* b, double* f, double dt, int method, double* monitors,
     }
   }
   if (rc == EC_OK && monitors) {
-    hipError_t e2 = launch_monitors(f, nullptr, b->d_off, b->d_n, b->d_hd, 0, b->n_cells, nullptr,
+    hipError_t e2 = launch_monitors(f, nullptr, b->d_off, b->d_n, b->d_hd, b->d_geo, b->d_L, 0, b->n_cells, nullptr,
                                     nullptr, nullptr, b->d_step, monitors, b->n_cells,
                                     b->d_step + 1, s);
     if (e2 == hipSuccess) e2 = launch_inc_int(b->d_step, s);

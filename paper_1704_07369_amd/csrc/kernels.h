@@ -42,11 +42,14 @@ hipError_t launch_fwd(const ChunkArgs& a, hipStream_t s, bool half = false);
 //   step_mon: (mass, eta) at [(*step) * step_stride + cell][2]; step and the
 //             capacity step_cap are read on device; nothing is written once
 //             *step >= *step_cap
+// cell_geo: (N, d) per cell; cell_L: L per cell (the grid points of the
+// momentum and energy of Q, written to full[c * 11 + 7 .. 10] when Q is given)
 hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
-                           const int* cell_n, const double* cell_hd, int64_t cell0,
-                           int64_t ncells, double* full, double* entprod,
-                           int32_t* n_nonpos, const int* step, double* step_mon,
-                           int64_t step_stride, const int* step_cap, hipStream_t s);
+                           const int* cell_n, const double* cell_hd, const int* cell_geo,
+                           const double* cell_L, int64_t cell0, int64_t ncells, double* full,
+                           double* entprod, int32_t* n_nonpos, const int* step,
+                           double* step_mon, int64_t step_stride, const int* step_cap,
+                           hipStream_t s);
 
 hipError_t launch_copy(const double* a, double* b, int64_t n, hipStream_t s);
 // blocks x 256 threads, each valu_probe_chains() FMA chains of iters steps;

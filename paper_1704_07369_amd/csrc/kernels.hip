@@ -315,12 +315,15 @@ hipError_t launch_chunk(const ChunkArgs& a, hipStream_t st) {
 // per-cell reductions
 // ---------------------------------------------------------------------------
 constexpr int MON_BS = 256;
-constexpr int MON_Q = 8;   // reduced quantities
+constexpr int MON_Q = 12;   // reduced quantities
+constexpr int MON_OUT = 11; // values per cell of `full` (EC_NMON)
 
+// cell_geo[2c] = N (points per axis), cell_geo[2c + 1] = d; cell_L[c] = L
 __global__ __launch_bounds__(MON_BS) void k_monitors(
     const double* __restrict__ f, const double* __restrict__ Q,
     const int64_t* __restrict__ off, const int* __restrict__ cell_n,
-    const double* __restrict__ cell_hd, int64_t cell0, double* full,
+    const double* __restrict__ cell_hd, const int* __restrict__ cell_geo,
+    const double* __restrict__ cell_L, int64_t cell0, double* full,
     double* entprod, int32_t* n_nonpos, const int* step, double* step_mon,
     int64_t step_stride, const int* step_cap) {
   __shared__ double red[MON_Q][MON_BS];
@@ -328,8 +331,11 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
   const double* fc = f + off[c];
   const double* qc = Q ? Q + off[c] : nullptr;
   const int n = cell_n[c];
-  // 0 mass, 1 sumQ, 2 sum Q ln F, 3 sum F ln F, 4 min F, 5 sum |F|, 6 sum |Q|, 7 #F<=0
-  double a[MON_Q] = {0, 0, 0, 0, 1.0e300, 0, 0, 0};
+  // 0 mass, 1 sumQ, 2 sum Q ln F, 3 sum F ln F, 4 min F, 5 sum |F|, 6 sum |Q|, 7 #F<=0,
+  // 8..10 sum Q v_i, 11 sum Q |v|^2 (the moments only when Q is given)
+  double a[MON_Q] = {0, 0, 0, 0, 1.0e300, 0, 0, 0, 0, 0, 0, 0};
+  const int N = cell_geo[2 * c], d = cell_geo[2 * c + 1];
+  const double L = cell_L[c], h = 2.0 * L / N;
   for (int r = threadIdx.x; r < n; r += MON_BS) {
     const double fv = fc[r];
     const double qv = qc ? qc[r] : 0.0;
@@ -345,6 +351,17 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
     a[4] = fmin(a[4], fv);
     a[5] += fabs(fv);
     a[6] += fabs(qv);
+    if (qc) {
+      // grid point v = -L + i h, C order: 3D [i0][i1][i2], 2D [i0][i1]
+      const int i0 = d == 3 ? r / (N * N) : r / N;
+      const int i1 = d == 3 ? (r / N) % N : r % N;
+      const int i2 = d == 3 ? r % N : 0;
+      const double v0 = -L + i0 * h, v1 = -L + i1 * h, v2 = d == 3 ? -L + i2 * h : 0.0;
+      a[8] += qv * v0;
+      a[9] += qv * v1;
+      a[10] += qv * v2;
+      a[11] += qv * (v0 * v0 + v1 * v1 + v2 * v2);
+    }
   }
 #pragma unroll
   for (int k = 0; k < MON_Q; ++k) red[k][threadIdx.x] = a[k];
@@ -366,7 +383,7 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
     const double ep = hd * red[2][0];
     const int64_t lc = blockIdx.x;
     if (full) {
-      double* o = full + lc * 7;
+      double* o = full + lc * MON_OUT;
       o[0] = mass;
       o[1] = red[1][0];
       o[2] = ep;
@@ -374,6 +391,10 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
       o[4] = red[4][0];
       o[5] = red[5][0] > 0.0 ? (red[5][0] - red[0][0]) / red[5][0] : 0.0;
       o[6] = red[6][0];
+      o[7] = hd * red[8][0];
+      o[8] = hd * red[9][0];
+      o[9] = hd * red[10][0];
+      o[10] = hd * red[11][0];
     }
     if (entprod) entprod[lc] = ep;
     if (n_nonpos) n_nonpos[lc] = (int32_t)red[7][0];
@@ -386,14 +407,15 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
 }
 
 hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
-                           const int* cell_n, const double* cell_hd, int64_t cell0,
-                           int64_t ncells, double* full, double* entprod,
-                           int32_t* n_nonpos, const int* step, double* step_mon,
-                           int64_t step_stride, const int* step_cap, hipStream_t s) {
+                           const int* cell_n, const double* cell_hd, const int* cell_geo,
+                           const double* cell_L, int64_t cell0, int64_t ncells, double* full,
+                           double* entprod, int32_t* n_nonpos, const int* step,
+                           double* step_mon, int64_t step_stride, const int* step_cap,
+                           hipStream_t s) {
   if (ncells <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_monitors, dim3((unsigned)ncells), dim3(MON_BS), 0, s, f, Q, off,
-                     cell_n, cell_hd, cell0, full, entprod, n_nonpos, step, step_mon,
-                     step_stride, step_cap);
+                     cell_n, cell_hd, cell_geo, cell_L, cell0, full, entprod, n_nonpos, step,
+                     step_mon, step_stride, step_cap);
   return hipGetLastError();
 }
 

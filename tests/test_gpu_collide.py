@@ -7,6 +7,8 @@ vanishes near equilibrium while the rounding of the transforms scales with
 the gain.  FP32 transforms: 1e-5 (worst-case rounding growth over the forward
 and inverse stages, doubled by the product a_t b_t).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -220,6 +222,13 @@ def test_monitors_and_entropy_production():
         assert mon[c, 3] == pytest.approx(m["eta"], rel=1e-13)
         assert mon[c, 4] == m["minF"]
         assert mon[c, 6] == pytest.approx(m["sumabsQ"], rel=1e-13)
+        # momentum and energy of Q (reported, not conserved): sums of the same
+        # terms in another order, scale h^d sum |Q| |v| and h^d sum |Q| |v|^2
+        h3 = (2.0 * L / N) ** 3
+        vmax = L * math.sqrt(3.0)
+        for i in range(3):
+            assert abs(mon[c, 7 + i] - m["momentum"][i]) <= 1e-13 * h3 * m["sumabsQ"] * vmax
+        assert abs(mon[c, 10] - m["energy"]) <= 1e-13 * h3 * m["sumabsQ"] * vmax ** 2
         assert ep[c].item() == pytest.approx(m["entropy_prod"], rel=1e-12, abs=1e-15)
         assert nn[c].item() == m["n_nonpos"]
         assert ep[c].item() <= 0.0                       # discrete H-theorem
