@@ -208,16 +208,18 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
  * one term at a time through device memory (per cell of a pass: spectrum and
  * term volume, complex FP64, and an FP64 accumulator, 40 N^3 bytes); the only
  * schedule of 128^3 grids, whose plans are FP64 only.  EC_SCHED_TERMS (3D,
- * N = 32; FP64 and FP32; splits 2, 4): the fused schedule's column kernel
- * run with one workgroup per (cell, term, residue class), each writing its
+ * N = 16, 24, 32; FP64 and FP32; the fused schedule's splits, default 4 at
+ * 32^3): the fused schedule's kernel run with one workgroup per (cell,
+ * term, residue class), each writing its
  * term's products to device memory (J N^3 FP64 values per cell of a pass),
  * then a kernel that sums them per point in the fused kernel's order; for
  * small batches, whose latency is then about one term's.
  * 0 for cells_per_pass or term_groups selects the default (chosen from the
- * cache size); the autotuner picks measured values.  A new batch starts with
- * the fused schedule where it exists and the group has at least 32 cells,
- * with the term-parallel schedule (32^3) or the pipelined schedule (3D,
- * N <= 32) for smaller groups, and with the two-pass schedule otherwise.
+ * cache size); the autotuner picks measured values.  A new batch starts 3D
+ * groups of N = 16, 24 with up to 64 cells and of N = 32 with up to 31 cells
+ * on the term-parallel schedule, larger groups on the fused schedule where
+ * it exists, other 3D groups of N <= 32 below 32 cells on the pipelined
+ * schedule, and the rest on the two-pass schedule.
  * Reallocates the workspace (synchronises the device); call it outside
  * graph capture.
  */

@@ -127,6 +127,12 @@ namespace {
 
 size_t csize(int precision) { return precision == EC_FP64 ? 16 : 8; }
 
+// 32^3: split 4 (twice the workgroups of split 2, measured faster for 1 to
+// 31 cells); otherwise the fused schedule's default split
+int terms_default_split(int N, int precision) {
+  return N == 32 ? 4 : fused_default_split(N, precision);
+}
+
 void default_schedule(BatchGroup& g, int precision) {
   const HostTables& T = g.plan->host;
   const int64_t count = std::max<int64_t>(1, g.count);
@@ -135,7 +141,8 @@ void default_schedule(BatchGroup& g, int precision) {
   if (g.mode == EC_SCHED_LINES && !lines_supported(T, precision)) g.mode = EC_SCHED_TWO_PASS;
   if (g.mode == EC_SCHED_FUSED && (T.d != 3 || fused_default_split(T.N, precision) == 0))
     g.mode = EC_SCHED_TWO_PASS;
-  if (g.mode == EC_SCHED_TERMS && (T.d != 3 || !terms_supported(T.N, precision, 2)))
+  if (g.mode == EC_SCHED_TERMS &&
+      (T.d != 3 || !terms_supported(T.N, precision, terms_default_split(T.N, precision))))
     g.mode = EC_SCHED_PIPELINE;
   if (g.mode == EC_SCHED_PIPELINE && T.N > 32) g.mode = EC_SCHED_TWO_PASS;   // register lines <= 32
   if (T.d == 3 && g.mode == EC_SCHED_TERMS) {
@@ -144,7 +151,7 @@ void default_schedule(BatchGroup& g, int precision) {
     const double per_cell = (double)T.J * T.n * 8.0;
     const int64_t c = (int64_t)std::max(1.0, std::floor(2.0 * 1073741824.0 / per_cell));
     g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, count));
-    g.G = 4;   // twice the workgroups of split 2: measured faster for 1 to 31 cells
+    g.G = terms_default_split(T.N, precision);
   } else if (T.d == 3 && g.mode == EC_SCHED_FUSED) {
     // one spectrum per cell of workspace; 2048 cells keep >= 2048 workgroups busy
     g.chunk = (int)std::min<int64_t>(2048, count);
@@ -542,11 +549,15 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
       bg.plan = plans[g];
       bg.count = counts[g];
       bg.first = cell;
-      // the fused schedule runs P workgroups per cell: below a few dozen cells
-      // the term-parallel form (J P workgroups per cell; N = 32) or else the
-      // pipelined schedule (term groups spread one cell over many workgroups)
-      // fills more CUs; they fall back to two-pass where absent
-      bg.mode = counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_TERMS;
+      // the fused schedule runs P workgroups per cell: for small groups the
+      // term-parallel form (J P workgroups per cell) fills more CUs; measured
+      // faster up to 64 cells of 16^3 and 24^3 and below 32 cells of 32^3.
+      // Other sizes take the pipelined schedule (term groups spread one cell
+      // over many workgroups); each falls back to two-pass where absent
+      const int Ng = plans[g]->host.N;
+      const int64_t terms_max = (Ng == 16 || Ng == 24) ? 64 : 31;
+      bg.mode = counts[g] <= terms_max ? EC_SCHED_TERMS
+                : (counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_PIPELINE);
       default_schedule(bg, precision);
       const HostTables& T = plans[g]->host;
       const double hd = std::pow(2.0 * T.L / T.N, T.d);
@@ -628,8 +639,11 @@ int ec_batch_set_schedule(ec_batch* b, int group, int mode, int cells_per_pass, 
       return fail(EC_ERR_ARG, "bad mode");
     BatchGroup& g = b->groups[group];
     if (mode == EC_SCHED_TERMS &&
-        (g.plan->host.d != 3 || !terms_supported(g.plan->host.N, b->precision, 2)))
-      return fail(EC_ERR_UNSUPPORTED, "the term-parallel schedule needs 3D cells of N = 32 in FP64 or FP32");
+        (g.plan->host.d != 3 ||
+         !terms_supported(g.plan->host.N, b->precision,
+                          terms_default_split(g.plan->host.N, b->precision))))
+      return fail(EC_ERR_UNSUPPORTED,
+                  "the term-parallel schedule needs 3D cells of N = 16, 24 or 32 in FP64 or FP32");
     if (mode == EC_SCHED_LINES && !lines_supported(g.plan->host, b->precision))
       return fail(EC_ERR_UNSUPPORTED, "the lines schedule needs 3D cells of N = 64 or 128 in FP64");
     if (mode != EC_SCHED_LINES && is_large3d_only(g.plan->host))
@@ -816,12 +830,14 @@ int ec_autotune(ec_batch* b, const double* f, double* Q, const char* cache_path,
               if (!dup) cand.push_back(sc);
             }
       }
-      if (T.d == 3 && terms_supported(T.N, b->precision, 2) && count < 256) {
+      if (T.d == 3 && count < 256 &&
+          terms_supported(T.N, b->precision, terms_default_split(T.N, b->precision))) {
         BatchGroup probe = g;
         probe.mode = EC_SCHED_TERMS;
         default_schedule(probe, b->precision);
-        for (int P : {2, 4})
-          cand.push_back(Sched{EC_SCHED_TERMS, probe.chunk, P});
+        for (int P : {1, 2, 3, 4})
+          if (terms_supported(T.N, b->precision, P))
+            cand.push_back(Sched{EC_SCHED_TERMS, probe.chunk, P});
       }
       if (T.d == 3 && T.N <= 32) {
         for (int c : {4, 6, 8, 12, 16, 24})

@@ -18,9 +18,10 @@ bool fused_supported(int N, int precision, int split);
 // set: before k_fwd, after k_fwd, after k_fwdx, after k_fused.
 hipError_t launch_fused(const ChunkArgs& a, int split, hipStream_t st);
 
-// Term-parallel variant for small batches (3D, N = 32, FP64 or FP32, split 2
-// or 4): the forward transform into a.W as for launch_fused, then one
-// workgroup per (cell, term, x residue) writing its term's products to a.Z
+// Term-parallel variant for small batches (3D, N = 16, 24, 32, FP64 or FP32,
+// the splits of launch_fused): the forward transform into a.W as for
+// launch_fused, then one workgroup per (cell, term, x residue) of the column
+// (N = 32) or LDS-volume kernel writing its term's products to a.Z
 // (ncells x J x N^3 doubles), then their sum per point into Q.  Events as for
 // launch_fused (a.ev[3] after the sum).
 bool terms_supported(int N, int precision, int split);

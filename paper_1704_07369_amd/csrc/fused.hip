@@ -528,6 +528,54 @@ void k_terms_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
   }
 }
 
+// The same for the LDS-volume kernel (N = 16, 24): one workgroup per (cell,
+// term, x residue class) runs that term with run_term and writes its products.
+template <typename R, int N, int P>
+__global__ __launch_bounds__(N / P * N) void k_terms_lds(
+    const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int J, const double* f,
+    const int64_t* __restrict__ off, int64_t cell0, int ncells, double* __restrict__ part) {
+  constexpr int NP = N / P, T = NP * N, LD = N + 1, n = N * N * N;
+  __shared__ cx<R> vol[NP * N * LD];
+  const int blk = blockIdx.x;
+  const int s = (blk / 8) % P;
+  const int cc = (blk / (8 * P)) * 8 + blk % 8;
+  if (cc >= ncells) return;             // whole workgroup
+  const int term = blockIdx.y;
+  const int th = threadIdx.x;
+  const int a = th / N, bq = th % N;
+  const cx<R> tw = unit_root<N, R>((a * s) % N);
+  const int am = (NP - a) % NP, bm = (N - bq) % N;
+  const cx<R>* Fc = Fh + (int64_t)cc * (n / 2);
+  const double* fc = f + off[cell0 + cc];
+  constexpr int C = fh_cache<N, P, (int)sizeof(R)>();
+  cx<R> fh[C > 0 ? C : 1][P];
+#pragma unroll
+  for (int k2 = 0; k2 < C; ++k2) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) fh[k2][j] = Fc[((a + NP * j) * (N / 2) + k2) * N + bq];
+  }
+  double acc[P][NP];
+  if (term == J - 1) {
+    run_term<R, N, P, C, true>(s, G + (int64_t)(J - 1) * n, Fc, fh, a, bq, am, bm, tw, vol, fc,
+                               acc);
+  } else {
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) acc[p][q] = 0.0;
+    run_term<R, N, P, C, false>(s, G + (int64_t)term * n, Fc, fh, a, bq, am, bm, tw, vol, fc,
+                                acc);
+  }
+  double* pc = part + ((int64_t)cc * J + term) * n;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int line = th + T * p;
+    const int y = line / N, z = line % N;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) pc[((P * q + s) * N + y) * N + z] = acc[p][q];
+  }
+}
+
 // Q = sum of the term partials in the fused kernel's order (the loss term's
 // -F l first); Euler update when dt != 0
 __global__ __launch_bounds__(256) void k_terms_reduce(const double* __restrict__ part, int J,
@@ -554,9 +602,9 @@ __global__ __launch_bounds__(256) void k_terms_reduce(const double* __restrict__
   Q[o] = dt == 0.0 ? acc : f[o] + dt * acc;
 }
 
-template <typename R, int P>
+template <typename R, int N, int P>
 static hipError_t launch_terms_t(const ChunkArgs& a, hipStream_t st) {
-  constexpr int N = 32, KZ = N / 2;
+  constexpr int KZ = N / 2;
   cx<R>* W = (cx<R>*)a.W;
   hipError_t e = launch_fwd(a, st, true);
   if (e != hipSuccess) return e;
@@ -566,9 +614,14 @@ static hipError_t launch_terms_t(const ChunkArgs& a, hipStream_t st) {
                      W, a.ncells);
   if (a.ev) (void)hipEventRecord(a.ev[2], st);
   const dim3 grid((unsigned)((a.ncells + 7) / 8 * 8 * P), (unsigned)a.J);
-  hipLaunchKernelGGL((k_terms_col<R, N, P>), grid, dim3(fused_threads<N, P>()), 0, st,
-                     (const cx<R>*)W, (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0, a.ncells,
-                     (double*)a.Z);
+  if constexpr (N == 32)
+    hipLaunchKernelGGL((k_terms_col<R, N, P>), grid, dim3(fused_threads<N, P>()), 0, st,
+                       (const cx<R>*)W, (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0,
+                       a.ncells, (double*)a.Z);
+  else
+    hipLaunchKernelGGL((k_terms_lds<R, N, P>), grid, dim3(fused_threads<N, P>()), 0, st,
+                       (const cx<R>*)W, (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0,
+                       a.ncells, (double*)a.Z);
   const int64_t pts = (int64_t)a.ncells * N * N * N;
   hipLaunchKernelGGL(k_terms_reduce, dim3((unsigned)((pts + 255) / 256)), dim3(256), 0, st,
                      (const double*)a.Z, a.J, N * N * N, a.f, a.off, a.cell0, a.ncells, a.Q,
@@ -578,15 +631,25 @@ static hipError_t launch_terms_t(const ChunkArgs& a, hipStream_t st) {
 }
 
 bool terms_supported(int N, int precision, int split) {
-  return N == 32 && precision != 2 && (split == 2 || split == 4);
+  // the splits of the fused schedule
+  return fused_supported(N, precision, split);
 }
 
 hipError_t launch_terms(const ChunkArgs& a, int split, hipStream_t st) {
   if (a.ncells <= 0) return hipSuccess;
   if (a.d != 3 || !terms_supported(a.N, a.precision, split) || !a.Z) return hipErrorInvalidValue;
-  if (a.precision == 0)
-    return split == 2 ? launch_terms_t<double, 2>(a, st) : launch_terms_t<double, 4>(a, st);
-  return split == 2 ? launch_terms_t<float, 2>(a, st) : launch_terms_t<float, 4>(a, st);
+  if (a.precision == 0) {
+    if (a.N == 16) return split == 1 ? launch_terms_t<double, 16, 1>(a, st)
+                                     : launch_terms_t<double, 16, 2>(a, st);
+    if (a.N == 24) return split == 2 ? launch_terms_t<double, 24, 2>(a, st)
+                                     : launch_terms_t<double, 24, 3>(a, st);
+    return split == 2 ? launch_terms_t<double, 32, 2>(a, st) : launch_terms_t<double, 32, 4>(a, st);
+  }
+  if (a.N == 16) return split == 1 ? launch_terms_t<float, 16, 1>(a, st)
+                                   : launch_terms_t<float, 16, 2>(a, st);
+  if (a.N == 24) return split == 2 ? launch_terms_t<float, 24, 2>(a, st)
+                                   : launch_terms_t<float, 24, 3>(a, st);
+  return split == 2 ? launch_terms_t<float, 32, 2>(a, st) : launch_terms_t<float, 32, 4>(a, st);
 }
 
 // k_fwd, k_fwdx, then the fused kernel (COL: the column form)

@@ -78,22 +78,61 @@ def test_terms_is_the_small_batch_default_and_validated():
         b.set_schedule(0, E.EC_SCHED_TERMS, 0, 3)
     p16 = E.Plan(16, 3, L, M, R=R)
     b16 = E.Batch([p16], [2], E.EC_FP64)
-    assert b16.get_schedule(0)[0] == E.EC_SCHED_PIPELINE
+    assert b16.get_schedule(0)[0] == E.EC_SCHED_TERMS
     with pytest.raises(E.EcError):
-        b16.set_schedule(0, E.EC_SCHED_TERMS, 0, 0)
+        b16.set_schedule(0, E.EC_SCHED_TERMS, 0, 4)       # not a split of 16^3
+    p64 = E.Plan(64, 3, L, 8, R=R)
+    b64 = E.Batch([p64], [1], E.EC_FP64)
+    with pytest.raises(E.EcError):
+        b64.set_schedule(0, E.EC_SCHED_TERMS, 0, 0)
     bb = E.Batch([plan], [2], E.EC_BF16X3)
     with pytest.raises(E.EcError):
         bb.set_schedule(0, E.EC_SCHED_TERMS, 0, 0)
 
 
 def test_small_batch_defaults_of_other_sizes():
-    """Groups below 32 cells of sizes without the term-parallel form keep the
-    schedule they had: pipelined up to 32^3, two-pass at 64^3 and for 2D
-    grids (whose groups always run two-pass)."""
+    """Default schedules by group size: term-parallel up to 64 cells of 16^3
+    and 24^3 (fused above), two-pass at 64^3 and for 2D grids (whose groups
+    always run two-pass)."""
     say("case small-batch defaults of other sizes")
-    for N, d, want in [(16, 3, E.EC_SCHED_PIPELINE), (24, 3, E.EC_SCHED_PIPELINE),
-                       (64, 3, E.EC_SCHED_TWO_PASS), (32, 2, E.EC_SCHED_TWO_PASS)]:
+    for N, d, count, want in [(16, 3, 2, E.EC_SCHED_TERMS), (24, 3, 2, E.EC_SCHED_TERMS),
+                              (16, 3, 64, E.EC_SCHED_TERMS), (24, 3, 64, E.EC_SCHED_TERMS),
+                              (16, 3, 65, E.EC_SCHED_FUSED), (24, 3, 65, E.EC_SCHED_FUSED),
+                              (64, 3, 2, E.EC_SCHED_TWO_PASS), (32, 2, 2, E.EC_SCHED_TWO_PASS)]:
         p = E.Plan(N, d, L, 8, R=R)
-        b = E.Batch([p], [2], E.EC_FP64)
-        say(f"  N={N} d={d}: schedule {b.get_schedule(0)}")
+        b = E.Batch([p], [count], E.EC_FP64)
+        say(f"  N={N} d={d} cells={count}: schedule {b.get_schedule(0)}")
         assert b.get_schedule(0)[0] == want
+
+
+@pytest.mark.parametrize("Nl,prec,split,ncell", [
+    (16, 0, 1, 2), (16, 0, 2, 3), (16, 1, 1, 2), (24, 0, 3, 2), (24, 0, 2, 3), (24, 1, 3, 1),
+])
+def test_terms_lds_volume_form(Nl, prec, split, ncell):
+    """N = 16, 24: the term-parallel form of the LDS-volume kernel against the
+    fused schedule (same products, same order of the sums) and the oracle."""
+    import torch
+    say(f"case term-parallel {Nl}^3 precision={prec} split={split} cells={ncell}")
+    plan = E.Plan(Nl, 3, L, M, R=R)
+    cells = [synth.sample_mixture(synth.mixture_anisotropic(8300 + Nl + i, 3), Nl, L)
+             for i in range(ncell)]
+    out = {}
+    for mode in (E.EC_SCHED_TERMS, E.EC_SCHED_FUSED):
+        b = E.Batch([plan], [ncell], prec)
+        b.set_schedule(0, mode, 0, split)
+        f = to_dev(E.pack(b, cells))
+        Q = torch.full_like(f, float("nan"))
+        b.collide(f, Q)
+        torch.cuda.synchronize()
+        out[mode] = E.unpack(b, Q.cpu().numpy())
+    op = efm.make_plan(Nl, 3, L, M, R=R)
+    rng = np.random.default_rng(Nl + split)
+    for c in range(ncell):
+        qt, qf = out[E.EC_SCHED_TERMS][c], out[E.EC_SCHED_FUSED][c]
+        d_fused = np.abs(qt - qf).max() / np.abs(qf).max()
+        idx = np.unique(np.concatenate([np.argsort(cells[c].ravel())[-16:],
+                                        rng.choice(Nl ** 3, 48, replace=False)]))
+        q, qp, _, _ = efm.collide_points(op, cells[c], idx)
+        err = np.abs(qt.ravel()[idx] - q).max() / np.abs(qp).max()
+        say(f"  cell {c}: vs fused {d_fused:.2e}, vs oracle {err:.2e}")
+        assert d_fused <= 1e-14 and err <= TOL[prec]
