@@ -1,6 +1,7 @@
-"""The term-parallel schedule (EC_SCHED_TERMS, 32^3): one workgroup per
-(cell, term, x residue class) writes its term's products, a second kernel
-sums them per point in the fused kernel's order.
+"""The term-parallel schedule (EC_SCHED_TERMS; 32^3 column kernel, 16^3 and
+24^3 LDS-volume kernel): one workgroup per (cell, term, x residue class)
+writes its term's products, a second kernel sums them per point in the
+fused kernel's order.
 
 - against the fused schedule on the same inputs: the same sums of the same
   FP64 products, so agreement to 1e-14 of the gain in FP64 and FP32 (only
@@ -9,7 +10,8 @@ sums them per point in the fused kernel's order.
   them): FP64 1e-12, FP32 1e-5 of the gain's scale;
 - ragged passes (chunk below the cell count), splits 2 and 4, a single cell;
 - three forward-Euler steps replayed from the captured graph equal three
-  steps of the fused schedule."""
+  steps of the fused schedule, also for a batch of small 16^3, 24^3 and
+  32^3 groups that all start on this schedule."""
 import numpy as np
 import pytest
 
@@ -136,3 +138,44 @@ def test_terms_lds_volume_form(Nl, prec, split, ncell):
         err = np.abs(qt.ravel()[idx] - q).max() / np.abs(qp).max()
         say(f"  cell {c}: vs fused {d_fused:.2e}, vs oracle {err:.2e}")
         assert d_fused <= 1e-14 and err <= TOL[prec]
+
+
+def test_mixed_small_groups_default_to_terms_and_step_like_fused():
+    """A batch of small 16^3, 24^3 and 32^3 groups starts every group on the
+    term-parallel schedule; one evaluation and three graph-replayed
+    forward-Euler steps (a ragged pass at 16^3) equal those of the fused
+    schedule."""
+    import torch
+    say("case mixed small groups 16^3 x 3, 24^3 x 2, 32^3 x 2, term-parallel vs fused")
+    sizes, counts = [16, 24, 32], [3, 2, 2]
+    plans = [E.Plan(Ng, 3, L, M, R=R) for Ng in sizes]
+    cells = [synth.sample_mixture(synth.mixture_anisotropic(8400 + 10 * Ng + i, 3), Ng, L)
+             for Ng, k in zip(sizes, counts) for i in range(k)]
+    res = {}
+    for mode in (E.EC_SCHED_TERMS, E.EC_SCHED_FUSED):
+        b = E.Batch(plans, counts, E.EC_FP64)
+        if mode == E.EC_SCHED_TERMS:
+            assert [b.get_schedule(g)[0] for g in range(3)] == [E.EC_SCHED_TERMS] * 3
+            b.set_schedule(0, E.EC_SCHED_TERMS, 2, 0)           # 3 cells in passes of 2
+        else:
+            for g in range(3):
+                b.set_schedule(g, E.EC_SCHED_FUSED, 0, 0)
+        f = to_dev(E.pack(b, cells))
+        Q = torch.full_like(f, float("nan"))
+        b.collide(f, Q)
+        b.step(f, 0.01, 3, None)
+        torch.cuda.synchronize()
+        res[mode] = (E.unpack(b, Q.cpu().numpy()), E.unpack(b, f.cpu().numpy()))
+        b.close()
+    (qt, ft), (qf, ff) = res[E.EC_SCHED_TERMS], res[E.EC_SCHED_FUSED]
+    ops = {Ng: efm.make_plan(Ng, 3, L, M, R=R) for Ng in sizes}
+    for c in range(len(cells)):
+        # scale: the gain at the 16 largest-F points (the oracle's); the two
+        # schedules add the same products in the same order and differ only
+        # where the fused kernel contracts a product into its sum
+        Ng = cells[c].shape[0]
+        _, qp, _, _ = efm.collide_points(ops[Ng], cells[c], np.argsort(cells[c].ravel())[-16:])
+        dq = np.abs(qt[c] - qf[c]).max() / np.abs(qp).max()
+        df = np.abs(ft[c] - ff[c]).max() / np.abs(ff[c]).max()
+        say(f"  cell {c} ({Ng}^3): Q {dq:.2e} of the gain, 3 steps {df:.2e}")
+        assert np.all(np.isfinite(qt[c])) and dq <= 1e-14 and df <= 1e-14
