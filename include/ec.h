@@ -216,10 +216,11 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
  * small batches, whose latency is then about one term's.
  * 0 for cells_per_pass or term_groups selects the default (chosen from the
  * cache size); the autotuner picks measured values.  A new batch starts 3D
- * groups of N = 16, 24 with up to 64 cells and of N = 32 with up to 31 cells
- * on the term-parallel schedule, larger groups on the fused schedule where
- * it exists, other 3D groups of N <= 32 below 32 cells on the pipelined
- * schedule, and the rest on the two-pass schedule.
+ * groups on the term-parallel schedule up to its measured crossover with the
+ * fused one (FP64 / FP32: N = 16 192 / 192 cells, N = 24 64 / 80, N = 32
+ * 56 / 40), larger groups on the fused schedule where it exists, other 3D
+ * groups of N <= 32 below 32 cells on the pipelined schedule, and the rest
+ * on the two-pass schedule.
  * Reallocates the workspace (synchronises the device); call it outside
  * graph capture.
  */

@@ -133,6 +133,20 @@ int terms_default_split(int N, int precision) {
   return N == 32 ? 4 : fused_default_split(N, precision);
 }
 
+// Largest group that starts on the term-parallel schedule: its time grows
+// with the cell count while the fused schedule's stays about flat until
+// its workgroups fill the CUs; measured crossovers (FP64 / FP32): 16^3
+// 192 / 192 cells, 24^3 64 / 80, 32^3 56 / 40.  0: no term-parallel default.
+int64_t terms_default_max_cells(int N, int precision) {
+  const bool fp64 = precision == EC_FP64;
+  switch (N) {
+    case 16: return 192;
+    case 24: return fp64 ? 64 : 80;
+    case 32: return fp64 ? 56 : 40;
+    default: return 0;
+  }
+}
+
 void default_schedule(BatchGroup& g, int precision) {
   const HostTables& T = g.plan->host;
   const int64_t count = std::max<int64_t>(1, g.count);
@@ -550,14 +564,13 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
       bg.count = counts[g];
       bg.first = cell;
       // the fused schedule runs P workgroups per cell: for small groups the
-      // term-parallel form (J P workgroups per cell) fills more CUs; measured
-      // faster up to 64 cells of 16^3 and 24^3 and below 32 cells of 32^3.
-      // Other sizes take the pipelined schedule (term groups spread one cell
-      // over many workgroups); each falls back to two-pass where absent
-      const int Ng = plans[g]->host.N;
-      const int64_t terms_max = (Ng == 16 || Ng == 24) ? 64 : 31;
-      bg.mode = counts[g] <= terms_max ? EC_SCHED_TERMS
-                : (counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_PIPELINE);
+      // term-parallel form (J P workgroups per cell) fills more CUs.  Small
+      // groups of other sizes take the pipelined schedule (term groups
+      // spread one cell over many workgroups); each falls back to two-pass
+      // where absent
+      bg.mode = counts[g] <= terms_default_max_cells(plans[g]->host.N, precision)
+                    ? EC_SCHED_TERMS
+                    : (counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_PIPELINE);
       default_schedule(bg, precision);
       const HostTables& T = plans[g]->host;
       const double hd = std::pow(2.0 * T.L / T.N, T.d);

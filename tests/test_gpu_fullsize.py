@@ -63,9 +63,12 @@ def test_headline_size_parity(prec, check):
         assert err <= tol
 
 
-def test_degenerate_cells_in_fused_batch():
+@pytest.mark.parametrize("mode", ["fused", "terms"])
+def test_degenerate_cells_in_fused_batch(mode):
+    """A zero cell, a one-point spike and a Maxwellian among 33 cells, under
+    the fused schedule and the term-parallel one (the default at 33 cells)."""
     import torch
-    say("case degenerate cells in a fused batch")
+    say(f"case degenerate cells in a batch of 33, {mode} schedule")
     cells = bench_cells(33)
     cells[3] = np.zeros((N,) * 3)
     spike = np.zeros((N,) * 3)
@@ -76,7 +79,10 @@ def test_degenerate_cells_in_fused_batch():
     cells[29] = mx
     p = E.Plan(N, D, L, M, R=R)
     b = E.Batch([p], [33])
-    assert b.get_schedule(0)[0] == E.EC_SCHED_FUSED
+    if mode == "terms":
+        assert b.get_schedule(0)[0] == E.EC_SCHED_TERMS
+    else:
+        b.set_schedule(0, E.EC_SCHED_FUSED, 0, 0)
     f = to_dev(E.pack(b, cells))
     Q = torch.full_like(f, float("nan"))
     b.collide(f, Q)

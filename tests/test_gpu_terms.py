@@ -93,18 +93,23 @@ def test_terms_is_the_small_batch_default_and_validated():
 
 
 def test_small_batch_defaults_of_other_sizes():
-    """Default schedules by group size: term-parallel up to 64 cells of 16^3
-    and 24^3 (fused above), two-pass at 64^3 and for 2D grids (whose groups
-    always run two-pass)."""
+    """Default schedules by group size: term-parallel up to the measured
+    crossover (FP64 / FP32: 16^3 192 / 192 cells, 24^3 64 / 80, 32^3 56 / 40),
+    fused above it, two-pass at 64^3 and for 2D grids (whose groups always
+    run two-pass)."""
     say("case small-batch defaults of other sizes")
-    for N, d, count, want in [(16, 3, 2, E.EC_SCHED_TERMS), (24, 3, 2, E.EC_SCHED_TERMS),
-                              (16, 3, 64, E.EC_SCHED_TERMS), (24, 3, 64, E.EC_SCHED_TERMS),
-                              (16, 3, 65, E.EC_SCHED_FUSED), (24, 3, 65, E.EC_SCHED_FUSED),
-                              (64, 3, 2, E.EC_SCHED_TWO_PASS), (32, 2, 2, E.EC_SCHED_TWO_PASS)]:
+    T, F = E.EC_SCHED_TERMS, E.EC_SCHED_FUSED
+    for N, d, prec, count, want in [
+            (16, 3, 0, 2, T), (24, 3, 0, 2, T), (16, 3, 0, 192, T), (16, 3, 0, 193, F),
+            (16, 3, 1, 192, T), (16, 3, 1, 193, F), (24, 3, 0, 64, T), (24, 3, 0, 65, F),
+            (24, 3, 1, 80, T), (24, 3, 1, 81, F), (32, 3, 0, 56, T), (32, 3, 0, 57, F),
+            (32, 3, 1, 40, T), (32, 3, 1, 41, F),
+            (64, 3, 0, 2, E.EC_SCHED_TWO_PASS), (32, 2, 0, 2, E.EC_SCHED_TWO_PASS)]:
         p = E.Plan(N, d, L, 8, R=R)
-        b = E.Batch([p], [count], E.EC_FP64)
-        say(f"  N={N} d={d} cells={count}: schedule {b.get_schedule(0)}")
+        b = E.Batch([p], [count], prec)
+        say(f"  N={N} d={d} precision={prec} cells={count}: schedule {b.get_schedule(0)}")
         assert b.get_schedule(0)[0] == want
+        b.close()
 
 
 @pytest.mark.parametrize("Nl,prec,split,ncell", [
