@@ -184,3 +184,46 @@ def test_mixed_small_groups_default_to_terms_and_step_like_fused():
         df = np.abs(ft[c] - ff[c]).max() / np.abs(ff[c]).max()
         say(f"  cell {c} ({Ng}^3): Q {dq:.2e} of the gain, 3 steps {df:.2e}")
         assert np.all(np.isfinite(qt[c])) and dq <= 1e-14 and df <= 1e-14
+
+
+@pytest.mark.parametrize("Nl,prec,ncell", [(16, 0, 192), (24, 1, 80), (32, 0, 56)])
+def test_terms_at_the_default_crossover(Nl, prec, ncell):
+    """The largest groups that start on the term-parallel schedule (the
+    measured crossover with the fused one): every cell against the fused
+    schedule, whose products and order of sums it shares (1e-13 of each
+    cell's max |Q|: J = 33 products per point rounded apart from their sum,
+    on gains up to ~20x |Q| for these mixtures), two cells against the
+    oracle at sampled points."""
+    import torch
+    say(f"case term-parallel default at {ncell} cells of {Nl}^3 precision={prec}")
+    plan = E.Plan(Nl, 3, L, M, R=R)
+    base = [synth.sample_mixture(synth.mixture_anisotropic(8500 + Nl + i, 3), Nl, L)
+            for i in range(8)]
+    cells = [base[i % 8] * (1.0 + 1e-3 * i) for i in range(ncell)]
+    out = {}
+    for mode in (E.EC_SCHED_TERMS, E.EC_SCHED_FUSED):
+        b = E.Batch([plan], [ncell], prec)
+        if mode == E.EC_SCHED_TERMS:
+            assert b.get_schedule(0)[0] == E.EC_SCHED_TERMS
+        else:
+            b.set_schedule(0, E.EC_SCHED_FUSED, 0, 0)
+        f = to_dev(E.pack(b, cells))
+        Q = torch.full_like(f, float("nan"))
+        b.collide(f, Q)
+        torch.cuda.synchronize()
+        out[mode] = E.unpack(b, Q.cpu().numpy())
+        b.close()
+        del f, Q
+    qt, qf = out[E.EC_SCHED_TERMS], out[E.EC_SCHED_FUSED]
+    worst = max(np.abs(qt[c] - qf[c]).max() / np.abs(qf[c]).max() for c in range(ncell))
+    say(f"  worst cell vs fused {worst:.2e}")
+    assert all(np.all(np.isfinite(q)) for q in qt) and worst <= 1e-13
+    op = efm.make_plan(Nl, 3, L, M, R=R)
+    rng = np.random.default_rng(Nl)
+    for c in (0, ncell - 1):
+        idx = np.unique(np.concatenate([np.argsort(cells[c].ravel())[-12:],
+                                        rng.choice(Nl ** 3, 20, replace=False)]))
+        q, qp, _, _ = efm.collide_points(op, cells[c], idx)
+        err = np.abs(qt[c].ravel()[idx] - q).max() / np.abs(qp).max()
+        say(f"  cell {c} vs oracle {err:.2e}")
+        assert err <= TOL[prec]
