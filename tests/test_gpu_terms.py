@@ -149,7 +149,7 @@ def test_mixed_small_groups_default_to_terms_and_step_like_fused():
     """A batch of small 16^3, 24^3 and 32^3 groups starts every group on the
     term-parallel schedule; one evaluation and three graph-replayed
     forward-Euler steps (a ragged pass at 16^3) equal those of the fused
-    schedule."""
+    schedule at the same x splits."""
     import torch
     say("case mixed small groups 16^3 x 3, 24^3 x 2, 32^3 x 2, term-parallel vs fused")
     sizes, counts = [16, 24, 32], [3, 2, 2]
@@ -163,8 +163,8 @@ def test_mixed_small_groups_default_to_terms_and_step_like_fused():
             assert [b.get_schedule(g)[0] for g in range(3)] == [E.EC_SCHED_TERMS] * 3
             b.set_schedule(0, E.EC_SCHED_TERMS, 2, 0)           # 3 cells in passes of 2
         else:
-            for g in range(3):
-                b.set_schedule(g, E.EC_SCHED_FUSED, 0, 0)
+            for g, Ng in enumerate(sizes):       # the term-parallel default splits
+                b.set_schedule(g, E.EC_SCHED_FUSED, 0, {16: 1, 24: 3, 32: 4}[Ng])
         f = to_dev(E.pack(b, cells))
         Q = torch.full_like(f, float("nan"))
         b.collide(f, Q)
@@ -190,7 +190,8 @@ def test_mixed_small_groups_default_to_terms_and_step_like_fused():
 def test_terms_at_the_default_crossover(Nl, prec, ncell):
     """The largest groups that start on the term-parallel schedule (the
     measured crossover with the fused one): every cell against the fused
-    schedule, whose products and order of sums it shares (1e-13 of each
+    schedule at the same x split, whose products and order of sums it
+    shares (1e-13 of each
     cell's max |Q|: J = 33 products per point rounded apart from their sum,
     on gains up to ~20x |Q| for these mixtures), two cells against the
     oracle at sampled points."""
@@ -206,7 +207,7 @@ def test_terms_at_the_default_crossover(Nl, prec, ncell):
         if mode == E.EC_SCHED_TERMS:
             assert b.get_schedule(0)[0] == E.EC_SCHED_TERMS
         else:
-            b.set_schedule(0, E.EC_SCHED_FUSED, 0, 0)
+            b.set_schedule(0, E.EC_SCHED_FUSED, 0, {16: 1, 24: 3, 32: 4}[Nl])   # same split
         f = to_dev(E.pack(b, cells))
         Q = torch.full_like(f, float("nan"))
         b.collide(f, Q)
@@ -227,3 +228,38 @@ def test_terms_at_the_default_crossover(Nl, prec, ncell):
         err = np.abs(qt[c].ravel()[idx] - q).max() / np.abs(qp).max()
         say(f"  cell {c} vs oracle {err:.2e}")
         assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("Nl,prec", [(16, 0), (32, 0), (32, 1)])
+def test_terms_with_a_ragged_term_count(Nl, prec):
+    """M = 13 directions: 13 gain terms, so the sum kernel's loads of 8 terms
+    at a time leave 5; against the fused schedule at the same x split and
+    the oracle."""
+    import torch
+    split = {16: 1, 32: 2}[Nl]
+    say(f"case term-parallel {Nl}^3 M=13 precision={prec} split={split}")
+    plan = E.Plan(Nl, 3, L, 13, R=R)
+    cells = [synth.sample_mixture(synth.mixture_anisotropic(8600 + Nl + i, 3), Nl, L)
+             for i in range(2)]
+    out = {}
+    for mode in (E.EC_SCHED_TERMS, E.EC_SCHED_FUSED):
+        b = E.Batch([plan], [2], prec)
+        b.set_schedule(0, mode, 0, split)
+        f = to_dev(E.pack(b, cells))
+        Q = torch.full_like(f, float("nan"))
+        b.collide(f, Q)
+        torch.cuda.synchronize()
+        out[mode] = E.unpack(b, Q.cpu().numpy())
+        b.close()
+    op = efm.make_plan(Nl, 3, L, 13, R=R)
+    rng = np.random.default_rng(13 + Nl)
+    for c in range(2):
+        qt, qf = out[E.EC_SCHED_TERMS][c], out[E.EC_SCHED_FUSED][c]
+        idx = np.unique(np.concatenate([np.argsort(cells[c].ravel())[-16:],
+                                        rng.choice(Nl ** 3, 32, replace=False)]))
+        q, qp, _, _ = efm.collide_points(op, cells[c], idx)
+        scale = np.abs(qp).max()
+        d_fused = np.abs(qt - qf).max() / scale
+        err = np.abs(qt.ravel()[idx] - q).max() / scale
+        say(f"  cell {c}: vs fused {d_fused:.2e} of the gain, vs oracle {err:.2e}")
+        assert np.all(np.isfinite(qt)) and d_fused <= 1e-14 and err <= TOL[prec]
