@@ -218,7 +218,10 @@ int ec_batch_offsets(const ec_batch* batch, int64_t* offsets);
  * cache size); the autotuner picks measured values.  A new batch starts 3D
  * groups on the term-parallel schedule up to its measured crossover with the
  * fused one (FP64 / FP32: N = 16 192 / 192 cells, N = 24 64 / 80, N = 32
- * 56 / 40), larger groups on the fused schedule where it exists, other 3D
+ * 48 / 40), larger groups on the fused schedule where it exists (default
+ * split by cells per launch: 4 at 32^3 up to a quarter of the CU count,
+ * 2 at 24^3 where two workgroups per cell fill one round over the CUs and
+ * three do not, else 1 at 16^3, 3 at 24^3 and 2 at 32^3), other 3D
  * groups of N <= 32 below 32 cells on the pipelined schedule, and the rest
  * on the two-pass schedule.
  * Reallocates the workspace (synchronises the device); call it outside

@@ -136,15 +136,41 @@ int terms_default_split(int N, int precision) {
 // Largest group that starts on the term-parallel schedule: its time grows
 // with the cell count while the fused schedule's stays about flat until
 // its workgroups fill the CUs; measured crossovers (FP64 / FP32): 16^3
-// 192 / 192 cells, 24^3 64 / 80, 32^3 56 / 40.  0: no term-parallel default.
+// 192 / 192 cells, 24^3 64 / 80, 32^3 48 / 40.  0: no term-parallel default.
 int64_t terms_default_max_cells(int N, int precision) {
   const bool fp64 = precision == EC_FP64;
   switch (N) {
     case 16: return 192;
     case 24: return fp64 ? 64 : 80;
-    case 32: return fp64 ? 56 : 40;
+    case 32: return fp64 ? 48 : 40;
     default: return 0;
   }
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return 256;
+  return cus;
+}
+
+// Fused split for launches of `cells` cells: the default split, unless its
+// workgroups (one per CU at these sizes) leave CUs idle in a launch that a
+// larger split fills in one round (32^3: split 4 up to CUs / 4 cells), or
+// need a second round that split 2 avoids (24^3: where 2 workgroups per
+// cell fit one round over the CUs and 3 do not).  Measured on 256 CUs:
+// 41-64 cells of 32^3 9-14 %
+// (FP64) and 8-10 % (FP32) faster at split 4; 96 and 128 cells of 24^3 16 %
+// and 13 % (FP64), 4-5 % (FP32) faster at split 2.
+int fused_split_for(int N, int precision, int64_t cells) {
+  const int d = fused_default_split(N, precision);
+  if (d == 0) return 0;
+  const int64_t cus = device_cus();
+  if (N == 32 && 4 * cells <= cus) return 4;
+  if (N == 24 && 2 * cells <= cus && 3 * cells > cus) return 2;
+  return d;
 }
 
 void default_schedule(BatchGroup& g, int precision) {
@@ -169,7 +195,7 @@ void default_schedule(BatchGroup& g, int precision) {
   } else if (T.d == 3 && g.mode == EC_SCHED_FUSED) {
     // one spectrum per cell of workspace; 2048 cells keep >= 2048 workgroups busy
     g.chunk = (int)std::min<int64_t>(2048, count);
-    g.G = fused_default_split(T.N, precision);
+    g.G = fused_split_for(T.N, precision, g.chunk);
   } else if (T.d == 3 && g.mode == EC_SCHED_PIPELINE) {
     // keep one slot of the per-term intermediates under ~96 MB (the MALL holds
     // the slot being written and the slot being read), then split the terms so

@@ -94,21 +94,31 @@ def test_terms_is_the_small_batch_default_and_validated():
 
 def test_small_batch_defaults_of_other_sizes():
     """Default schedules by group size: term-parallel up to the measured
-    crossover (FP64 / FP32: 16^3 192 / 192 cells, 24^3 64 / 80, 32^3 56 / 40),
-    fused above it, two-pass at 64^3 and for 2D grids (whose groups always
-    run two-pass)."""
+    crossover (FP64 / FP32: 16^3 192 / 192 cells, 24^3 64 / 80, 32^3 48 / 40),
+    fused above it (x split 4 for 32^3 launches of up to CUs / 4 cells, 2 for
+    24^3 launches where 2 workgroups per cell fill one round and 3 do not),
+    two-pass at 64^3 and for 2D grids (whose groups always run two-pass)."""
     say("case small-batch defaults of other sizes")
     T, F = E.EC_SCHED_TERMS, E.EC_SCHED_FUSED
     for N, d, prec, count, want in [
             (16, 3, 0, 2, T), (24, 3, 0, 2, T), (16, 3, 0, 192, T), (16, 3, 0, 193, F),
             (16, 3, 1, 192, T), (16, 3, 1, 193, F), (24, 3, 0, 64, T), (24, 3, 0, 65, F),
-            (24, 3, 1, 80, T), (24, 3, 1, 81, F), (32, 3, 0, 56, T), (32, 3, 0, 57, F),
+            (24, 3, 1, 80, T), (24, 3, 1, 81, F), (32, 3, 0, 48, T), (32, 3, 0, 49, F),
             (32, 3, 1, 40, T), (32, 3, 1, 41, F),
             (64, 3, 0, 2, E.EC_SCHED_TWO_PASS), (32, 2, 0, 2, E.EC_SCHED_TWO_PASS)]:
         p = E.Plan(N, d, L, 8, R=R)
         b = E.Batch([p], [count], prec)
         say(f"  N={N} d={d} precision={prec} cells={count}: schedule {b.get_schedule(0)}")
         assert b.get_schedule(0)[0] == want
+        b.close()
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for N, count, split in [(32, cus // 4, 4), (32, cus // 4 + 1, 2), (32, 1024, 2),
+                            (24, cus // 3 + 1, 2), (24, cus // 2, 2), (24, cus // 2 + 1, 3)]:
+        b = E.Batch([E.Plan(N, 3, L, 8, R=R)], [count], E.EC_FP64)
+        b.set_schedule(0, E.EC_SCHED_FUSED, 0, 0)
+        say(f"  fused N={N} cells={count} (CUs {cus}): schedule {b.get_schedule(0)}")
+        assert b.get_schedule(0)[2] == split
         b.close()
 
 
@@ -186,7 +196,7 @@ def test_mixed_small_groups_default_to_terms_and_step_like_fused():
         assert np.all(np.isfinite(qt[c])) and dq <= 1e-14 and df <= 1e-14
 
 
-@pytest.mark.parametrize("Nl,prec,ncell", [(16, 0, 192), (24, 1, 80), (32, 0, 56)])
+@pytest.mark.parametrize("Nl,prec,ncell", [(16, 0, 192), (24, 1, 80), (32, 0, 48)])
 def test_terms_at_the_default_crossover(Nl, prec, ncell):
     """The largest groups that start on the term-parallel schedule (the
     measured crossover with the fused one): every cell against the fused
