@@ -449,6 +449,14 @@ def main():
         one = cells[:1]
         _, _, _, t1_64, _ = time_collide(E, torch, plan, one, E.EC_FP64, reps, 2, False)
         _, _, _, t1_32, _ = time_collide(E, torch, plan, one, E.EC_FP32, reps, 2, False)
+        import synth
+        small_us = {}
+        for Ns in (16, 24):       # one cell of the smaller grids of the mixed-N leg
+            ps = E.Plan(Ns, D, L, M, R=R)
+            one_s = [synth.sample_mixture(synth.mixture_anisotropic(2001, D), Ns, L)]
+            bs, _, _, ts, _ = time_collide(E, torch, ps, one_s, E.EC_FP64, reps, 2, False)
+            small_us[f"n{Ns}_fp64_us"] = ts / reps * 1e6
+            bs.close()
 
     out = {
         "metric": METRIC, "value": ev64, "unit": "evals/s", "n_gpus": 1,
@@ -468,7 +476,8 @@ def main():
         out["bf16x3"] = {"value": evb, "ms_per_step": tb / args.steps * 1e3,
                          "roofline": roofline(profb, flops, PEAK_FP32, "bf16x3")}
     if t1_64 is not None:
-        out["single_cell"] = {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6}
+        out["single_cell"] = {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6,
+                              **small_us}
     # the device as it runs: vector FMA throughput measured by ec_valu_probe,
     # beside the published peaks that `roofline.peak` uses
     log("bench: vector-ALU probe")
