@@ -89,36 +89,3 @@ void efm_direct_sum(int d, int N, int T,
     }
     free(diag);
 }
-
-/* The same sum restricted to a list of output modes (used to time a bounded
- * sample of a large cell).  ks: [nk] output mode indices. */
-void efm_direct_sum_some(int d, int N, int T,
-                         const double* c, const double* U, const double* V,
-                         const double* sig, const double* Fr, const double* Fi,
-                         int64_t nk, const int64_t* ks,
-                         double* Gr, double* Gi, double* Lr, double* Li)
-{
-    int64_t n = 1;
-    for (int i = 0; i < d; ++i) n *= N;
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t q = 0; q < nk; ++q) {
-        int64_t k = ks[q];
-        nsum gr = {0, 0}, gi = {0, 0}, lr = {0, 0}, li = {0, 0};
-        for (int64_t l = 0; l < n; ++l) {
-            int64_t m = sub_index(k, l, d, N);
-            double b = 0.0, bd = 0.0;
-            const double* ul = U + l * T;
-            const double* um = U + m * T;
-            const double* vm = V + m * T;
-            for (int t = 0; t < T; ++t) { b += c[t] * ul[t] * vm[t]; bd += c[t] * um[t] * vm[t]; }
-            b *= sig[l] * sig[m];
-            bd *= sig[m] * sig[m];
-            double pr = Fr[l] * Fr[m] - Fi[l] * Fi[m];
-            double pi = Fr[l] * Fi[m] + Fi[l] * Fr[m];
-            nadd(&gr, b * pr);  nadd(&gi, b * pi);
-            nadd(&lr, bd * pr); nadd(&li, bd * pi);
-        }
-        Gr[q] = gr.s + gr.c; Gi[q] = gi.s + gi.c;
-        Lr[q] = lr.s + lr.c; Li[q] = li.s + li.c;
-    }
-}

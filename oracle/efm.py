@@ -337,7 +337,7 @@ def hankel_disk(q: np.ndarray, rho: float, a: float, R: float, bcos=None) -> np.
 
 
 def lowrank_3d_vhs(N: int, L: float, R: float, M: int, gamma: float, n_radial: int,
-                   truncation: str = "box", bcos=None) -> LowRank:
+                   truncation: str = "box", bcos=None, modes=None) -> LowRank:
     """Variable hard spheres B = C_3 |g|^gamma in 3D: Carleman weight
     Bt(y, z) = 2^2 C_3 (|y|^2 + |z|^2)^a with a = (gamma - 1)/2 (section 1),
     which does not factor in (|y|, |z|).  The polar form of the 3D kernel
@@ -360,8 +360,12 @@ def lowrank_3d_vhs(N: int, L: float, R: float, M: int, gamma: float, n_radial: i
 
     bcos: an angular factor B = C_3 |g|^gamma b(cos theta), b a polynomial
     (coefficients of 1, x, x^2, ...), inside the radial weight of phi_{t,j}
-    (cos theta = (rho^2 - r^2)/(rho^2 + r^2), see hankel_disk)."""
-    kx, ky, kz = mode_grid(N, 3)
+    (cos theta = (rho^2 - r^2)/(rho^2 + r^2), see hankel_disk).
+
+    modes: optional (3, P) integer mode vectors at which to evaluate U and V
+    (default: every mode of the grid, in the order of mode_grid).  The
+    quadratures are sized by the largest frequency among the given modes."""
+    kx, ky, kz = mode_grid(N, 3) if modes is None else (np.asarray(m, float) for m in modes)
     dirs, w = directions_3d(M)
     bt = 4.0 * C_D[3]
     a = 0.5 * (gamma - 1.0)
@@ -526,8 +530,6 @@ def _load():
         _lib = ctypes.CDLL(_LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
         _lib.efm_direct_sum.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [dp] * 10
-        _lib.efm_direct_sum_some.argtypes = ([ctypes.c_int, ctypes.c_int, ctypes.c_int] + [dp] * 7
-                                             + [ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)] + [dp] * 4)
     return _lib
 
 
@@ -585,22 +587,6 @@ def collide_dense(B: np.ndarray, sigma: np.ndarray, F: np.ndarray, L: float) -> 
         pr = Fh * Fh[m]
         Qh[k] = np.dot(Bs[ar, m] - diag[m], pr)
     return idft(Qh.reshape((N,) * d), L).real
-
-
-def collide_modes_some(plan: Plan, F: np.ndarray, ks: np.ndarray):
-    """Gain and loss Fourier coefficients at a subset of output modes."""
-    lib = _load()
-    Fh = dft(F, plan.L).ravel()
-    Fr = np.ascontiguousarray(Fh.real); Fi = np.ascontiguousarray(Fh.imag)
-    U = np.ascontiguousarray(plan.lr.U.T); V = np.ascontiguousarray(plan.lr.V.T)
-    c = np.ascontiguousarray(plan.lr.c); sig = np.ascontiguousarray(plan.sigma)
-    ks = np.ascontiguousarray(ks, dtype=np.int64)
-    Gr, Gi, Lr, Li = (np.empty(ks.size) for _ in range(4))
-    lib.efm_direct_sum_some(plan.d, plan.N, len(c), _p(c), _p(U), _p(V), _p(sig),
-                            _p(Fr), _p(Fi), ctypes.c_int64(ks.size),
-                            ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                            _p(Gr), _p(Gi), _p(Lr), _p(Li))
-    return Gr + 1j * Gi, Lr + 1j * Li
 
 
 def collision_frequency(plan: Plan, F: np.ndarray) -> np.ndarray:

@@ -89,6 +89,31 @@ def test_mass_and_h_theorem(d, N, M, L):
         assert c.imag_max < 1e-14 * np.abs(c.Qplus).max()
 
 
+@pytest.mark.parametrize("d,N,M,L", [(2, 16, 8, 8.0), (2, 10, 4, 8.0), (3, 8, 8, 8.0), (3, 6, 8, 8.0)])
+def test_unfiltered_even_n_zeroing_pins_mass(d, N, M, L):
+    """The unfiltered method (sigma = 1) on even N: section 4.1 reduces even N
+    to the odd N - 1 case by zeroing the kernel on modes with a component
+    -N/2.  With that zeroing the discrete mass is conserved exactly (Theorem
+    1, eq. conservationMass: Qhat_0 = 0 needs B(-m, m) = B(m, m), and -m of a
+    mode with a component -N/2 wraps to itself mod N).  Keeping those modes
+    breaks it: a planted sigma = 1 everywhere must lose mass."""
+    p = efm.make_plan(N, d, L, M, R=R, filtered=False)
+    # the zeroed modes are exactly those with some component -N/2
+    kl = np.array(efm.mode_grid(N, d))
+    has_edge = np.any(kl == -(N // 2), axis=0)
+    assert np.all(p.sigma[has_edge] == 0.0) and np.all(p.sigma[~has_edge] == 1.0)
+    for seed in range(2):
+        F = synth.sample_mixture(synth.mixture_anisotropic(300 + seed, d), N, L)
+        c = efm.collide_modes(p, F)
+        m = efm.monitors(p, F, c.Q)
+        assert abs(m["sumQ"]) <= 1e-13 * m["sumabsQ"]
+        # the planted mistake: no zeroing of the -N/2 modes
+        bad = efm.Plan(p.N, p.d, p.L, p.R, p.M, p.kind, np.ones(p.n), p.lr)
+        cb = efm.collide_modes(bad, F)
+        mb = efm.monitors(bad, F, cb.Q)
+        assert abs(mb["sumQ"]) > 1e-6 * mb["sumabsQ"]
+
+
 def test_gain_nonnegative_where_f_vanishes():
     """Proof of Theorem 1: where F_r = 0, dF_r/dt = sum A F_p F_q >= 0."""
     N, L = 16, 8.0
