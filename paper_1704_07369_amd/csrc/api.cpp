@@ -93,7 +93,12 @@ struct StepGraph {
   double dt = 0.0;
   double* mon = nullptr;
   int method = 0;      // 0 forward Euler, 1 SSP-RK3
+  int steps = 0;       // time steps recorded in the graph
 };
+
+// Most time steps one captured graph holds; longer runs launch it repeatedly
+// (and a second graph for the remainder).
+constexpr int kGraphMaxSteps = 200;
 
 struct ProfRec {
   int group;
@@ -119,7 +124,8 @@ struct ec_batch {
   void* d_ws = nullptr;     // workspace shared by the groups (one at a time)
   size_t ws_bytes = 0;
   int* d_step = nullptr;
-  StepGraph graph;
+  StepGraph graph;          // kGraphMaxSteps steps (or all of a shorter run)
+  StepGraph tail;           // the remainder of a longer run
   double* d_rk = nullptr;   // SSP-RK3 stage states: 2 x n_elems (allocated on first use)
 };
 
@@ -254,13 +260,47 @@ size_t group_ws_bytes(const BatchGroup& g, int precision) {
   return bytes;
 }
 
-int alloc_workspaces(ec_batch* b) {
+size_t batch_ws_bytes(const ec_batch* b) {
   size_t need = 0;
   for (auto& g : b->groups) need = std::max(need, group_ws_bytes(g, b->precision));
-  if (b->d_ws) { (void)hipFree(b->d_ws); b->d_ws = nullptr; }
+  return need;
+}
+
+// Sizes the shared workspace for the groups' current schedules.  The new
+// buffer is allocated before the old one is released, so on failure the
+// batch keeps a valid workspace of the old size (the caller restores the old
+// schedules).  A buffer that is large enough is kept unless it is more than
+// twice what is needed.
+int alloc_workspaces(ec_batch* b) {
+  const size_t need = batch_ws_bytes(b);
+  if (b->d_ws && need <= b->ws_bytes && 2 * need >= b->ws_bytes) return EC_OK;
+  if (need == 0) {
+    if (b->d_ws) (void)hipFree(b->d_ws);
+    b->d_ws = nullptr;
+    b->ws_bytes = 0;
+    return EC_OK;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, need) != hipSuccess) {
+    (void)hipGetLastError();
+    if (b->d_ws && need <= b->ws_bytes) return EC_OK;   // the larger old buffer still serves
+    return fail(EC_ERR_OOM, "workspace");
+  }
+  if (b->d_ws) (void)hipFree(b->d_ws);
+  b->d_ws = p;
   b->ws_bytes = need;
-  if (need && hipMalloc(&b->d_ws, need) != hipSuccess) return fail(EC_ERR_OOM, "workspace");
   return EC_OK;
+}
+
+// Device memory that a schedule change could still obtain: what is free now
+// (the old workspace stays allocated while the new one is created).
+size_t device_free_bytes() {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return (size_t)-1;
+  }
+  return fr;
 }
 
 char* align256(char* p) { return (char*)(((uintptr_t)p + 255) & ~(uintptr_t)255); }
@@ -273,7 +313,9 @@ void release_prof(ec_batch* b) {
 
 void drop_graph(ec_batch* b) {
   if (b->graph.exec) (void)hipGraphExecDestroy(b->graph.exec);
+  if (b->tail.exec) (void)hipGraphExecDestroy(b->tail.exec);
   b->graph = StepGraph{};
+  b->tail = StepGraph{};
 }
 
 hipEvent_t take_event(ec_batch* b) {
@@ -437,6 +479,8 @@ int run_group(ec_batch* b, int gi, const double* f, double* Q, double dt, hipStr
 
 int run_collide(ec_batch* b, const double* f, double* Q, double dt, hipStream_t s,
                 bool profile = false) {
+  if (!b->d_ws && batch_ws_bytes(b) > 0)
+    return fail(EC_ERR_OOM, "the batch has no workspace (an earlier allocation failed)");
   for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
     if (b->groups[gi].count == 0) continue;
     int rc = run_group(b, gi, f, Q, dt, s, profile);
@@ -492,6 +536,24 @@ int ec_host_tables(int N, int d, double L, const ec_kernel* kernel, int M, int* 
     if (rc) return fail(rc, err);
     if (n_terms) *n_terms = T.terms;
     if (gamma) std::memcpy(gamma, T.gamma.data(), T.gamma.size() * sizeof(double));
+    return EC_OK;
+  });
+}
+
+int ec_host_table_modes(int N, int d, double L, const ec_kernel* kernel, int M, int64_t n_modes,
+                        const int64_t* modes, int* n_terms, double* gamma) {
+  return guarded([&]() -> int {
+    if (!kernel) return fail(EC_ERR_ARG, "kernel is null");
+    if (n_modes < 0 || (n_modes > 0 && !modes)) return fail(EC_ERR_ARG, "bad mode list");
+    HostTables T;
+    std::vector<double> out;
+    std::string err;
+    int rc = build_table_modes(N, d, L, kernel->kind, kernel->gamma, kernel->R, kernel->n_radial,
+                               kernel->unfiltered, kernel->truncation, kernel->n_bcos,
+                               kernel->bcos, M, n_modes, modes, T, out, err);
+    if (rc) return fail(rc, err);
+    if (n_terms) *n_terms = T.terms;
+    if (gamma) std::memcpy(gamma, out.data(), out.size() * sizeof(double));
     return EC_OK;
   });
 }
@@ -677,6 +739,11 @@ int ec_batch_set_schedule(ec_batch* b, int group, int mode, int cells_per_pass, 
         mode != EC_SCHED_LINES && mode != EC_SCHED_TERMS)
       return fail(EC_ERR_ARG, "bad mode");
     BatchGroup& g = b->groups[group];
+    const BatchGroup saved = g;
+    auto restore = [&](int rc) {
+      g = saved;
+      return rc;
+    };
     if (mode == EC_SCHED_TERMS &&
         (g.plan->host.d != 3 ||
          !terms_supported(g.plan->host.N, b->precision,
@@ -694,17 +761,18 @@ int ec_batch_set_schedule(ec_batch* b, int group, int mode, int cells_per_pass, 
     if (term_groups > 0 && use_pipe(g)) g.G = std::min(term_groups, g.plan->host.J);
     if (term_groups > 0 && use_fused(g)) {
       if (!fused_supported(g.plan->host.N, b->precision, term_groups))
-        return fail(EC_ERR_UNSUPPORTED, "unsupported x split for the fused schedule");
+        return restore(fail(EC_ERR_UNSUPPORTED, "unsupported x split for the fused schedule"));
       g.G = term_groups;
     }
     if (term_groups > 0 && use_terms(g)) {
       if (!terms_supported(g.plan->host.N, b->precision, term_groups))
-        return fail(EC_ERR_UNSUPPORTED, "unsupported x split for the term-parallel schedule");
+        return restore(fail(EC_ERR_UNSUPPORTED, "unsupported x split for the term-parallel schedule"));
       g.G = term_groups;
     }
     drop_graph(b);
-    HIPCHK(hipDeviceSynchronize());
-    return alloc_workspaces(b);
+    if (hipDeviceSynchronize() != hipSuccess) return restore(fail(EC_ERR_DEVICE, "device sync failed"));
+    const int rc = alloc_workspaces(b);
+    return rc ? restore(rc) : EC_OK;
   });
 }
 
@@ -790,8 +858,23 @@ void cache_store(const char* path, const std::string& key, const Sched& s, doubl
   if (outf) outf << key << ' ' << s.mode << ' ' << s.chunk << ' ' << s.G << ' ' << ms << '\n';
 }
 
+// Workspace bytes the batch would need with group gi on schedule s.
+size_t sched_ws_bytes(const ec_batch* b, int gi, const Sched& s) {
+  BatchGroup g = b->groups[gi];
+  g.mode = s.mode;
+  default_schedule(g, b->precision);
+  const int64_t count = std::max<int64_t>(1, g.count);
+  if (s.chunk > 0) g.chunk = (int)std::min<int64_t>(s.chunk, count);
+  if (s.G > 0 && use_pipe(g)) g.G = std::min(s.G, g.plan->host.J);
+  size_t need = group_ws_bytes(g, b->precision);
+  for (int i = 0; i < (int)b->groups.size(); ++i)
+    if (i != gi) need = std::max(need, group_ws_bytes(b->groups[i], b->precision));
+  return need;
+}
+
 int apply_sched(ec_batch* b, int gi, const Sched& s) {
   BatchGroup& g = b->groups[gi];
+  const BatchGroup saved = g;
   g.mode = s.mode;
   default_schedule(g, b->precision);
   const int64_t count = std::max<int64_t>(1, g.count);
@@ -799,7 +882,9 @@ int apply_sched(ec_batch* b, int gi, const Sched& s) {
   if (s.G > 0 && use_pipe(g)) g.G = std::min(s.G, g.plan->host.J);
   if (s.G > 0 && use_fused(g) && fused_supported(g.plan->host.N, b->precision, s.G)) g.G = s.G;
   if (s.G > 0 && use_terms(g) && terms_supported(g.plan->host.N, b->precision, s.G)) g.G = s.G;
-  return alloc_workspaces(b);
+  const int rc = alloc_workspaces(b);
+  if (rc) g = saved;
+  return rc;
 }
 
 int time_group(ec_batch* b, int gi, const double* f, double* Q, hipStream_t st, double& best_ms) {
@@ -885,15 +970,25 @@ int ec_autotune(ec_batch* b, const double* f, double* Q, const char* cache_path,
             cand.push_back(Sched{EC_SCHED_PIPELINE, (int)std::min<int64_t>(c, count), G});
           }
       }
+      // keep a margin of 1/16 of the free memory for the caller; a
+      // candidate whose workspace does not fit is not measured
+      const size_t room = std::max(b->ws_bytes, device_free_bytes() / 16 * 15);
+      std::vector<Sched> fit;
+      for (auto& s : cand)
+        if (sched_ws_bytes(b, gi, s) <= room) fit.push_back(s);
+      if (fit.empty()) return fail(EC_ERR_OOM, "no schedule's workspace fits the free device memory");
       double best_ms = 1e30;
-      for (auto& s : cand) {
+      best = fit[0];
+      for (auto& s : fit) {
         rc = apply_sched(b, gi, s);
+        if (rc == EC_ERR_OOM) continue;   // the old schedule and workspace are kept
         if (rc) return rc;
         double ms;
         rc = time_group(b, gi, f, Q, st, ms);
         if (rc) return rc;
         if (ms < best_ms) { best_ms = ms; best = s; }
       }
+      if (best_ms >= 1e30) return fail(EC_ERR_OOM, "no candidate schedule's workspace could be allocated");
       rc = apply_sched(b, gi, best);
       if (rc) return rc;
       cache_store(cache_path, key, best, best_ms);
@@ -1050,10 +1145,52 @@ int record_step(ec_batch* b, double* f, double dt, int method, double* monitors,
   return rc;
 }
 
+// Captures `steps` consecutive time steps into one graph (g), unless g
+// already holds exactly that.
+int capture_steps(ec_batch* b, StepGraph& g, double* f, double dt, double* monitors, int method,
+                  int steps) {
+  if (g.exec && g.f == f && g.dt == dt && g.mon == monitors && g.method == method &&
+      g.steps == steps)
+    return EC_OK;
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g = StepGraph{};
+  hipStream_t cap_stream;
+  HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+  int rc = EC_OK;
+  if (e == hipSuccess) {
+    for (int k = 0; k < steps && rc == EC_OK; ++k)
+      rc = record_step(b, f, dt, method, monitors, cap_stream);
+    hipError_t e3 = hipStreamEndCapture(cap_stream, &graph);
+    if (rc == EC_OK && e3 != hipSuccess) rc = fail(EC_ERR_DEVICE, hipGetErrorString(e3));
+  } else {
+    rc = fail(EC_ERR_DEVICE, hipGetErrorString(e));
+  }
+  if (rc == EC_OK) {
+    hipError_t e4 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e4 != hipSuccess) {
+      g.exec = nullptr;
+      rc = fail(EC_ERR_DEVICE, hipGetErrorString(e4));
+    }
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap_stream);
+  if (rc) return rc;
+  g.f = f;
+  g.dt = dt;
+  g.mon = monitors;
+  g.method = method;
+  g.steps = steps;
+  return EC_OK;
+}
+
 int run_steps(ec_batch* b, double* f, double dt, int n_steps, double* monitors, int method,
               hipStream_t s) {
   if (n_steps < 0 || !(dt > 0.0)) return fail(EC_ERR_ARG, "need dt > 0 and n_steps >= 0");
   if (n_steps == 0) return EC_OK;
+  if (!b->d_ws && batch_ws_bytes(b) > 0)
+    return fail(EC_ERR_OOM, "the batch has no workspace (an earlier allocation failed)");
   if (method == 1 && !b->d_rk) {
     HIPCHK(hipDeviceSynchronize());
     void* p = nullptr;
@@ -1061,38 +1198,21 @@ int run_steps(ec_batch* b, double* f, double dt, int n_steps, double* monitors, 
       return fail(EC_ERR_OOM, "SSP-RK3 stage buffers");
     b->d_rk = (double*)p;
   }
-  if (!(b->graph.exec && b->graph.f == f && b->graph.dt == dt && b->graph.mon == monitors &&
-        b->graph.method == method)) {
+  // up to kGraphMaxSteps steps in one graph; a longer run launches it
+  // repeatedly and a second graph for the remainder
+  const int K = std::min(n_steps, kGraphMaxSteps);
+  const int full = n_steps / K, rest = n_steps % K;
+  int rc = capture_steps(b, b->graph, f, dt, monitors, method, K);
+  if (rc == EC_OK && rest) rc = capture_steps(b, b->tail, f, dt, monitors, method, rest);
+  if (rc) {
     drop_graph(b);
-    // capture one step; replays advance the device step counter
-    hipStream_t cap_stream;
-    HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-    int rc2 = EC_OK;
-    if (e == hipSuccess) {
-      rc2 = record_step(b, f, dt, method, monitors, cap_stream);
-      hipError_t e3 = hipStreamEndCapture(cap_stream, &graph);
-      if (rc2 == EC_OK && e3 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e3));
-    } else {
-      rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e));
-    }
-    if (rc2 == EC_OK) {
-      hipError_t e4 = hipGraphInstantiate(&b->graph.exec, graph, nullptr, nullptr, 0);
-      if (e4 != hipSuccess) rc2 = fail(EC_ERR_DEVICE, hipGetErrorString(e4));
-    }
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipStreamDestroy(cap_stream);
-    if (rc2) { drop_graph(b); return rc2; }
-    b->graph.f = f;
-    b->graph.dt = dt;
-    b->graph.mon = monitors;
-    b->graph.method = method;
+    return rc;
   }
   // step counter and the capacity of the monitor buffer (in steps)
   HIPCHK(launch_set_int(b->d_step, 0, s));
   HIPCHK(launch_set_int(b->d_step + 1, monitors ? n_steps : 0, s));
-  for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(b->graph.exec, s));
+  for (int k = 0; k < full; ++k) HIPCHK(hipGraphLaunch(b->graph.exec, s));
+  if (rest) HIPCHK(hipGraphLaunch(b->tail.exec, s));
   return EC_OK;
 }
 
@@ -1106,6 +1226,11 @@ int ec_step(ec_batch* b, double* f, double dt, int n_steps, double* monitors, vo
     if (rc) return rc;
     return run_steps(b, f, dt, n_steps, monitors, 0, (hipStream_t)stream);
   });
+}
+
+int ec_step_graph(ec_batch* b, double* f, double dt, int n_steps, double* monitors,
+                  void* stream) {
+  return ec_step(b, f, dt, n_steps, monitors, stream);
 }
 
 int ec_step_ssprk3(ec_batch* b, double* f, double dt, int n_steps, double* monitors,

@@ -428,6 +428,11 @@ int ec_surrogate_train_step(ec_surrogate* s, const float* Fin, const float* targ
   });
 }
 
+int ec_surrogate_train(ec_surrogate* s, const float* Fin, const float* target, int B, float lr,
+                       int update, double* loss, void* stream) {
+  return ec_surrogate_train_step(s, Fin, target, B, lr, update, loss, stream);
+}
+
 int ec_surrogate_prepare(ec_surrogate* s, const ec_batch* batch, const double* f, const double* Q,
                          int64_t cell0, int B, float* Fin, float* target, void* stream) {
   return sguard([&]() -> int {
@@ -465,9 +470,16 @@ int ec_surrogate_collide(ec_surrogate* s, ec_batch* batch, const double* f, doub
       if (s->d_screen) (void)hipFree(s->d_screen);
       if (s->d_idx) (void)hipFree(s->d_idx);
       s->d_flag = nullptr; s->d_screen = nullptr; s->d_idx = nullptr;
-      SCHK(hipMalloc(&s->d_flag, ncell * sizeof(int32_t)));
-      SCHK(hipMalloc(&s->d_screen, ncell * 4 * sizeof(double)));
-      SCHK(hipMalloc(&s->d_idx, ncell * sizeof(int64_t)));
+      s->scap = 0;
+      if (hipMalloc(&s->d_flag, ncell * sizeof(int32_t)) != hipSuccess ||
+          hipMalloc(&s->d_screen, ncell * 4 * sizeof(double)) != hipSuccess ||
+          hipMalloc(&s->d_idx, ncell * sizeof(int64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (s->d_flag) (void)hipFree(s->d_flag);
+        if (s->d_screen) (void)hipFree(s->d_screen);
+        s->d_flag = nullptr; s->d_screen = nullptr; s->d_idx = nullptr;
+        return set_error(EC_ERR_OOM, "screen buffers");
+      }
       s->scap = ncell;
     }
     for (int64_t c0 = 0; c0 < ncell; c0 += s->maxB) {
@@ -500,11 +512,22 @@ int ec_surrogate_collide(ec_surrogate* s, ec_batch* batch, const double* f, doub
         s->d_fc = s->d_qc = nullptr;
         const ec_plan* plans[1] = {batch_group_plan(batch, 0)};
         int64_t counts[1] = {ncell};
+        s->fb_cap = 0;
         int rc = ec_batch_create(plans, counts, 1, EC_FP64, &s->fb);
-        if (rc) return rc;
-        s->fb_cap = ncell;
-        SCHK(hipMalloc(&s->d_fc, batch_elems(s->fb) * sizeof(double)));
-        SCHK(hipMalloc(&s->d_qc, batch_elems(s->fb) * sizeof(double)));
+        if (rc) {
+          s->fb = nullptr;
+          return rc;
+        }
+        if (hipMalloc(&s->d_fc, batch_elems(s->fb) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&s->d_qc, batch_elems(s->fb) * sizeof(double)) != hipSuccess) {
+          (void)hipGetLastError();
+          if (s->d_fc) (void)hipFree(s->d_fc);
+          s->d_fc = nullptr;
+          ec_batch_destroy(s->fb);
+          s->fb = nullptr;
+          return set_error(EC_ERR_OOM, "fallback buffers");
+        }
+        s->fb_cap = ncell;   // only once every buffer of that capacity exists
       }
       SCHK(hipMemcpyAsync(s->d_idx, idx.data(), k * sizeof(int64_t), hipMemcpyHostToDevice, st));
       const int64_t tot = k * s->n;
