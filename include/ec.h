@@ -174,6 +174,19 @@ int ec_host_tables(int N, int d, double L, const ec_kernel* kernel, int M,
                    int* n_terms, double* gamma /* may be NULL to query */);
 
 /*
+ * ec_host_table_modes -- the same table entries at a list of modes only
+ * (host only), for checking plans whose full tables are large.
+ *   modes: [n_modes] flat mode indices in the table layout of
+ *   ec_plan_tables, idx = (k0 N + k2) N + k1 (d = 2: k2 N + k1), each in
+ *   [0, N^d); out of range -> EC_ERR_ARG.
+ *   gamma: [M'+1][n_modes] complex (re, im) FP64 pairs, caller-owned,
+ *   2 (M'+1) n_modes doubles; may be NULL to query n_terms.
+ */
+int ec_host_table_modes(int N, int d, double L, const ec_kernel* kernel, int M,
+                        int64_t n_modes, const int64_t* modes, int* n_terms,
+                        double* gamma);
+
+/*
  * ec_batch_create -- a packed batch of cells grouped by plan.
  *   plans[g], counts[g]: group g holds counts[g] cells of plans[g] (the plans
  *   must stay alive while the batch exists).
@@ -292,12 +305,22 @@ int ec_monitors(ec_batch* batch, const double* f, const double* Q, double* out,
                 void* hip_stream);
 
 /*
- * ec_step -- n_steps forward-Euler steps F <- F + dt Q^s[F] of the EFM ODE
- * (section 3.3, eq. modifiedIVP), in place on f, captured once into a HIP
- * graph and replayed.  If monitors != NULL it receives, per step and cell,
- * (mass, eta) of the state after the step: monitors[(s * n_cells + c) * 2 + i].
- * Positivity is kept when dt max_r l_r <= 1 (proof of Theorem 1).
+ * ec_step_graph -- n_steps forward-Euler steps F <- F + dt Q^s[F] of the EFM
+ * ODE (section 3.3, eq. modifiedIVP), in place on f.  The steps are captured
+ * into one HIP graph (every step's kernels and monitors as graph nodes, up to
+ * 200 steps per graph; a longer run launches that graph repeatedly and a
+ * second graph for the remainder) and launched on hip_stream; the graphs are
+ * kept and reused while (f, dt, monitors, n_steps) stay the same.  The first
+ * call for new arguments captures and instantiates (no device allocation);
+ * later calls only launch.  If monitors != NULL it receives, per step and
+ * cell, (mass, eta) of the state after the step:
+ * monitors[(s * n_cells + c) * 2 + i], device memory of n_steps * n_cells * 2
+ * doubles owned by the caller.  Positivity is kept when dt max_r l_r <= 1
+ * (proof of Theorem 1).  Errors: EC_ERR_ARG for dt <= 0 or n_steps < 0.
+ * ec_step is the same call under its earlier name.
  */
+int ec_step_graph(ec_batch* batch, double* f, double dt, int n_steps,
+                  double* monitors, void* hip_stream);
 int ec_step(ec_batch* batch, double* f, double dt, int n_steps,
             double* monitors, void* hip_stream);
 
@@ -306,7 +329,7 @@ int ec_step(ec_batch* batch, double* f, double dt, int n_steps,
  * preserving Runge-Kutta method (the time integrator of the paper's numerical
  * experiments, section 4; Shu-Osher form: u1 = f + dt Q(f), u2 = 3/4 f +
  * 1/4 (u1 + dt Q(u1)), f <- 1/3 f + 2/3 (u2 + dt Q(u2))), in place on f,
- * with the same graph replay, monitors and arguments as ec_step.  Each step
+ * with the same graphs, monitors and arguments as ec_step_graph.  Each step
  * is a convex combination of forward-Euler steps, so the positivity condition
  * of ec_step applies per stage.  The first call allocates two stage buffers
  * of the batch's size (synchronises the device; call it outside capture).
@@ -379,6 +402,9 @@ int ec_surrogate_forward(ec_surrogate* s, const float* Fin, float* y, int B, voi
 /* One forward + backward (per-sample relative squared error, averaged) and,
  * if update != 0, one Adam step (lr, beta 0.9/0.999).  If loss != NULL the
  * mean loss is returned (synchronises the stream). */
+int ec_surrogate_train(ec_surrogate* s, const float* Fin, const float* target, int B,
+                       float lr, int update, double* loss, void* hip_stream);
+/* The same call under its earlier name. */
 int ec_surrogate_train_step(ec_surrogate* s, const float* Fin, const float* target, int B,
                             float lr, int update, double* loss, void* hip_stream);
 /* Screened inference on a batch (one group of 3D cells of the surrogate's N):

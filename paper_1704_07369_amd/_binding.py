@@ -52,6 +52,9 @@ _SIGS = {
     "ec_plan_tables": ([_vp, ctypes.POINTER(_c_double)], _c_int),
     "ec_host_tables": ([_c_int, _c_int, _c_double, ctypes.POINTER(ec_kernel), _c_int,
                         ctypes.POINTER(_c_int), ctypes.POINTER(_c_double)], _c_int),
+    "ec_host_table_modes": ([_c_int, _c_int, _c_double, ctypes.POINTER(ec_kernel), _c_int, _c_i64,
+                             ctypes.POINTER(_c_i64), ctypes.POINTER(_c_int),
+                             ctypes.POINTER(_c_double)], _c_int),
     "ec_batch_create": ([ctypes.POINTER(_vp), ctypes.POINTER(_c_i64), _c_int, _c_int,
                          ctypes.POINTER(_vp)], _c_int),
     "ec_batch_destroy": ([_vp], _c_int),
@@ -62,6 +65,7 @@ _SIGS = {
     "ec_entropy_prod": ([_vp, _vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_monitors": ([_vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_step": ([_vp, _vp, _c_double, _c_int, _vp, _vp], _c_int),
+    "ec_step_graph": ([_vp, _vp, _c_double, _c_int, _vp, _vp], _c_int),
     "ec_step_ssprk3": ([_vp, _vp, _c_double, _c_int, _vp, _vp], _c_int),
     "ec_batch_set_schedule": ([_vp, _c_int, _c_int, _c_int, _c_int], _c_int),
     "ec_batch_get_schedule": ([_vp, _c_int, ctypes.POINTER(_c_int), ctypes.POINTER(_c_int),
@@ -80,6 +84,8 @@ _SIGS = {
     "ec_surrogate_forward": ([_vp, _vp, _vp, _c_int, _vp], _c_int),
     "ec_surrogate_train_step": ([_vp, _vp, _vp, _c_int, ctypes.c_float, _c_int,
                                  ctypes.POINTER(_c_double), _vp], _c_int),
+    "ec_surrogate_train": ([_vp, _vp, _vp, _c_int, ctypes.c_float, _c_int,
+                            ctypes.POINTER(_c_double), _vp], _c_int),
     "ec_surrogate_collide": ([_vp, _vp, _vp, _vp, _c_double, _c_double, _vp, _vp,
                               ctypes.POINTER(_c_i64), _vp], _c_int),
     "ec_profile": ([_vp, _c_int], _c_int),
@@ -195,6 +201,20 @@ def ec_host_tables(N, d, L, kernel, M):
     return (out[0::2] + 1j * out[1::2]).reshape(t.value + 1, n)
 
 
+def ec_host_table_modes(N, d, L, kernel, M, modes):
+    """Table entries [M'+1][len(modes)] at flat mode indices of the table
+    layout (ec_plan_tables)."""
+    idx = np.ascontiguousarray(modes, dtype=np.int64)
+    t = _c_int()
+    _check(lib().ec_host_table_modes(N, d, L, ctypes.byref(kernel), M, 0, None, ctypes.byref(t),
+                                     None))
+    out = np.empty(2 * (t.value + 1) * idx.size)
+    _check(lib().ec_host_table_modes(N, d, L, ctypes.byref(kernel), M, idx.size,
+                                     idx.ctypes.data_as(ctypes.POINTER(_c_i64)), ctypes.byref(t),
+                                     out.ctypes.data_as(ctypes.POINTER(_c_double))))
+    return (out[0::2] + 1j * out[1::2]).reshape(t.value + 1, idx.size)
+
+
 def ec_batch_create(plans, counts, precision=EC_FP64):
     n = len(plans)
     pa = (_vp * n)(*plans)
@@ -236,6 +256,11 @@ def ec_entropy_prod(batch, f, Q, out, n_nonpos=None, stream=None):
 
 def ec_monitors(batch, f, Q, out, stream=None):
     return _check(lib().ec_monitors(batch, _ptr(f), _ptr(Q), _ptr(out), _stream(stream)))
+
+
+def ec_step_graph(batch, f, dt, n_steps, monitors=None, stream=None):
+    return _check(lib().ec_step_graph(batch, _ptr(f), dt, n_steps, _ptr(monitors),
+                                      _stream(stream)))
 
 
 def ec_step(batch, f, dt, n_steps, monitors=None, stream=None):
@@ -328,6 +353,13 @@ def ec_surrogate_prepare(s, batch, f, Q, cell0, B, Fin, target, stream=None):
 
 def ec_surrogate_forward(s, Fin, y, B, stream=None):
     return _check(lib().ec_surrogate_forward(s, _ptr(Fin), _ptr(y), B, _stream(stream)))
+
+
+def ec_surrogate_train(s, Fin, target, B, lr, update=True, want_loss=True, stream=None):
+    loss = _c_double(float("nan"))
+    _check(lib().ec_surrogate_train(s, _ptr(Fin), _ptr(target), B, lr, 1 if update else 0,
+                                    ctypes.byref(loss) if want_loss else None, _stream(stream)))
+    return loss.value
 
 
 def ec_surrogate_train_step(s, Fin, target, B, lr, update=True, want_loss=True, stream=None):

@@ -86,10 +86,10 @@ class Batch:
         B.ec_monitors(self.handle, f, Q, out, stream)
 
     def step(self, f, dt, n_steps, monitors=None, stream=None, method="euler"):
-        """n_steps time steps in place on f: method "euler" (ec_step) or
+        """n_steps time steps in place on f: method "euler" (ec_step_graph) or
         "ssprk3" (ec_step_ssprk3)."""
         if method == "euler":
-            B.ec_step(self.handle, f, dt, n_steps, monitors, stream)
+            B.ec_step_graph(self.handle, f, dt, n_steps, monitors, stream)
         elif method == "ssprk3":
             B.ec_step_ssprk3(self.handle, f, dt, n_steps, monitors, stream)
         else:

@@ -325,13 +325,8 @@ int build_spec(int N, int d, double L, int kind, double gamma_exp, double R, int
   return EC_OK;
 }
 
-int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
-                 int n_radial, int unfiltered, int truncation, int n_bcos, const double* bcos,
-                 int M, HostTables& T, std::string& err) {
-  TableSpec S;
-  const int rc = build_spec(N, d, L, kind, gamma_exp, R, n_radial, unfiltered, truncation,
-                            n_bcos, bcos, M, T, S, err);
-  if (rc) return rc;
+namespace {
+TableView make_view(const TableSpec& S) {
   TableView V;
   V.N = S.N; V.d = S.d; V.M = S.M; V.nrad = S.nrad; V.radial = S.radial ? 1 : 0;
   V.n = S.n; V.J = S.J; V.R = S.R; V.kf = S.kf; V.scale = S.scale; V.qmax = S.qmax;
@@ -339,6 +334,37 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
   V.px = S.px.data(); V.py = S.py.data(); V.wt = S.wt.data();
   V.rho = S.rho.data(); V.om = S.om.data();
   V.cheb = S.cheb.data(); V.cheb_off = S.cheb_off.data(); V.sig1 = S.sig1.data();
+  return V;
+}
+}  // namespace
+
+int build_table_modes(int N, int d, double L, int kind, double gamma_exp, double R,
+                      int n_radial, int unfiltered, int truncation, int n_bcos,
+                      const double* bcos, int M, int64_t n_modes, const int64_t* idx,
+                      HostTables& T, std::vector<double>& out, std::string& err) {
+  TableSpec S;
+  const int rc = build_spec(N, d, L, kind, gamma_exp, R, n_radial, unfiltered, truncation,
+                            n_bcos, bcos, M, T, S, err);
+  if (rc) return rc;
+  for (int64_t i = 0; i < n_modes; ++i)
+    if (idx[i] < 0 || idx[i] >= T.n) {
+      err = "mode index out of range";
+      return EC_ERR_ARG;
+    }
+  const TableView V = make_view(S);
+  out.assign((size_t)2 * T.J * n_modes, 0.0);
+  for (int64_t i = 0; i < n_modes; ++i) fill_mode_at(V, idx[i], n_modes, i, out.data(), nullptr);
+  return EC_OK;
+}
+
+int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
+                 int n_radial, int unfiltered, int truncation, int n_bcos, const double* bcos,
+                 int M, HostTables& T, std::string& err) {
+  TableSpec S;
+  const int rc = build_spec(N, d, L, kind, gamma_exp, R, n_radial, unfiltered, truncation,
+                            n_bcos, bcos, M, T, S, err);
+  if (rc) return rc;
+  const TableView V = make_view(S);
   T.gamma.assign((size_t)2 * T.J * T.n, 0.0);
   double* g = T.gamma.data();
   // modes in parallel on the host threads (each writes its own entries)

@@ -48,6 +48,13 @@ int build_tables(int N, int d, double L, int kind, double gamma_exp, double R,
                  int n_radial, int unfiltered, int truncation, int n_bcos, const double* bcos,
                  int M, HostTables& out, std::string& err);
 
+// build_spec, then the J entries of the listed modes only (flat indices in the
+// table layout, idx = (k0 n2 + k2) n1 + k1): out[(j n_modes + i) * 2 + {0,1}].
+int build_table_modes(int N, int d, double L, int kind, double gamma_exp, double R,
+                      int n_radial, int unfiltered, int truncation, int n_bcos,
+                      const double* bcos, int M, int64_t n_modes, const int64_t* idx,
+                      HostTables& T, std::vector<double>& out, std::string& err);
+
 // Modified Jackson filter (section 3.2.2, eq. JacksonFilter2) for the mode
 // value k of an N-point axis.
 double jackson(int N, int k);

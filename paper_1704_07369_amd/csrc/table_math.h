@@ -83,8 +83,10 @@ TM_HD double tm_cheb(const double* c, int D, double qmax, double q) {
 }
 
 // All J entries of mode idx = ((i0 n2 + i2) n1 + i1) (2D: i0 = 0):
-// g64[(term n + idx) * 2 + {0, 1}] and, when g32 is set, its FP32 copy.
-TM_HD void fill_mode(const TableView& V, int64_t idx, double* g64, float* g32) {
+// g64[(term out_n + out_idx) * 2 + {0, 1}] and, when g32 is set, its FP32
+// copy.  The full table is out_n = n, out_idx = idx (fill_mode).
+TM_HD void fill_mode_at(const TableView& V, int64_t idx, int64_t out_n, int64_t out_idx,
+                        double* g64, float* g32) {
   const int N = V.N;
   auto mode = [N](int i) { return i < (N + 1) / 2 ? i : i - N; };
   int i0 = 0, i1, i2;
@@ -105,7 +107,7 @@ TM_HD void fill_mode(const TableView& V, int64_t idx, double* g64, float* g32) {
     sig = V.sig1[i1] * V.sig1[i2];
   }
   auto put = [&](int64_t term, double re, double im) {
-    const int64_t e = (term * V.n + idx) * 2;
+    const int64_t e = (term * out_n + out_idx) * 2;
     g64[e] = re;
     g64[e + 1] = im;
     if (g32) {
@@ -141,6 +143,10 @@ TM_HD void fill_mode(const TableView& V, int64_t idx, double* g64, float* g32) {
     diag += V.wt[t] * ps * ph;
   }
   put((int64_t)V.J - 1, scale * sig * sig * diag, 0.0);
+}
+
+TM_HD void fill_mode(const TableView& V, int64_t idx, double* g64, float* g32) {
+  fill_mode_at(V, idx, V.n, idx, g64, g32);
 }
 
 }  // namespace efm

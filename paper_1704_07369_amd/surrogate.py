@@ -41,7 +41,7 @@ class Surrogate:
         B.ec_surrogate_forward(self.handle, Fin, y, nb)
 
     def train_step(self, Fin, target, nb, lr, update=True, want_loss=True):
-        return B.ec_surrogate_train_step(self.handle, Fin, target, nb, lr, update, want_loss)
+        return B.ec_surrogate_train(self.handle, Fin, target, nb, lr, update, want_loss)
 
     def collide(self, batch: Batch, f, Q, tau_m=1e-3, tau_e=5e-2, fell_back=None, screen=None):
         return B.ec_surrogate_collide(self.handle, batch.handle, f, Q, tau_m, tau_e, fell_back,

@@ -162,3 +162,54 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert declared <= set(E.binding.exported_symbols())
+
+
+@pytest.mark.parametrize("gamma,trunc", [(0.5, "box")])
+def test_c4_plan_tables_match_oracle_quadrature_on_sampled_modes(gamma, trunc):
+    """The precision-sweep plan itself: 64^3, M = 64 directions x 8 radial
+    nodes (512 products + loss), variable hard spheres gamma = 0.5 (the
+    non-separable radial form of section 4.1, eq. fastAlg).  The full tables
+    are 2 GB, so both sides evaluate the same 211 modes: the corners and
+    edges of the retained band (largest |k_perp|, so both sides size their
+    quadratures and fits for the full range), modes with a -N/2 component
+    (zero), and 200 random modes.  Every product's factorisation
+    N^{2d} alpha_t(k) beta_t(m) = c_t sigma_k U_t(k) sigma_m V_t(m) over all
+    sampled pairs (k, m), and the loss diagonal, to 1e-13 of the largest."""
+    N, M, nr, L = 64, 64, 8, 8.0
+    rng = np.random.default_rng(4)
+    ks = [(31, 31, 31), (-31, 31, 31), (31, -31, -31), (-31, -31, -31), (31, 31, 0),
+          (0, 31, -31), (31, 0, 0), (0, 0, 0), (1, 0, 0), (-32, 5, 3), (0, -32, 0)]
+    ks += [tuple(rng.integers(-32, 32, 3)) for _ in range(200)]
+    k = np.array(ks).T
+    fi = k % N
+    idx = (fi[0] * N + fi[2]) * N + fi[1]          # library layout [k0][k2][k1]
+    kern = E.make_kernel(E.EC_KERNEL_VHS, gamma, R, nr,
+                         truncation=E.EC_TRUNC_BALL if trunc == "ball" else E.EC_TRUNC_BOX)
+    G = E.ec_host_table_modes(N, 3, L, kern, M, idx)
+    assert G.shape == (M * nr + 1, len(ks))
+    lr = efm.lowrank_3d_vhs(N, L, R, M, gamma, nr, truncation=trunc, modes=k)
+    s1 = efm.sigma_1d(N)
+    sig = s1[fi[0]] * s1[fi[1]] * s1[fi[2]]
+    n = N ** 3
+    a, b = G[:-1].real * n, G[:-1].imag * n
+    lib = np.einsum("tk,tm->tkm", a, b)
+    ref = np.einsum("t,tk,tm->tkm", lr.c, sig * lr.U, sig * lr.V)
+    assert np.abs(lib - ref).max() <= 1e-13 * np.abs(ref).max()
+    D = sig ** 2 * lr.diagonal()
+    assert np.abs(G[-1].real * n - D).max() <= 1e-13 * np.abs(D).max()
+    assert np.all(G[-1].imag == 0.0)
+    edge = np.any(k == -N // 2, axis=0)
+    assert np.all(G[:, edge] == 0.0)
+
+
+def test_host_table_modes_equal_full_tables():
+    """The sampled-mode entry point returns the same entries as the full
+    table fill (the same per-mode formulas), and rejects indices out of range."""
+    N, d, L, M = 12, 3, 8.0, 32
+    full = E.ec_host_tables(N, d, L, _kernel(d), M)
+    idx = np.array([0, 5, 77, N ** 3 - 1, 1000])
+    part = E.ec_host_table_modes(N, d, L, _kernel(d), M, idx)
+    assert np.array_equal(part, full[:, idx])
+    with pytest.raises(E.EcError) as ei:
+        E.ec_host_table_modes(N, d, L, _kernel(d), M, np.array([N ** 3]))
+    assert ei.value.code == E.EC_ERR_ARG
