@@ -482,6 +482,10 @@ class Plan:
     kind: str
     sigma: np.ndarray
     lr: LowRank
+    # None: sigma and the low-rank factors cover every mode (mode_grid order).
+    # Otherwise (d, S) integer mode vectors: they cover only these modes, and
+    # the plan serves inputs whose spectrum vanishes off them (collide_points).
+    modes: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -494,11 +498,23 @@ class Plan:
 
 def make_plan(N: int, d: int, L: float, M: int, kind: str | None = None,
               R: float = 6.0, filtered: bool = True, gamma: float | None = None,
-              n_radial: int = 8, truncation: str = "box", bcos=None) -> Plan:
+              n_radial: int = 8, truncation: str = "box", bcos=None, modes=None) -> Plan:
     """kind None: 2D Maxwell / 3D hard spheres.  In 3D, KIND_MAXWELL is the
     variable-hard-sphere kernel with gamma = 0 and KIND_VHS takes gamma; both
     use n_radial radial nodes (M' = M n_radial terms) and either truncation
-    (lowrank_3d_vhs)."""
+    (lowrank_3d_vhs).  modes: optional (d, S) integer mode vectors in [-N/2,
+    N/2) (3D radial kernels only): the plan then holds the filter and the
+    low-rank factors on these modes only, for inputs whose spectrum lives on
+    them (collide_points), so that large grids with many products stay cheap."""
+    if modes is not None:
+        if not (d == 3 and kind in (KIND_MAXWELL, KIND_VHS)):
+            raise NotImplementedError("a mode subset needs the 3D radial (non-separable) path")
+        modes = np.asarray(modes, dtype=np.int64)
+        g = 0.0 if kind == KIND_MAXWELL else float(gamma)
+        lr = lowrank_3d_vhs(N, L, R, M, g, n_radial, truncation, bcos, modes=modes)
+        s1 = sigma_1d(N) if filtered else unfiltered_nd(N, 1)
+        sig = np.prod([s1[m % N] for m in modes], axis=0)
+        return Plan(N, d, L, R, M, kind, sig, lr, modes)
     if kind is None:
         kind = KIND_MAXWELL if d == 2 else KIND_HARD_SPHERE
     if d == 2 and kind == KIND_MAXWELL:
@@ -612,6 +628,21 @@ def collide_points(plan: Plan, F: np.ndarray, idx: np.ndarray):
     """
     Fh = dft(F, plan.L).ravel()
     kl = mode_grid(plan.N, plan.d)
+    if plan.modes is not None:
+        # the spectrum must vanish off the plan's modes (to roundoff): then
+        # the sums over all modes are the sums over these
+        N = plan.N
+        flat = np.zeros(plan.modes.shape[1], dtype=np.int64)
+        for m in plan.modes:
+            flat = flat * N + (m % N)
+        if np.unique(flat).size != flat.size:
+            raise ValueError("repeated modes in the plan")
+        off = np.ones(plan.n, bool)
+        off[flat] = False
+        if np.abs(Fh[off]).max(initial=0.0) > 1e-13 * np.abs(Fh).max():
+            raise ValueError("the input's spectrum does not vanish off the plan's modes")
+        Fh = Fh[flat]
+        kl = list(plan.modes)
     vl = [v[idx] for v in grid_points(plan.N, plan.d, plan.L)]
     Er = E(kl, vl, plan.L)                       # (P, n)
     sF = plan.sigma * Fh

@@ -20,7 +20,7 @@ import numpy as np
 __all__ = [
     "grid_1d", "velocity_grid", "Gaussian", "Mixture", "mixture_two_gaussians",
     "mixture_anisotropic", "sample_mixture", "bkw", "bkw_datum",
-    "batch_mixed_sizes", "rng",
+    "batch_mixed_sizes", "rng", "trig_polynomial",
 ]
 
 
@@ -125,3 +125,33 @@ def batch_mixed_sizes(seed: int, n_cells: int, sizes=(16, 24, 32),
     counts[0] += n_cells - sum(counts)
     arr = np.concatenate([np.full(c, s, dtype=np.int64) for s, c in zip(sizes, counts)])
     return rng(seed).permutation(arr)
+
+
+def trig_polynomial(seed: int, N: int, d: int, L: float, n_waves: int = 12,
+                    kmax: int | None = None, background: float = 1.0):
+    """A real trigonometric polynomial on the grid with a known, small set of
+    frequencies: F(v) = background + sum over n_waves random integer vectors
+    k (components in [-kmax, kmax], distinct, k != 0) of
+    2 Re(c_k exp(i pi k.v / L)), c_k complex with |c_k| <= 1/(4 n_waves), so
+    F stays within background +- 1/2.  Returns (F, modes): modes is the
+    (d, 2 n_waves + 1) integer array of the frequencies present (0, the k and
+    their negatives).  For parity tests of large plans, whose reference
+    needs the kernel factors only on these modes."""
+    g = rng(seed)
+    kmax = N // 2 - 2 if kmax is None else kmax
+    chosen = set()
+    while len(chosen) < n_waves:
+        k = tuple(int(x) for x in g.integers(-kmax, kmax + 1, d))
+        if any(k) and k not in chosen and tuple(-x for x in k) not in chosen:
+            chosen.add(k)
+    ks = np.array(sorted(chosen), dtype=np.int64)                 # (n_waves, d)
+    amp = g.uniform(0.0, 1.0 / (4 * n_waves), n_waves)
+    ph = g.uniform(0.0, 2.0 * math.pi, n_waves)
+    v = velocity_grid(N, d, L)
+    F = np.full((N,) * d, float(background))
+    for k, a, p in zip(ks, amp, ph):
+        arg = sum(math.pi / L * kk * vv for kk, vv in zip(k, v))
+        F += 2.0 * a * np.cos(arg + p)
+    modes = np.concatenate([np.zeros((1, d), np.int64), ks, -ks]).T
+    return F, modes
+

@@ -2,13 +2,16 @@
 1024 cells of 32^3 (hard spheres, M = 32, L = 8, R = 6, the bench's
 anisotropic mixtures, seed 2001 + cell) with the schedule read from the
 measured tune cache (fused passes of 1024 cells in FP64 and 512 in FP32, x
-split 2), checked against the oracle's point form on sampled points of cells
-at pass and workgroup-round boundaries.
+split 2), checked against the oracle: the full grid of 8 cells at pass and
+workgroup-round boundaries against the plain double sum of eq. Qsk, and
+sampled points of more cells against the point form.
 Degenerate cells inside a fused batch: F = 0 gives Q = 0 exactly, a spike
 stays finite, a Maxwellian matches the oracle.
 
-Bars: FP64 1e-12, FP32 1e-5 of max |Q+| over the samples (samples include
-the points where F peaks)."""
+Bars (paper_1704_07369_amd.bounds, stated a priori): FP64 1e-12 and FP32
+e1 (2 + ||Q-|| / ||Q+||) of ||Q+||_2 on the full grid; on sampled points the
+same numbers relative to max |Q+| over the samples (which include the points
+where F peaks)."""
 import os
 
 import numpy as np
@@ -16,6 +19,7 @@ import pytest
 
 import synth
 from oracle import efm
+from paper_1704_07369_amd import bounds
 from tests.gpu_util import say, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -37,6 +41,44 @@ def bench_cells(n):
     return [synth.sample_mixture(synth.mixture_anisotropic(2001 + c, D), N, L) for c in range(n)]
 
 
+# cells at the boundaries of the fused passes (FP64: one pass of 1024 cells;
+# FP32: passes of 512) and of the workgroup rounds (two workgroups per cell,
+# 256 CUs: 128 cells per round)
+FULL_GRID_CELLS = [0, 127, 128, 255, 256, 511, 512, 1023]
+
+
+def test_headline_batch_full_grid_vs_oracle():
+    """8 cells of the 1024-cell headline batch, every grid point, against the
+    oracle's plain double sum over modes (section 3.2.2, eq. Qsk), FP64 and
+    FP32 in the bench's launch configuration."""
+    import torch
+    say("case headline batch 1024 x 32^3, full grid of 8 cells vs the double sum")
+    cells = bench_cells(1024)
+    p = E.Plan(N, D, L, M, R=R)
+    outs = {}
+    for prec in (0, 1):
+        b = E.Batch([p], [1024], prec)
+        f = to_dev(E.pack(b, cells))
+        Q = torch.full_like(f, float("nan"))
+        b.autotune(f, Q, CACHE)
+        say(f"  precision {prec} schedule {b.get_schedule(0)}")
+        b.collide(f, Q)
+        torch.cuda.synchronize()
+        outs[prec] = E.unpack(b, Q.cpu().numpy())
+        b.close()
+    for c in FULL_GRID_CELLS:
+        ref = efm.collide_modes(oplan(), cells[c])
+        den = np.linalg.norm(ref.Qplus)
+        r = np.linalg.norm(ref.Qminus) / den
+        e64 = np.linalg.norm(outs[0][c] - ref.Q) / den
+        e32 = np.linalg.norm(outs[1][c] - ref.Q) / den
+        b32 = bounds.fp32_bound(N, D, r)
+        say(f"  cell {c}: FP64 {e64:.3e} (bound 1e-12), FP32 {e32:.3e} (bound {b32:.3e}), "
+            f"||Q-||/||Q+|| {r:.3f}")
+        assert e64 <= 1e-12
+        assert e32 <= b32
+
+
 @pytest.mark.parametrize("prec,check", [(0, [0, 255, 256, 511, 512, 1023]), (1, [0, 511, 512, 1023])])
 def test_headline_size_parity(prec, check):
     import torch
@@ -53,11 +95,11 @@ def test_headline_size_parity(prec, check):
     out = E.unpack(b, Q.cpu().numpy())
     assert all(np.all(np.isfinite(o)) for o in out[::97])
     rng = np.random.default_rng(11)
-    tol = 1e-12 if prec == 0 else 1e-5
     for c in check:
         idx = np.unique(np.concatenate([np.argsort(cells[c].ravel())[-12:],
                                         rng.choice(N ** 3, 20, replace=False)]))
-        q, qp, _, _ = efm.collide_points(oplan(), cells[c], idx)
+        q, qp, qm, _ = efm.collide_points(oplan(), cells[c], idx)
+        tol = bounds.bound(prec, N, D, np.abs(qm).max() / np.abs(qp).max())
         err = np.abs(out[c].ravel()[idx] - q).max() / np.abs(qp).max()
         say(f"  cell {c}: max rel err {err:.3e}")
         assert err <= tol

@@ -90,3 +90,33 @@ def test_maxwell_3d_approaches_bkw_derivative():
         q = efm.collide_points(p, F, idx)[0]
         errs.append(np.linalg.norm(q - g[idx]) / np.linalg.norm(g[idx]))
     assert errs[1] < 0.85 * errs[0]
+
+
+def test_sparse_support_plan_equals_full_plan():
+    """A plan restricted to the modes where the input's spectrum lives (a
+    real trigonometric polynomial) gives the same point form of the fast
+    algorithm as the full plan (section 4.1, eq. fastAlg: every sum over
+    modes k carries Fh_k, which vanishes off the support) and the same
+    operator as the double sum of eq. Qsk; an input with spectrum off the
+    support is refused."""
+    N, L, R = 12, 8.0, 6.0
+    F, modes = synth.trig_polynomial(5, N, 3, L, n_waves=10)
+    assert modes.shape == (3, 21)
+    kw = dict(kind=efm.KIND_VHS, R=R, gamma=0.5, n_radial=3)
+    full = efm.make_plan(N, 3, L, 8, **kw)
+    sp = efm.make_plan(N, 3, L, 8, modes=modes, **kw)
+    idx = np.arange(N ** 3)
+    a = efm.collide_points(full, F, idx)
+    b = efm.collide_points(sp, F, idx)
+    ref = efm.collide_modes(full, F)
+    scale = np.abs(ref.Qplus).max()
+    assert np.abs(a[0] - b[0]).max() <= 1e-13 * scale
+    assert np.abs(b[0] - ref.Q.ravel()).max() <= 1e-13 * scale
+    assert np.abs(b[1] - ref.Qplus.ravel()).max() <= 1e-13 * scale
+    # the polynomial's spectrum: exactly the listed modes (to roundoff)
+    Fh = efm.dft(F, L)
+    on = np.zeros(Fh.shape, bool)
+    on[tuple(m % N for m in modes)] = True
+    assert np.abs(Fh[~on]).max() <= 1e-15 * np.abs(Fh).max()
+    with pytest.raises(ValueError):
+        efm.collide_points(sp, synth.sample_mixture(synth.mixture_two_gaussians(1, 3), N, L), idx[:4])
