@@ -41,3 +41,16 @@ def run_collide(E, plans, counts, cells, precision=0, chunks=None):
 
 def rel_err(q, ref, scale_ref):
     return float(np.linalg.norm((q - ref).ravel()) / np.linalg.norm(scale_ref.ravel()))
+
+
+def bound_full(prec, N, d, ref):
+    """Stated bound of a path (paper_1704_07369_amd.bounds) for a full-grid
+    check against the oracle result ref (ratio of the loss to the gain)."""
+    from paper_1704_07369_amd import bounds
+    return bounds.bound(prec, N, d, float(np.linalg.norm(ref.Qminus) / np.linalg.norm(ref.Qplus)))
+
+
+def bound_pts(prec, N, d, qp, qm):
+    """The same bound for a check on sampled points (max-norm ratio)."""
+    from paper_1704_07369_amd import bounds
+    return bounds.bound(prec, N, d, float(np.abs(qm).max() / np.abs(qp).max()))
