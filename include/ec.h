@@ -273,6 +273,31 @@ int ec_batch_set_chunk(ec_batch* batch, int group, int cells_per_pass);
 int ec_collide(ec_batch* batch, const double* f, double* Q, void* hip_stream);
 
 /*
+ * ec_collide_noalloc -- ec_collide without any device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Q^s of n_cells contiguous 3D
+ * cells of `plan` (N = 16, 24 or 32; f and Q each hold n_cells x N^3 FP64
+ * values, cell c at offset c N^3, C order [x][y][z]; device memory owned by
+ * the caller, not aliased), on the fused schedule of ec_collide (same
+ * kernels, same x split for the same cells per launch) in precision EC_FP64
+ * or EC_FP32.  Its only device memory beyond f and Q is a fixed scratch
+ * array of EC_NOALLOC_SCRATCH_BYTES that the library's code object holds on
+ * every device it runs on until the process ends (the half-space spectra of
+ * one pass of cells and their offsets: 255 cells of 32^3 in FP64 per pass;
+ * more cells run in passes).  Every call on a device shares that device's
+ * scratch: calls that overlap on one device (other streams, other threads)
+ * race and must be ordered by the caller.  Nothing in the scratch needs
+ * clearing between calls.  Stream-ordered on hip_stream, no host sync.
+ * Errors: EC_ERR_ARG (null or aliased pointers, n_cells < 0, a precision
+ * other than EC_FP64/EC_FP32, a plan of another device), EC_ERR_UNSUPPORTED
+ * (a plan other than 3D N = 16, 24, 32, or one cell larger than the
+ * scratch), EC_ERR_DEVICE (launch failure).
+ */
+#define EC_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int ec_collide_noalloc(const ec_plan* plan, int precision, int64_t n_cells, const double* f,
+                       double* Q, void* hip_stream);
+
+/*
  * ec_entropy_prod -- per cell, out[c] = h^d sum_{F_r > 0} Q_r ln F_r (the
  * discrete H-functional of Theorem 1, eq. Htheorem; <= 0 in exact arithmetic
  * for F >= 0) and, if n_nonpos != NULL, n_nonpos[c] = #{r : F_r <= 0}.

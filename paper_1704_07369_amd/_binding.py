@@ -62,6 +62,7 @@ _SIGS = {
     "ec_batch_offsets": ([_vp, ctypes.POINTER(_c_i64)], _c_int),
     "ec_batch_set_chunk": ([_vp, _c_int, _c_int], _c_int),
     "ec_collide": ([_vp, _vp, _vp, _vp], _c_int),
+    "ec_collide_noalloc": ([_vp, _c_int, _c_i64, _vp, _vp, _vp], _c_int),
     "ec_entropy_prod": ([_vp, _vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_monitors": ([_vp, _vp, _vp, _vp, _vp], _c_int),
     "ec_step": ([_vp, _vp, _c_double, _c_int, _vp, _vp], _c_int),
@@ -247,6 +248,11 @@ def ec_batch_set_chunk(batch, group, cells_per_pass):
 
 def ec_collide(batch, f, Q, stream=None):
     return _check(lib().ec_collide(batch, _ptr(f), _ptr(Q), _stream(stream)))
+
+
+def ec_collide_noalloc(plan, precision, n_cells, f, Q, stream=None):
+    return _check(lib().ec_collide_noalloc(plan, precision, n_cells, _ptr(f), _ptr(Q),
+                                           _stream(stream)))
 
 
 def ec_entropy_prod(batch, f, Q, out, n_nonpos=None, stream=None):

@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function"]
 SOURCES = ["kernels.hip", "pipe.hip", "mfma.hip", "fused.hip", "large2d.hip", "large3d.hip", "fno.hip",
-           "tables.hip", "api.cpp", "surrogate.cpp", "plan.cpp"]
+           "tables.hip", "noalloc.hip", "api.cpp", "surrogate.cpp", "plan.cpp"]
 
 
 def _compile(src: str) -> str:

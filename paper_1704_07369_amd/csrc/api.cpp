@@ -508,6 +508,14 @@ int64_t batch_group_count(const ec_batch* b, int g) { return b->groups[g].count;
 int plan_N(const ec_plan* p) { return p->host.N; }
 int plan_d(const ec_plan* p) { return p->host.d; }
 double plan_L(const ec_plan* p) { return p->host.L; }
+int plan_J(const ec_plan* p) { return p->host.J; }
+int plan_device(const ec_plan* p) { return p->device; }
+const void* plan_gamma(const ec_plan* p, int precision) {
+  return precision == EC_FP64 ? p->d_gamma64 : p->d_gamma32;
+}
+int fused_split_for_cells(int N, int precision, int64_t cells) {
+  return fused_split_for(N, precision, cells);
+}
 
 int collide_prefix(ec_batch* b, int64_t n_active, const double* f, double* Q, hipStream_t s) {
   if (n_active <= 0) return EC_OK;

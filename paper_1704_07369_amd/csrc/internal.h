@@ -24,6 +24,15 @@ int64_t batch_group_count(const ec_batch* b, int g);
 int plan_N(const ec_plan* p);
 int plan_d(const ec_plan* p);
 double plan_L(const ec_plan* p);
+int plan_J(const ec_plan* p);
+int plan_device(const ec_plan* p);
+// the plan's device tables in FP64 (precision 0) or FP32; null if the plan
+// keeps no copy in that precision
+const void* plan_gamma(const ec_plan* p, int precision);
+
+// x split that the fused schedule's defaults pick for launches of `cells`
+// cells of N^3 (0: no fused schedule for N and precision)
+int fused_split_for_cells(int N, int precision, int64_t cells);
 
 // Q for the first n_active cells of group 0 only (the other cells untouched)
 int collide_prefix(ec_batch* b, int64_t n_active, const double* f, double* Q, hipStream_t s);
