@@ -7,18 +7,30 @@ independent cells, each a seeded sum of 2-4 anisotropic Gaussians (means
 U[-2,2]^3, diagonal temperatures U[0.3,2], Dirichlet weights; seed 2001 + cell).
 One step = one ec_collide over the whole batch (every cell's Q).  Inputs are
 resident in HBM before the timed region.  FP64 is the headline value; FP32
-transforms and single-cell latency are reported beside it, each with its
-error against the CPU oracle on sampled points.
+transforms, the split-BF16 x pass and single-cell latency (3D and the 2D
+32^2, M = 16 configuration) are reported beside it.  Roofline: algorithmic
+flops (nominal FFT convention) of the dominant kernel over its duration from
+HIP events on the launch stream in the timed region; HBM bytes per launch
+from rocprofv3 byte counters of a child run of the same batches, calibrated
+by a plain copy.  Parity: the full grid of 8 cells against the oracle's
+double sum (the same oracle runs are the CPU baseline), each path against
+its stated bound.
 
 Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import json
 import math
 import os
+import shutil
+import signal
+import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -28,6 +40,9 @@ if ROOT not in sys.path:
 METRIC = "collision evals/sec at N=32^3,M=32: FP64 vs mixed vs surrogate at stated rel err"
 PEAK_FP64 = 78.6    # TFLOP/s, MI355X vector FP64
 PEAK_FP32 = 157.3   # TFLOP/s, MI355X vector FP32
+PEAK_BF16_MFMA = 2500.0   # TFLOP/s, MI355X dense BF16 matrix cores
+COPY_MIB = 256            # ec_copy size of the byte-counter calibration
+FULL_GRID_CELLS = [0, 127, 128, 255, 256, 511, 512, 1023]   # pass and round boundaries
 N, D, L, M, R = 32, 3, 8.0, 32, 6.0
 KNAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe", "k_fwdx", "k_fused"]
 
@@ -36,26 +51,49 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_flops(n_side: int, d: int, terms: int) -> list:
-    """Algorithmic flops per cell of each kernel (nominal 2.5 n log2 n per real
-    and 5 n log2 n per complex transform, split by axes passes; products and
-    sums as written in the algorithm)."""
+def flops_8d(n_side: int, d: int, terms: int) -> float:
+    """Algorithmic flops of one collision evaluation in the nominal FFT
+    convention (2.5 n log2 n per real transform): (2M'+2) 2.5 n log2 n for
+    the forward and the 2M'+1 real inverse transforms, M'(4H + 3n) for the
+    spectral multiplies and the weighted products, 2H + 2n for the loss
+    (H = N^{d-1} (N/2 + 1) half-spectrum entries, n = N^d).  86.58 MFLOP at
+    32^3, M' = 32; 12.78 GFLOP at 64^3, M' = 512."""
     n = n_side ** d
+    H = n_side ** (d - 1) * (n_side // 2 + 1)
     lg = math.log2(n)
+    return (2 * terms + 2) * 2.5 * n * lg + terms * (4 * H + 3 * n) + 2 * H + 2 * n
+
+
+def kernel_flops(n_side: int, d: int, terms: int) -> list:
+    """The same work split over the kernels that do it, indexed like the
+    profile slots (k_fwd, k_pencil, k_slab, k_pipe, k_fwdx, k_fused): the
+    forward transform's y, z passes (2/3) and x pass (1/3); the two-pass x
+    pass (forward x, the inverse x passes, the multiplies) and slab pass
+    (inverse y, z passes, products, loss); the pipelined and fused kernels do
+    everything after the forward transform (fused) or all of it (pipelined)."""
+    n = n_side ** d
+    H = n_side ** (d - 1) * (n_side // 2 + 1)
+    lg = math.log2(n)
+    fwd = 2.5 * n * lg
+    inv = (2 * terms + 1) * 2.5 * n * lg
+    total = flops_8d(n_side, d, terms)
     if d == 3:
-        fwd = (2.0 / 3.0) * 2.5 * n * lg
-        pencil = (1.0 / 3.0) * 2.5 * n * lg + terms * (1.0 / 3.0) * 5.0 * n * lg \
-            + (1.0 / 3.0) * 2.5 * n * lg + terms * 6.0 * n + 2.0 * n
-        slab = terms * (2.0 / 3.0) * 5.0 * n * lg + (2.0 / 3.0) * 2.5 * n * lg \
-            + terms * 2.0 * n + 2.0 * n
+        k_fwd, k_fwdx = fwd * 2 / 3, fwd / 3
+        k_pencil = fwd / 3 + inv / 3 + terms * 4 * H + 2 * H
+        k_slab = inv * 2 / 3 + terms * 3 * n + 2 * n
     else:
-        fwd = 2.5 * n * lg
-        pencil = 0.0
-        slab = terms * 5.0 * n * lg + 2.5 * n * lg + terms * 8.0 * n + 4.0 * n
-    total = fwd + pencil + slab
-    # the fused schedule: k_fwd, then the x forward pass, then everything else
-    fwdx = (1.0 / 3.0) * 2.5 * n * lg if d == 3 else 0.0
-    return [fwd, pencil, slab, total, fwdx, total - fwd - fwdx]
+        k_fwd, k_fwdx = fwd, 0.0
+        k_pencil = 0.0
+        k_slab = total - fwd
+    return [k_fwd, k_pencil, k_slab, total, k_fwdx, total - fwd]
+
+
+def bf16_gemm_flops(n_side: int, d: int, terms: int) -> float:
+    """Matrix-core flops of the split-BF16 x pass per cell: for every pencil
+    and each of the J = M'+1 inverse transforms, a (2N x 2N) real DFT matrix
+    times a 2N vector, three products (hi hi, hi lo, lo hi)."""
+    pencils = n_side ** (d - 1)
+    return 3 * 2 * (2 * n_side) ** 2 * pencils * (terms + 1)
 
 
 def make_cells(n_cells, seed0=2001):
@@ -94,56 +132,143 @@ def time_collide(E, torch, plan, cells, precision, steps, warmup, profile):
     return b, f, Q, (t1 - t0), prof
 
 
-def sampled_error(E, b, Q, cells, cell_ids, oplan, efm, npts=64):
-    import numpy as np
-    qh = E.unpack(b, Q.cpu().numpy())
-    rng = np.random.default_rng(12345)
-    worst = 0.0
-    for c in cell_ids:
-        # the points where F peaks are among the samples, so that max |Q+| over
-        # the samples is the gain's scale
-        idx = np.unique(np.concatenate([np.argsort(cells[c].ravel())[-16:],
-                                        rng.choice(N ** D, npts, replace=False)]))
-        q, qp, _, _ = efm.collide_points(oplan, cells[c], idx)
-        worst = max(worst, float(np.abs(qh[c].ravel()[idx] - q).max() / np.abs(qp).max()))
-    return worst
-
-
-# HBM bytes per launch of the dominant kernels, 2 FETCH_SIZE + WRITE_SIZE (factors
-# from the ec_copy calibration) of the run recorded in
-# profiles/collide_n32_m32_default_counters.md; keyed by (kernel, precision,
-# cells per launch) and valid for that code only (re-measure after changing it)
-MEASURED_TRAFFIC = {
-    ("k_fused", "f64", 1024): (2 * 2705696 + 262144) * 1024,
-    ("k_fused", "f32", 512): (2 * 620835 + 131072) * 1024,
-    ("k_pencil", "bf16x3", 1024): (2 * 236649 + 8650752) * 1024,
-}
-
-
-def roofline(prof, flops_cell, peak, prec="f64"):
-    """Dominant kernel of the timed region: algorithmic flops it performed
-    over its summed duration (HIP events on the launch stream)."""
+def roofline(prof, flops_cell, peak, traffic=None, bound="alu", unit="TFLOP/s"):
+    """Dominant kernel of the timed region: its algorithmic flops (the
+    per-kernel split of flops_8d, or the GEMM flops of a matrix-core stage)
+    over its summed duration, from HIP events the library records on the
+    launch stream around every launch.  traffic: HBM bytes per launch from
+    the byte counters of the same kernel and workload (measure_traffic), or
+    None."""
     ms, launches, cells = prof
     k = max(range(len(ms)), key=lambda i: ms[i])
     fl = flops_cell[k]
     achieved = fl * cells / (ms[k] * 1e-3) / 1e12
+    nl = max(1, int(launches[k]))
     return {
-        "bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+        "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
         "frac": round(achieved / peak, 4),
-        "traffic": MEASURED_TRAFFIC.get((KNAMES[k], prec, round(cells / max(1, launches[k])))),
+        "traffic": traffic,
         "kernel": KNAMES[k],
-        "avg_launch_ms": round(ms[k] / max(1, launches[k]), 5),
-        "launches": int(launches[k]), "cells_per_launch": cells / max(1, launches[k]),
-        "flops_per_launch": fl * cells / max(1, launches[k]),
+        "avg_launch_ms": round(ms[k] / nl, 5),
+        "launches": int(launches[k]), "cells_per_launch": cells / nl,
+        "flops_per_cell": fl, "flops_per_launch": fl * cells / nl,
         "kernel_ms_total": {KNAMES[i]: round(float(ms[i]), 3) for i in range(len(ms))},
     }
+
+
+# ---------------------------------------------------------------------------
+# HBM bytes per launch from hardware counters: bench.py re-runs itself as a
+# child under rocprofv3 --pmc (FETCH_SIZE, then WRITE_SIZE: they do not fit one
+# pass), running the same batches with the same schedules plus a plain copy
+# of known size that calibrates each counter to bytes.
+# ---------------------------------------------------------------------------
+
+COUNTER_KERNELS = {            # (profile slot, precision) -> kernel-name pattern
+    ("k_fused", "f64"): ("k_fused", "<double"),
+    ("k_fused", "f32"): ("k_fused", "<float"),
+    ("k_pencil", "bf16x3"): ("k_pencil_bf16", ""),
+}
+
+
+def counter_child(args):
+    """Runs under rocprofv3: the copy, then the FP64, FP32 and split-BF16
+    batches of the timed regions (schedules from the tune cache), twice each."""
+    import torch
+    import paper_1704_07369_amd as E
+    nc = COPY_MIB * 1048576 // 8
+    a = torch.ones(nc, dtype=torch.float64, device="cuda:0")
+    bb = torch.zeros_like(a)
+    for _ in range(2):
+        E.ec_copy(a, bb, nc)
+    torch.cuda.synchronize()
+    del a, bb
+    cells = make_cells(args.cells)
+    plan = E.Plan(N, D, L, M, R=R)
+    for prec in (E.EC_FP64, E.EC_FP32, E.EC_BF16X3):
+        b = E.Batch([plan], [len(cells)], prec)
+        f = torch.from_numpy(E.pack(b, cells)).to("cuda:0")
+        Q = torch.zeros_like(f)
+        b.autotune(f, Q, TUNE_CACHE)
+        for _ in range(2):
+            b.collide(f, Q)
+        torch.cuda.synchronize()
+        log(f"bench counter child: precision {prec} done")
+        b.close()
+        del f, Q
+
+
+def _read_counter_csv(d):
+    """{kernel name: [counter value per dispatch]} from rocprofv3's CSV."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection*.csv"), recursive=True)
+    per = {}
+    for fn in files:
+        with open(fn, newline="") as fh:
+            for row in csv.DictReader(fh):
+                key = (row.get("Dispatch_Id") or row.get("Correlation_Id"), row.get("Kernel_Name", ""))
+                per[key] = per.get(key, 0.0) + float(row.get("Counter_Value") or 0.0)
+    out = {}
+    for (_, name), v in per.items():
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def measure_traffic(args):
+    """HBM bytes per launch of the dominant kernels, 2 counter runs of the
+    child; None where rocprofv3 is missing or a run fails."""
+    exe = shutil.which("rocprofv3") or "/opt/rocm/bin/rocprofv3"
+    if not os.path.exists(exe):
+        return None, "rocprofv3 not found"
+    vals = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        d = tempfile.mkdtemp(prefix="efm_pmc_", dir="/tmp")
+        cmd = [exe, "--pmc", ctr, "-d", d, "-o", "run", "--output-format", "csv", "--",
+               sys.executable, os.path.abspath(__file__), "--counter-child", "--cells",
+               str(args.cells)]
+        log(f"bench: byte counter run {ctr}")
+        with open(os.path.join(d, "rocprof.log"), "w") as lf:
+            p = subprocess.Popen(cmd, cwd="/tmp", env=dict(os.environ, TMPDIR="/tmp"),
+                                 stdout=lf, stderr=subprocess.STDOUT, start_new_session=True)
+            try:
+                rc = p.wait(timeout=240)
+            except subprocess.TimeoutExpired:
+                os.killpg(p.pid, signal.SIGKILL)
+                p.wait()
+                shutil.rmtree(d, ignore_errors=True)
+                return None, f"{ctr} counter run timed out"
+        vals[ctr] = _read_counter_csv(d)
+        shutil.rmtree(d, ignore_errors=True)
+        # rocprofv3 can end with a signal after the program finished and the
+        # results are complete; the CSV decides
+        if not vals[ctr]:
+            return None, f"{ctr} counter run gave no data (rc {rc})"
+
+    def med(ctr, pat, prec_pat):
+        xs = [v for name, vs in vals[ctr].items() if pat in name and prec_pat in name for v in vs]
+        xs.sort()
+        return xs[len(xs) // 2] if xs else None
+
+    copy_kib = COPY_MIB * 1024.0          # bytes read = bytes written = 256 MiB
+    cf, cw = med("FETCH_SIZE", "k_copy", ""), med("WRITE_SIZE", "k_copy", "")
+    if not cf or not cw:
+        return None, "no k_copy dispatch in the counter data"
+    ff, fw = copy_kib / cf, copy_kib / cw
+    out = {"calibration": {"copy_mib": COPY_MIB, "fetch_size_kib": cf, "write_size_kib": cw,
+                           "fetch_factor": round(ff, 4), "write_factor": round(fw, 4)}}
+    for key, (pat, pp) in COUNTER_KERNELS.items():
+        fk, wk = med("FETCH_SIZE", pat, pp), med("WRITE_SIZE", pat, pp)
+        if fk is None or wk is None:
+            continue
+        out[f"{key[0]}/{key[1]}"] = {"fetch_size_kib": fk, "write_size_kib": wk,
+                                     "bytes": int(round(1024.0 * (ff * fk + fw * wk)))}
+    return out, None
 
 
 def relaxation_leg(E, torch, steps=200, dt=0.01, n_cells=4096, seed=3000):
     """Batched space-homogeneous relaxation: n_cells cells with grids mixed
     16^3/24^3/32^3 (40/35/25 %, seeded permutation), hard spheres, M = 32,
-    FP64, `steps` forward-Euler steps replayed from one captured HIP graph,
-    per-cell (mass, eta) after every step."""
+    FP64, `steps` forward-Euler steps launched as one captured HIP graph that
+    holds every step (ec_step_graph), per-cell (mass, eta) after every step.
+    The timed run reuses the graph of an untimed first run."""
     import numpy as np
     import synth
     sizes = synth.batch_mixed_sizes(seed, n_cells)
@@ -158,7 +283,8 @@ def relaxation_leg(E, torch, steps=200, dt=0.01, n_cells=4096, seed=3000):
     Q = torch.zeros_like(f)
     b.autotune(f, Q, TUNE_CACHE)
     mon = torch.zeros(steps * n_cells * 2, dtype=torch.float64, device="cuda:0")
-    b.step(f, dt, 1, mon)          # graph capture + warm-up
+    # capture of the graph that holds all the steps, and a warm-up run of it
+    b.step(f, dt, steps, mon)
     f.copy_(torch.from_numpy(E.pack(b, cells)).to("cuda:0"))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -275,15 +401,15 @@ def surrogate_leg(E, torch, seconds=40.0, n_traj=500, n_steps=100, n_test=1024, 
     }
 
 
-def precision_sweep_leg(E, torch, n_cells=256, reps=2):
+def precision_sweep_leg(E, torch, efm=None, n_cells=256, reps=2):
     """Precision sweep on the non-separable kernel: 3D variable hard spheres
     (gamma = 0.5), N = 64^3, M = 64 directions x 8 radial nodes (513
     transforms per evaluation), n_cells two-Gaussian mixtures (means
     U[-2,2]^3, temperatures U[0.5,1.5], seed 4001 + cell).  FP64, FP32 and
     split-BF16 evaluations timed; FP32 and split-BF16 errors against the FP64
-    GPU result on every cell (the FP64 path itself is checked against the
-    oracle at 64^3 in the GPU tests; the oracle's tables at this size are out
-    of reach of a bench run)."""
+    GPU result on every cell, and all three paths against the oracle on the
+    full grid of two cells whose spectrum the oracle can afford at this plan
+    (sweep_oracle_check)."""
     import numpy as np
     import synth
     Nn, Mm, nr, gam = 64, 64, 8, 0.5
@@ -314,6 +440,13 @@ def precision_sweep_leg(E, torch, n_cells=256, reps=2):
                      "schedule": list(b.get_schedule(0))}
         log(f"bench: sweep {name} {n_cells / t:.4g} evals/s")
         del b, f, Q
+    if efm is not None:
+        log("bench: sweep plan vs the oracle (full grid, sparse-spectrum cells)")
+        out["oracle_check"] = sweep_oracle_check(E, torch, plan, Nn, Mm, nr, gam, efm)
+    out["flops_per_eval"] = flops_8d(Nn, D, plan.terms())
+    for name in ("fp64", "fp32"):
+        out[name]["frac_of_peak"] = round(out["flops_per_eval"] * out[name]["evals_per_s"] / 1e12
+                                          / (PEAK_FP64 if name == "fp64" else PEAK_FP32), 4)
     q64 = Qs["fp64"]
     for name in ("fp32", "bf16x3"):
         d = (Qs[name] - q64).view(n_cells, -1).norm(dim=1) / q64.view(n_cells, -1).norm(dim=1)
@@ -324,28 +457,25 @@ def precision_sweep_leg(E, torch, n_cells=256, reps=2):
     return out
 
 
-def cpu_baseline(cells, efm, oplan, budget_s=10.0):
-    """The oracle (plain double sum over modes, OpenMP over all host threads)
-    on as many cells of the workload as fit in about budget_s seconds (at
-    least one); evals/s = cells / time.  Beside it, the same fast algorithm
-    the library runs (one forward and M'+1 packed inverse FFTs per cell, on
-    the oracle's tables, torch FP64 FFTs on the host threads): a like-for-like
-    CPU rate for the transform-based method."""
+def cpu_baseline(cells, efm, oplan, ids):
+    """The oracle (plain double sum over modes of eq. Qsk, OpenMP over all
+    host threads) on the full grid of the cells `ids` of the workload (the
+    boundaries of the GPU passes and workgroup rounds): evals/s = cells /
+    time.  Their results are also the full-grid references of the parity
+    leg.  Beside it, the same fast algorithm the library runs (one forward
+    and M'+1 packed inverse FFTs per cell, on the oracle's tables, torch FP64
+    FFTs on the host threads): a like-for-like CPU rate for the
+    transform-based method."""
     import numpy as np
     import torch
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     efm._load()
     t0 = time.perf_counter()
-    done = 0
-    ref0 = None
-    while done < len(cells) and (done == 0 or time.perf_counter() - t0 < budget_s):
-        ref = efm.collide_modes(oplan, cells[done])
-        ref0 = ref0 or ref
-        done += 1
+    refs = {c: efm.collide_modes(oplan, cells[c]) for c in ids}
     t = time.perf_counter() - t0
-    out = {"value": done / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
-           "sample": f"{done} of the 1024 cells, full 32^3 direct double sum over modes (M=32), "
-                     f"{t:.1f} s"}
+    out = {"value": len(ids) / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(ids)} of the {len(cells)} cells (ids {ids}), full 32^3 direct double "
+                     f"sum over modes (M=32), {t:.1f} s"}
     # fast algorithm on the host
     torch.set_num_threads(threads)
     shp = (N,) * D
@@ -354,21 +484,112 @@ def cpu_baseline(cells, efm, oplan, budget_s=10.0):
     Dg = torch.from_numpy((sig * sig * lr.diagonal()).reshape(shp)).to(torch.complex128)
     t0 = time.perf_counter()
     k = 0
-    while k < len(cells) and (k == 0 or time.perf_counter() - t0 < 0.5 * budget_s):
-        F = torch.from_numpy(cells[k])
+    err = None
+    while k < len(ids) and (k == 0 or time.perf_counter() - t0 < 5.0):
+        c = ids[k]
+        F = torch.from_numpy(cells[c])
         Fh = torch.fft.fftn(F.to(torch.complex128))
         qp = torch.zeros(shp, dtype=torch.float64)
-        for j in range(G.shape[0]):
-            c = torch.fft.ifftn(G[j] * Fh)
-            qp += c.real * c.imag
+        for jj in range(G.shape[0]):
+            cz = torch.fft.ifftn(G[jj] * Fh)
+            qp += cz.real * cz.imag
         q = qp - F * torch.fft.ifftn(Dg * Fh).real
         if k == 0:
-            err = float(np.abs(q.numpy() - ref0.Q).max() / np.abs(ref0.Qplus).max())
+            err = float(np.linalg.norm(q.numpy() - refs[c].Q) / np.linalg.norm(refs[c].Qplus))
         k += 1
     t = time.perf_counter() - t0
     out["fast_fft_cpu"] = {"value": k / t, "unit": "evals/s", "cores": threads,
                            "sample": f"{k} cells, torch FP64 FFTs, {t:.1f} s",
-                           "max_err_vs_oracle": err}
+                           "rel_l2_vs_oracle": err}
+    return out, refs
+
+
+def full_grid_parity(E, batches, refs, d=D, n_side=N):
+    """||Q - Q_oracle||_2 / ||Q+_oracle||_2 per reference cell and path, with
+    the stated bound of the path (paper_1704_07369_amd.bounds)."""
+    import numpy as np
+    from paper_1704_07369_amd import bounds
+    out = {}
+    for name, (prec, b, Q) in batches.items():
+        if b is None:
+            continue
+        qh = E.unpack(b, Q.cpu().numpy())
+        errs, bnds = [], []
+        for c, ref in refs.items():
+            den = np.linalg.norm(ref.Qplus)
+            errs.append(float(np.linalg.norm(qh[c] - ref.Q) / den))
+            bnds.append(bounds.bound(prec, n_side, d, float(np.linalg.norm(ref.Qminus) / den)))
+        out[name] = {"max": max(errs), "median": float(np.median(errs)), "bound": min(bnds),
+                     "within_bound": all(e <= bb for e, bb in zip(errs, bnds))}
+    return out
+
+
+def sweep_oracle_check(E, torch, plan, n_side, terms_m, nr, gam, efm, ncheck=2):
+    """The sweep plan against the oracle on the full grid: cells that are
+    real trigonometric polynomials (spectrum on 25 known modes), so the
+    oracle's tables are needed on those modes only."""
+    import numpy as np
+    import synth
+    from paper_1704_07369_amd import bounds
+    inputs = [synth.trig_polynomial(7001 + c, n_side, D, L) for c in range(ncheck)]
+    cells = [F for F, _ in inputs]
+    refs = []
+    for F, modes in inputs:
+        op = efm.make_plan(n_side, D, L, terms_m, kind=efm.KIND_VHS, R=R, gamma=gam,
+                           n_radial=nr, modes=modes)
+        n = F.size
+        q = np.empty(n); qp = np.empty(n); qm = np.empty(n)
+        for i in range(0, n, 16384):
+            idx = np.arange(i, min(n, i + 16384))
+            q[idx], qp[idx], qm[idx], _ = efm.collide_points(op, F, idx)
+        refs.append((q, qp, qm))
+    out = {"cells": f"{ncheck} trigonometric polynomials (12 waves, background 1), full grid"}
+    for prec, name in ((E.EC_FP64, "fp64"), (E.EC_FP32, "fp32"), (E.EC_BF16X3, "bf16x3")):
+        b = E.Batch([plan], [ncheck], prec)
+        f = torch.from_numpy(E.pack(b, cells)).to("cuda:0")
+        Q = torch.zeros_like(f)
+        b.collide(f, Q)
+        qh = E.unpack(b, Q.cpu().numpy())
+        errs, bnds = [], []
+        for c, (q, qp, qm) in enumerate(refs):
+            den = np.linalg.norm(qp)
+            errs.append(float(np.linalg.norm(qh[c].ravel() - q) / den))
+            bnds.append(bounds.bound(prec, n_side, D, float(np.linalg.norm(qm) / den)))
+        out[name] = {"rel_l2_vs_oracle_max": max(errs), "bound": min(bnds),
+                     "within_bound": all(e <= bb for e, bb in zip(errs, bnds))}
+        b.close()
+    return out
+
+
+def c1_leg(E, torch, efm, reps):
+    """The 2D configuration: N = 32^2, M = 16 (2M directions on [0, pi)),
+    Maxwell molecules, L = 8, R = 6, FP64, one cell: latency per evaluation,
+    and the full-grid error of the BKW datum at t = 0 and of a two-Gaussian
+    mixture (seed 1001) against the oracle's double sum."""
+    import numpy as np
+    import synth
+    from paper_1704_07369_amd import bounds
+    n2, m2 = 32, 16
+    p2 = E.Plan(n2, 2, L, m2, R=R)
+    inputs = {"bkw": synth.bkw_datum(2, n2, L),
+              "mixture": synth.sample_mixture(synth.mixture_two_gaussians(1001, 2), n2, L)}
+    b, f, Q, t, _ = time_collide(E, torch, p2, [inputs["mixture"]], E.EC_FP64, reps, 2, False)
+    out = {"workload": "2D Maxwell, N=32^2, M=16, L=8, R=6, FP64, one cell",
+           "latency_us": t / reps * 1e6, "flops_per_eval": flops_8d(n2, 2, p2.terms())}
+    b.close()
+    if efm is not None:
+        op = efm.make_plan(n2, 2, L, m2, R=R)
+        bb = E.Batch([p2], [2], E.EC_FP64)
+        ff = torch.from_numpy(E.pack(bb, list(inputs.values()))).to("cuda:0")
+        QQ = torch.zeros_like(ff)
+        bb.collide(ff, QQ)
+        qh = E.unpack(bb, QQ.cpu().numpy())
+        for k, (name, F) in enumerate(inputs.items()):
+            ref = efm.collide_modes(op, F)
+            out[f"{name}_rel_l2_vs_oracle"] = float(np.linalg.norm(qh[k] - ref.Q)
+                                                    / np.linalg.norm(ref.Qplus))
+        out["bound"] = bounds.FP64_BOUND
+        bb.close()
     return out
 
 
@@ -388,6 +609,9 @@ def main():
     ap.add_argument("--skip-relax", action="store_true", help="omit the mixed-N relaxation leg")
     ap.add_argument("--skip-surrogate", action="store_true", help="omit the learned-surrogate leg")
     ap.add_argument("--skip-sweep", action="store_true", help="omit the 64^3 VHS precision sweep")
+    ap.add_argument("--skip-counters", action="store_true",
+                    help="omit the byte-counter runs under rocprofv3 (roofline.traffic = null)")
+    ap.add_argument("--counter-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--surrogate-seconds", type=float, default=40.0, help="surrogate training budget")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run ec_copy on a buffer of this size (counter calibration)")
@@ -397,6 +621,9 @@ def main():
               "and would be split across GPUs by cost with no exchange per step, but that "
               "split is not implemented or measured here.", file=sys.stderr)
         sys.exit(2)
+    if args.counter_child:
+        counter_child(args)
+        return
 
     import numpy as np  # noqa: F401
     import torch
@@ -421,7 +648,7 @@ def main():
     plan = E.Plan(N, D, L, M, R=R)
     terms = plan.terms()
     flops = kernel_flops(N, D, terms)
-    flops_eval = flops[3]
+    flops_eval = flops_8d(N, D, terms)
 
     log("bench: FP64 timed region")
     b64, f64, Q64, t64, prof64 = time_collide(E, torch, plan, cells, E.EC_FP64, args.steps,
@@ -442,21 +669,35 @@ def main():
                                              args.warmup, True)
         evb = args.cells * args.steps / tb
         log(f"bench: BF16x3 {evb:.4g} evals/s")
+    efm = None
+    if not args.skip_parity or not args.skip_cpu:
+        from oracle import efm
     t1_64 = t1_32 = None
     reps = max(10, args.steps)
+    small_us = {}
     if not args.skip_single:
         log("bench: single-cell latency")
         one = cells[:1]
         _, _, _, t1_64, _ = time_collide(E, torch, plan, one, E.EC_FP64, reps, 2, False)
         _, _, _, t1_32, _ = time_collide(E, torch, plan, one, E.EC_FP32, reps, 2, False)
         import synth
-        small_us = {}
         for Ns in (16, 24):       # one cell of the smaller grids of the mixed-N leg
             ps = E.Plan(Ns, D, L, M, R=R)
             one_s = [synth.sample_mixture(synth.mixture_anisotropic(2001, D), Ns, L)]
             bs, _, _, ts, _ = time_collide(E, torch, ps, one_s, E.EC_FP64, reps, 2, False)
             small_us[f"n{Ns}_fp64_us"] = ts / reps * 1e6
             bs.close()
+
+    traffic, traffic_note = {}, "not measured (--skip-counters)"
+    if not args.skip_counters:
+        log("bench: HBM byte counters (rocprofv3 --pmc child runs)")
+        tr, err = measure_traffic(args)
+        traffic = tr or {}
+        traffic_note = err or "rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE of a child run of the same batches"
+
+    def tr_bytes(key):
+        v = traffic.get(key)
+        return v["bytes"] if v else None
 
     out = {
         "metric": METRIC, "value": ev64, "unit": "evals/s", "n_gpus": 1,
@@ -467,17 +708,30 @@ def main():
                                f"L=8, R=6, batch of {args.cells} Gaussian-mixture cells, FP64",
                    "d": D, "N": N, "M": M, "L": L, "R": R, "cells": args.cells,
                    "kernel": "hard_sphere", "flops_per_eval": flops_eval},
-        "roofline": roofline(prof64, flops, PEAK_FP64),
+        "roofline": roofline(prof64, flops, PEAK_FP64, tr_bytes("k_fused/f64")),
     }
+    # the whole step (forward transforms included) against the same peak
+    out["roofline"]["step_frac"] = round(flops_eval * args.cells / (t64 / args.steps) / 1e12
+                                         / PEAK_FP64, 4)
+    out["roofline"]["traffic_source"] = traffic_note
+    if traffic.get("calibration"):
+        out["roofline"]["traffic_calibration"] = traffic["calibration"]
     if ev32 is not None:
-        out["fp32"] = {"value": ev32, "ms_per_step": t32 / args.steps * 1e3,
-                       "roofline": roofline(prof32, flops, PEAK_FP32, "f32")}
+        r32 = roofline(prof32, flops, PEAK_FP32, tr_bytes("k_fused/f32"))
+        r32["step_frac"] = round(flops_eval * args.cells / (t32 / args.steps) / 1e12 / PEAK_FP32, 4)
+        out["fp32"] = {"value": ev32, "ms_per_step": t32 / args.steps * 1e3, "roofline": r32}
     if evb is not None:
-        out["bf16x3"] = {"value": evb, "ms_per_step": tb / args.steps * 1e3,
-                         "roofline": roofline(profb, flops, PEAK_FP32, "bf16x3")}
+        gemm = [0.0] * len(KNAMES)
+        gemm[KNAMES.index("k_pencil")] = bf16_gemm_flops(N, D, terms)
+        rb = roofline(profb, gemm, PEAK_BF16_MFMA, tr_bytes("k_pencil/bf16x3"), bound="mfma")
+        rb["flops_note"] = ("matrix-core flops of the split-BF16 x pass: 3 products x 2 x (2N)^2 "
+                            "per pencil and transform")
+        out["bf16x3"] = {"value": evb, "ms_per_step": tb / args.steps * 1e3, "roofline": rb}
     if t1_64 is not None:
         out["single_cell"] = {"fp64_us": t1_64 / reps * 1e6, "fp32_us": t1_32 / reps * 1e6,
                               **small_us}
+        log("bench: 2D 32^2 M=16 single cell")
+        out["single_cell"]["c1_2d"] = c1_leg(E, torch, efm, reps)
     # the device as it runs: vector FMA throughput measured by ec_valu_probe,
     # beside the published peaks that `roofline.peak` uses
     log("bench: vector-ALU probe")
@@ -490,31 +744,30 @@ def main():
         r32["measured_peak_unpacked"] = round(meas32, 2)
         r32["frac_of_measured_unpacked"] = round(r32["achieved"] / meas32, 4)
     if not args.skip_relax:
-        log("bench: mixed-N relaxation leg (200 graph-replayed FE steps)")
+        log("bench: mixed-N relaxation leg (200 FE steps in one captured graph)")
         out["relaxation"] = relaxation_leg(E, torch)
     if not args.skip_sweep:
         log("bench: 64^3 VHS precision sweep")
-        out["precision_sweep"] = precision_sweep_leg(E, torch)
+        out["precision_sweep"] = precision_sweep_leg(E, torch, efm)
     if not args.skip_surrogate:
         log("bench: learned surrogate (data, training, screened inference)")
         out["surrogate"] = surrogate_leg(E, torch, seconds=args.surrogate_seconds, log_fn=log)
         log(f"bench: surrogate {out['surrogate']}")
-    if not args.skip_parity or not args.skip_cpu:
-        from oracle import efm
+    if efm is not None:
         log("bench: oracle tables (quadrature)")
         oplan = efm.make_plan(N, D, L, M, R=R)
+        ids = [c for c in FULL_GRID_CELLS if c < args.cells]
+        log(f"bench: oracle on the full grid of cells {ids} (CPU baseline and parity)")
+        base, refs = cpu_baseline(cells, efm, oplan, ids)
+        if not args.skip_cpu:
+            out["cpu_baseline"] = base
         if not args.skip_parity:
-            log("bench: sampled parity vs oracle")
             out["parity"] = {
-                "metric": "max_r |Q - Q_oracle| / max_r |Q+_oracle| on 64 random and the 16 largest-F points x 2 cells",
-                "fp64": sampled_error(E, b64, Q64, cells, [0, args.cells - 1], oplan, efm),
+                "metric": "||Q - Q_oracle||_2 / ||Q+_oracle||_2 on the full grid of the cells "
+                          f"{ids} (oracle: double sum over modes), bound stated a priori",
+                **full_grid_parity(E, {"fp64": (0, b64, Q64), "fp32": (1, b32, Q32),
+                                       "bf16x3": (2, bb, Qb)}, refs),
             }
-            if b32 is not None:
-                out["parity"]["fp32"] = sampled_error(E, b32, Q32, cells, [0, args.cells - 1],
-                                                      oplan, efm)
-            if bb is not None:
-                out["parity"]["bf16x3"] = sampled_error(E, bb, Qb, cells, [0, args.cells - 1],
-                                                        oplan, efm)
             # every cell of the batch against the FP64 GPU result
             n = N ** D
             if Q64.numel() == args.cells * n:
@@ -527,9 +780,6 @@ def main():
                     out["parity"][f"{name}_vs_fp64_gpu_all_cells"] = {
                         "metric": "per-cell ||Q - Q_fp64|| / ||Q_fp64|| over all cells",
                         "median": float(r.median()), "max": float(r.max())}
-        if not args.skip_cpu:
-            log("bench: CPU baseline (oracle)")
-            out["cpu_baseline"] = cpu_baseline(cells, efm, oplan)
     print(json.dumps(out), flush=True)
 
 
