@@ -283,6 +283,13 @@ __global__ __launch_bounds__(N / P * N) void k_fused(
 // interleave).
 // ---------------------------------------------------------------------------
 
+// LDS row stride (in reals) of the column kernel's exchange buffer: even, so
+// that the rows of the z -> y transpose are 16-byte aligned and read as
+// 128-bit words (N + 1 rows were read as 64-bit words; measured at 32^3,
+// 1024 cells: FP64 3.26 -> 3.20 ms per launch)
+template <int N>
+constexpr int col_ld() { return N + 2; }
+
 // v as held by lane src4 / 4 of this wave (a lane permute; no LDS storage)
 __device__ __forceinline__ double lane_read(double v, int src4) {
   const long long b = __double_as_longlong(v);
@@ -313,41 +320,71 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Planes of the thread's spectrum inputs that the column kernel keeps in
+// registers for every term: all N/2 of them in FP32 at split 2 (64 more
+// registers, 219 in all; the gather then reads only the term table: 1024
+// cells of 32^3, 1.12 -> 1.055 ms per launch), none otherwise (no room next
+// to the FP64 column).
+template <typename R, int N, int P>
+constexpr int fh_regs() { return sizeof(R) == 4 && P == 2 ? N / 2 : 0; }
+
 // Gather of one term into the thread's z column v[k2] (plane a, column bq;
 // col = a N^2 + bq indexes its first table entry, fcol = a N^2 / 2 + bq its
-// first input in the half-space spectrum [k0][k2 < N/2][k1]): entries
-// k2 < N/2 from its own loads, k2 > N/2 from the mirror partner, whose lane
-// is partner4 / 4.
+// first input in the half-space spectrum [k0][k2 < N/2][k1], unless fh holds
+// them): entries k2 < N/2 from its own loads, k2 > N/2 from the mirror
+// partner, whose lane is partner4 / 4.  One group of GP planes of loads is in
+// flight at a time: issuing the next group's loads before combining this one
+// measured 3.5 % slower in FP64 and no faster in FP32 -- the gather is bound
+// by the bytes delivered into the CU, not by the round trip.
+template <typename R, int N, int P, int GP>
+__device__ __forceinline__ void gather_load(const cx<R>* __restrict__ Gt,
+                                            const cx<R>* __restrict__ Fc, int col, int fcol,
+                                            int k2, cx<R> (&gl)[GP][P], cx<R> (&fl)[GP][P]) {
+  constexpr int NP = N / P;
+#pragma unroll
+  for (int u = 0; u < GP; ++u) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      gl[u][j] = Gt[col + (NP * j * N + k2 + u) * N];
+      fl[u][j] = Fc[fcol + (NP * j * (N / 2) + k2 + u) * N];
+    }
+  }
+}
+
 template <typename R, int N, int P, int S>
 __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
                                            const cx<R>* __restrict__ Fc, int col, int fcol,
-                                           int partner4, cx<R> tw, cx<R> (&v)[N]) {
-  constexpr int NP = N / P;
+                                           int partner4, cx<R> tw,
+                                           const cx<R> (&fh)[fh_regs<R, N, P>() ? N / 2 : 1][P],
+                                           cx<R> (&v)[N]) {
   constexpr int GP = 2;                 // planes per group of loads (4 spill in FP64)
+  constexpr int NG = N / 2 / GP;
+  constexpr bool FH = fh_regs<R, N, P>() > 0;
   const cx<R> twc = {tw.x, -tw.y};
+  cx<R> gl[GP][P], fl[GP][P];
 #pragma unroll
-  for (int k2 = 0; k2 < N / 2; k2 += GP) {
-    cx<R> gl[GP][P], fl[GP][P];
+  for (int g = 0; g < NG; ++g) {
+    if constexpr (FH) {
 #pragma unroll
-    for (int u = 0; u < GP; ++u) {
+      for (int u = 0; u < GP; ++u)
 #pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const int idx = col + (NP * j * N + k2 + u) * N;
-        gl[u][j] = Gt[idx];
-        fl[u][j] = Fc[fcol + (NP * j * (N / 2) + k2 + u) * N];
-      }
+        for (int j = 0; j < P; ++j) gl[u][j] = Gt[col + ((N / P) * j * N + g * GP + u) * N];
+    } else {
+      gather_load<R, N, P, GP>(Gt, Fc, col, fcol, g * GP, gl, fl);
     }
+    __builtin_amdgcn_sched_barrier(0);  // this group's loads go out before its math
 #pragma unroll
     for (int u = 0; u < GP; ++u) {
-      const int kk = k2 + u;
+      const int kk = g * GP + u;
       cx<R> SA = {(R)0, (R)0}, SB = {(R)0, (R)0};
-      accum_roots<P, S>(gl[u], fl[u], SA, SB);
+      if constexpr (FH) accum_roots<P, S>(gl[u], fh[kk], SA, SB);
+      else accum_roots<P, S>(gl[u], fl[u], SA, SB);
       const cx<R> zp = {SA.x - SB.y, SA.y + SB.x}, zm = {SA.x + SB.y, SB.x - SA.y};
       // s = 0: the twiddle is exp(0) = 1
       v[kk] = S == 0 ? zp : cmul(tw, zp);
       if (kk > 0) v[N - kk] = lane_read(S == 0 ? zm : cmul(twc, zm), partner4);
     }
-    __builtin_amdgcn_sched_barrier(0);  // keep the next group's loads behind this group
+    __builtin_amdgcn_sched_barrier(0);  // and the next group's loads stay behind it
   }
   v[N / 2] = {(R)0, (R)0};
 }
@@ -355,19 +392,34 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
 template <typename R, int N, int P, int S = 0>
 __device__ __forceinline__ void gather_col_s(int s, const cx<R>* __restrict__ Gt,
                                              const cx<R>* __restrict__ Fc, int col, int fcol,
-                                             int partner4, cx<R> tw, cx<R> (&v)[N]) {
-  if (s == S) gather_col<R, N, P, S>(Gt, Fc, col, fcol, partner4, tw, v);
+                                             int partner4, cx<R> tw,
+                                             const cx<R> (&fh)[fh_regs<R, N, P>() ? N / 2 : 1][P],
+                                             cx<R> (&v)[N]) {
+  if (s == S) gather_col<R, N, P, S>(Gt, Fc, col, fcol, partner4, tw, fh, v);
   else if constexpr (S + 1 < P)
-    gather_col_s<R, N, P, S + 1>(s, Gt, Fc, col, fcol, partner4, tw, v);
+    gather_col_s<R, N, P, S + 1>(s, Gt, Fc, col, fcol, partner4, tw, fh, v);
+}
+
+// The thread's spectrum inputs of the planes kept in registers (fh_regs)
+template <typename R, int N, int P>
+__device__ __forceinline__ void load_fh(const cx<R>* __restrict__ Fc, int fcol,
+                                        cx<R> (&fh)[fh_regs<R, N, P>() ? N / 2 : 1][P]) {
+  if constexpr (fh_regs<R, N, P>() > 0) {
+#pragma unroll
+    for (int k2 = 0; k2 < N / 2; ++k2)
+#pragma unroll
+      for (int j = 0; j < P; ++j) fh[k2][j] = Fc[fcol + ((N / P) * j * (N / 2) + k2) * N];
+  }
 }
 
 template <typename R, int N, int P, bool LOSS>
 __device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt,
                                              const cx<R>* __restrict__ Fc, int a, int bq,
-                                             int partner4, cx<R> tw, R* buf,
-                                             const double* __restrict__ fc,
+                                             int partner4, cx<R> tw,
+                                             const cx<R> (&fh)[fh_regs<R, N, P>() ? N / 2 : 1][P],
+                                             R* buf, const double* __restrict__ fc,
                                              double (&acc)[P][N / P]) {
-  constexpr int NP = N / P, T = NP * N, LD = N + 1;
+  constexpr int NP = N / P, T = NP * N, LD = col_ld<N>();
   const int th = threadIdx.x;
   // offset by an opaque zero, the per-element addresses are formed here
   // instead of being hoisted out of the term loop (64 of them would stay live
@@ -376,7 +428,7 @@ __device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt
   const double* fp = fc + z0;
   cx<R> v[N];
   gather_col_s<R, N, P>(s, Gt, Fc, a * N * N + bq + z0, a * N * N / 2 + bq + z0, partner4, tw,
-                        v);
+                        fh, v);
   fft_line<N, +1>(v);                   // along z: (k', k1 = bq, z)
   R* pl = buf + a * N * LD;             // this half-wave's plane
   __syncthreads();                      // every wave is done reading the previous term
@@ -437,7 +489,7 @@ void k_fused_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
                  const double* f, const int64_t* __restrict__ off, int64_t cell0, int ncells,
                  double* Q, double dt) {
   static_assert(N == 32, "one half-wave per (plane, column) line");
-  constexpr int NP = N / P, T = NP * N, LD = N + 1, n = N * N * N;
+  constexpr int NP = N / P, T = NP * N, LD = col_ld<N>(), n = N * N * N;
   static_assert(T % 64 == 0 && T / 64 == NP / 2, "two planes per wave");
   __shared__ R buf[NP * N * LD];
   const int blk = blockIdx.x;
@@ -456,11 +508,13 @@ void k_fused_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
   const int64_t base = off[cell0 + cc];
   const double* fc = f + base;
   double acc[P][NP];
-  run_term_col<R, N, P, true>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4, tw, buf, fc,
+  cx<R> fh[fh_regs<R, N, P>() ? N / 2 : 1][P];
+  load_fh<R, N, P>(Fc, a * N * N / 2 + bq, fh);
+  run_term_col<R, N, P, true>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4, tw, fh, buf, fc,
                               acc);
   for (int term = 0; term < J - 1; ++term)
-    run_term_col<R, N, P, false>(s, G + (int64_t)term * n, Fc, a, bq, partner4, tw, buf, fc,
-                                 acc);
+    run_term_col<R, N, P, false>(s, G + (int64_t)term * n, Fc, a, bq, partner4, tw, fh, buf,
+                                 fc, acc);
   // fresh copies again, so that the output addresses are not shared with
   // (and kept live from) the loss term's reads of F
   const int z0 = opaque_zero();
@@ -491,7 +545,7 @@ void k_terms_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
                  const double* f, const int64_t* __restrict__ off, int64_t cell0, int ncells,
                  double* __restrict__ part) {
   static_assert(N == 32, "one half-wave per (plane, column) line");
-  constexpr int NP = N / P, T = NP * N, LD = N + 1, n = N * N * N;
+  constexpr int NP = N / P, T = NP * N, LD = col_ld<N>(), n = N * N * N;
   __shared__ R buf[NP * N * LD];
   const int blk = blockIdx.x;
   const int s = (blk / 8) % P;
@@ -507,15 +561,17 @@ void k_terms_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
   const cx<R>* Fc = Fh + (int64_t)cc * (n / 2);
   const double* fc = f + off[cell0 + cc];
   double acc[P][NP];
+  cx<R> fh[fh_regs<R, N, P>() ? N / 2 : 1][P];
+  load_fh<R, N, P>(Fc, a * N * N / 2 + bq, fh);
   if (term == J - 1) {
-    run_term_col<R, N, P, true>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4, tw, buf, fc,
-                                acc);
+    run_term_col<R, N, P, true>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4, tw, fh, buf,
+                                fc, acc);
   } else {
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
       for (int q = 0; q < NP; ++q) acc[p][q] = 0.0;
-    run_term_col<R, N, P, false>(s, G + (int64_t)term * n, Fc, a, bq, partner4, tw, buf, fc,
+    run_term_col<R, N, P, false>(s, G + (int64_t)term * n, Fc, a, bq, partner4, tw, fh, buf, fc,
                                  acc);
   }
   double* pc = part + ((int64_t)cc * J + term) * n;
