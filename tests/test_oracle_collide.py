@@ -238,3 +238,30 @@ def test_momentum_energy_not_conserved_but_converge():
         en.append(abs(m["energy"]))
         assert abs(m["energy"]) > 1e-8
     assert en[0] > en[1] > en[2]
+
+
+def test_time_integrators_on_a_linear_ode():
+    """The oracle's forward Euler and SSP-RK3 (Shu-Osher form, the paper's
+    integrator, section 4.1) on u' = lam u: one step multiplies u by the
+    stability polynomial, 1 + z and 1 + z + z^2/2 + z^3/6 (z = lam dt), the
+    latter being third order; a wrong stage weight changes the polynomial."""
+    u = np.array([1.0, -2.0, 0.5])
+    for lam, dt in ((-3.0, 0.01), (-0.7, 0.3), (1.3, 0.05)):
+        z = lam * dt
+        op = lambda v: lam * v   # noqa: E731
+        assert np.allclose(efm.fe_step(op, u, dt), (1 + z) * u, rtol=1e-15, atol=0)
+        assert np.allclose(efm.ssprk3_step(op, u, dt), (1 + z + z * z / 2 + z ** 3 / 6) * u,
+                           rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("d,N,M", [(2, 8, 4), (3, 6, 8)])
+def test_dense_kernel_sum_equals_low_rank_double_sum(d, N, M):
+    """collide_dense (numpy sum of eq. EFMk over a dense kernel-mode matrix)
+    with the low-rank kernel written out densely equals the C double sum of
+    eq. Qsk (two codes of the same definition)."""
+    L = 8.0
+    p = efm.make_plan(N, d, L, M, R=R)
+    F = _mix(61 + N, d, N, L)
+    q = efm.collide_dense(p.lr.matrix(), p.sigma, F, L)
+    ref = efm.collide_modes(p, F)
+    assert np.abs(q - ref.Q).max() <= 1e-13 * np.abs(ref.Qplus).max()
