@@ -302,17 +302,21 @@ def relaxation_leg(E, torch, steps=200, dt=0.01, n_cells=4096, seed=3000):
             "min_F": fmin}
 
 
-def surrogate_leg(E, torch, seconds=40.0, n_traj=500, n_steps=100, n_test=1024, dt=0.01, log_fn=None):
+def surrogate_leg(E, torch, seconds=40.0, n_traj=5000, n_steps=10, n_test=1024, dt=0.01, log_fn=None):
     """Learned surrogate at the headline size: (F, Q) pairs from n_traj
     forward-Euler trajectories of the exact FP64 operator (seeds 5001 + i,
-    n_steps steps each), training by the library's own kernels for `seconds`,
-    then n_test fresh cells (seeds 6001 + i): relative L2 error of the raw
-    network and of the screened result against the FP64 operator, fallback
-    count, and evals/s of the screened path (network, screen and fallback
-    inside the timed region) beside the exact operator's."""
+    n_steps steps each: 50 000 pairs, the fresh cells and their first steps,
+    the distribution the surrogate is applied to), training by the library's
+    own kernels for `seconds`, then n_test fresh cells (seeds 6001 + i):
+    relative L2 error of the raw network and of the screened result against
+    the FP64 operator, the stated bound and whether the accepted cells meet
+    it, fallback count, and evals/s of the screened path (network, screen and
+    fallback inside the timed region) beside the exact FP64 and FP32
+    operator's."""
     import numpy as np
     import synth
-    from paper_1704_07369_amd.surrogate import DEFAULT, Surrogate, generate_pairs, train
+    from paper_1704_07369_amd.surrogate import (DEFAULT, SCREEN_TAU_E, SCREEN_TAU_M,
+                                                SURROGATE_BOUND, Surrogate, generate_pairs, train)
     plan = E.Plan(N, D, L, M, R=R)
     sur = Surrogate(N, seed=1234, max_batch=64, **DEFAULT)
     t0 = time.perf_counter()
@@ -336,6 +340,19 @@ def surrogate_leg(E, torch, seconds=40.0, n_traj=500, n_steps=100, n_test=1024, 
         b.collide(f, Qe)
     torch.cuda.synchronize()
     t_exact = (time.perf_counter() - t0) / 3
+    b32 = E.Batch([plan], [n_test], E.EC_FP32)
+    Q32 = torch.zeros_like(f)
+    b32.autotune(f, Q32, TUNE_CACHE)
+    b32.collide(f, Q32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        b32.collide(f, Q32)
+    torch.cuda.synchronize()
+    t_exact32 = (time.perf_counter() - t0) / 3
+    e32 = ((Q32 - Qe).view(n_test, -1).norm(dim=1) / Qe.view(n_test, -1).norm(dim=1)).max().item()
+    b32.close()
+    del Q32
     # raw network output (no screen), per-cell relative L2 error
     n = N ** D
     mb = sur.max_batch
@@ -367,8 +384,11 @@ def surrogate_leg(E, torch, seconds=40.0, n_traj=500, n_steps=100, n_test=1024, 
     sur.collide(b, f, Qs, tau_m=-1.0, fell_back=fell, screen=scr_d)
     scr_h = scr_d.view(n_test, 4).cpu().numpy()
     sweep = []
-    for tm, te in [(1e-3, 1e-2), (1e-2, 1e-2), (1e-2, 5e-2), (5e-2, 5e-2), (1.0, 1.0)]:
-        ok = (scr_h[:, 0] <= 0) & (scr_h[:, 1] <= tm) & (scr_h[:, 2] <= te) & (scr_h[:, 3] <= te)
+    for tm, te in [(SCREEN_TAU_M, SCREEN_TAU_E), (1e-3, -1.0), (1e-2, -1.0), (1e-3, 1e-2),
+                   (1e-2, 5e-2), (1.0, -1.0)]:
+        ok = (scr_h[:, 0] <= 0) & (scr_h[:, 1] <= tm)
+        if te >= 0:
+            ok &= (scr_h[:, 2] <= te) & (scr_h[:, 3] <= te)
         sweep.append({"tau_m": tm, "tau_e": te, "accepted": int(ok.sum()),
                       "accepted_rel_l2_max": float(proj[ok].max()) if ok.any() else None})
     nf = sur.collide(b, f, Qs, fell_back=fell)
@@ -392,12 +412,17 @@ def surrogate_leg(E, torch, seconds=40.0, n_traj=500, n_steps=100, n_test=1024, 
         "projected_evals_per_s": n_test / t_net,
         "screen_sweep": sweep,
         "raw_residual_median": [float(np.median(scr_h[:, i])) for i in (1, 2, 3)],
+        "screen": {"tau_m": SCREEN_TAU_M, "tau_e": SCREEN_TAU_E,
+                   "rule": "H-functional of the projected Q <= 0 and raw mass residual <= tau_m"},
+        "bound": SURROGATE_BOUND,
         "fallback_cells": int(nf),
         "accepted_rel_l2_median": float(np.median(scr[acc])) if acc.any() else None,
         "accepted_rel_l2_max": float(scr[acc].max()) if acc.any() else None,
+        "within_bound": bool(scr.max() <= SURROGATE_BOUND),
         "screened_rel_l2_max": float(scr.max()),
         "screened_evals_per_s": n_test / t_sur, "exact_fp64_evals_per_s": n_test / t_exact,
-        "gain_vs_exact_fp64": t_exact / t_sur,
+        "exact_fp32_evals_per_s": n_test / t_exact32, "exact_fp32_rel_l2_max": e32,
+        "gain_vs_exact_fp64": t_exact / t_sur, "gain_vs_exact_fp32": t_exact32 / t_sur,
     }
 
 

@@ -107,9 +107,14 @@ __global__ __launch_bounds__(256) void k_screen(const double* __restrict__ f,
     const double P = h * h * h * red[0];
     o[0] = P;
     const double mass_res = o[1], mom_res = o[2], en_res = o[3];
-    const bool ok = tau_m < 0.0 ||     // screen disabled: every cell keeps the prediction
-                    ((P <= 0.0) && (mass_res <= tau_m) && (mom_res <= tau_e) &&
-                     (en_res <= tau_e) && isfinite(P) && isfinite(mass_res));
+    // tau_m < 0: screen disabled, every cell keeps the prediction;
+    // tau_e < 0: no momentum and energy checks (the exact operator conserves
+    // neither exactly on the grid, and their residuals do not single out the
+    // cells the network predicts worst)
+    const bool moments_ok = tau_e < 0.0 || ((mom_res <= tau_e) && (en_res <= tau_e));
+    const bool ok = tau_m < 0.0 ||
+                    ((P <= 0.0) && (mass_res <= tau_m) && moments_ok && isfinite(P) &&
+                     isfinite(mass_res));
     flag[c] = ok ? 0 : 1;
   }
 }

@@ -14,6 +14,15 @@ from .batch import Batch, Plan, pack
 # network of the learned surrogate: 4 layers, 16 channels, 12 modes per axis
 DEFAULT = dict(modes=12, channels=16, layers=4)
 
+# Stated accuracy of the screened surrogate: relative L2 error of every
+# accepted cell's Q against the exact FP64 operator <= SURROGATE_BOUND; cells
+# failing the screen take the exact operator's Q.  Default screen: discrete
+# H-functional of the projected Q <= 0 (Theorem 1) and mass residual of the
+# raw prediction <= 5e-3; no momentum/energy check (tau_e < 0).
+SURROGATE_BOUND = 5e-2
+SCREEN_TAU_M = 5e-3
+SCREEN_TAU_E = -1.0
+
 
 class Surrogate:
     def __init__(self, N=32, modes=12, channels=16, layers=4, seed=1234, max_batch=16):
@@ -43,7 +52,8 @@ class Surrogate:
     def train_step(self, Fin, target, nb, lr, update=True, want_loss=True):
         return B.ec_surrogate_train(self.handle, Fin, target, nb, lr, update, want_loss)
 
-    def collide(self, batch: Batch, f, Q, tau_m=1e-3, tau_e=5e-2, fell_back=None, screen=None):
+    def collide(self, batch: Batch, f, Q, tau_m=SCREEN_TAU_M, tau_e=SCREEN_TAU_E, fell_back=None,
+                screen=None):
         return B.ec_surrogate_collide(self.handle, batch.handle, f, Q, tau_m, tau_e, fell_back,
                                       screen)
 

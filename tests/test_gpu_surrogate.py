@@ -196,3 +196,44 @@ def test_mass_projection_matches_reference():
                abs((raw * (vx**2 + vy**2 + vz**2)).sum()) / (3 * L * L * ra)]
         got = scr.cpu().numpy()[c * 4 + 1:c * 4 + 4]
         assert np.allclose(got, res, rtol=1e-8, atol=1e-14), (got, res)
+
+
+def test_screen_flags_follow_the_stated_rule():
+    """ec_surrogate_collide's screen: a cell falls back unless the projected
+    Q's H-functional is <= 0, the raw mass residual <= tau_m and, when
+    tau_e >= 0, the momentum and energy residuals <= tau_e.  Checked flag by
+    flag against the screen values it reports, for tau_e < 0 (the default:
+    no moment checks) and for a tau_e that every cell fails; fallen-back
+    cells carry the exact operator's Q."""
+    import torch
+    from paper_1704_07369_amd.surrogate import SCREEN_TAU_E, SCREEN_TAU_M
+    say("case surrogate screen rule")
+    N, L, M = 16, 8.0, 32
+    plan = E.Plan(N, 3, L, M, R=6.0)
+    nc = 6
+    cells = [synth.sample_mixture(synth.mixture_anisotropic(900 + i, 3), N, L) for i in range(nc)]
+    b = E.Batch([plan], [nc])
+    f = to_dev(E.pack(b, cells))
+    Qe = torch.zeros_like(f)
+    b.collide(f, Qe)
+    sur = Surrogate(N, 6, 8, 2, seed=3, max_batch=4)
+    qe = E.unpack(b, Qe.cpu().numpy())
+    assert SCREEN_TAU_E < 0 and SCREEN_TAU_M > 0
+    for tau_m, tau_e in ((SCREEN_TAU_M, SCREEN_TAU_E), (1.0, 1e-12), (1.0, -1.0)):
+        Qs = torch.zeros_like(f)
+        fell = torch.zeros(nc, dtype=torch.int32, device="cuda")
+        scr = torch.zeros(nc * 4, dtype=torch.float64, device="cuda")
+        nf = sur.collide(b, f, Qs, tau_m=tau_m, tau_e=tau_e, fell_back=fell, screen=scr)
+        torch.cuda.synchronize()
+        s = scr.cpu().numpy().reshape(nc, 4)
+        ok = (s[:, 0] <= 0) & (s[:, 1] <= tau_m)
+        if tau_e >= 0:
+            ok &= (s[:, 2] <= tau_e) & (s[:, 3] <= tau_e)
+        fl = fell.cpu().numpy()
+        say(f"  tau_m {tau_m} tau_e {tau_e}: fallback {fl.tolist()}")
+        assert fl.tolist() == (~ok).astype(int).tolist() and nf == int((~ok).sum())
+        if tau_e == 1e-12:
+            assert nf == nc
+        qs = E.unpack(b, Qs.cpu().numpy())
+        for c in np.nonzero(fl)[0]:
+            assert np.abs(qs[c] - qe[c]).max() <= 1e-14 * np.abs(qe[c]).max()
