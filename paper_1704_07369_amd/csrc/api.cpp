@@ -153,6 +153,20 @@ int64_t terms_default_max_cells(int N, int precision) {
   }
 }
 
+// Largest 2D group that starts on the term-parallel schedule (one block per
+// (cell, term)).  Measured at 32^2, M = 16 (FP64, wall time per call):
+// 1 cell 16 us against 101 us for the two-pass slab pass (one block walking
+// every term), 64 cells 24 / 103 us, 1024 cells 101 / 118 us.
+constexpr int64_t kTerms2dMaxCells = 1024;
+
+// The term-parallel schedule exists for 3D N = 16, 24, 32 (FP64, FP32) and
+// for the small 2D grids (two-pass sizes, FP64, FP32).
+bool terms_ok(const HostTables& T, int precision) {
+  if (T.d == 2)
+    return T.N < 64 && terms_2d_supported(T.N) && precision != EC_BF16X3;
+  return T.d == 3 && terms_supported(T.N, precision, terms_default_split(T.N, precision));
+}
+
 int device_cus() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -187,11 +201,15 @@ void default_schedule(BatchGroup& g, int precision) {
   if (g.mode == EC_SCHED_LINES && !lines_supported(T, precision)) g.mode = EC_SCHED_TWO_PASS;
   if (g.mode == EC_SCHED_FUSED && (T.d != 3 || fused_default_split(T.N, precision) == 0))
     g.mode = EC_SCHED_TWO_PASS;
-  if (g.mode == EC_SCHED_TERMS &&
-      (T.d != 3 || !terms_supported(T.N, precision, terms_default_split(T.N, precision))))
-    g.mode = EC_SCHED_PIPELINE;
+  if (g.mode == EC_SCHED_TERMS && !terms_ok(T, precision)) g.mode = EC_SCHED_PIPELINE;
   if (g.mode == EC_SCHED_PIPELINE && T.N > 32) g.mode = EC_SCHED_TWO_PASS;   // register lines <= 32
-  if (T.d == 3 && g.mode == EC_SCHED_TERMS) {
+  if (T.d == 2 && g.mode == EC_SCHED_TERMS) {
+    // per cell: the spectrum and J N^2 FP64 term partials; passes under ~2 GiB
+    const double per_cell = (double)T.J * T.n * 8.0;
+    const int64_t c = (int64_t)std::max(1.0, std::floor(2.0 * 1073741824.0 / per_cell));
+    g.chunk = (int)std::max<int64_t>(1, std::min<int64_t>(c, count));
+    g.G = 1;
+  } else if (T.d == 3 && g.mode == EC_SCHED_TERMS) {
     // per cell: the half spectrum and J N^3 FP64 term partials; keep a pass
     // under ~2 GiB of partials
     const double per_cell = (double)T.J * T.n * 8.0;
@@ -242,7 +260,9 @@ void default_schedule(BatchGroup& g, int precision) {
 bool use_pipe(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_PIPELINE; }
 bool use_fused(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_FUSED; }
 bool use_lines(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_LINES; }
-bool use_terms(const BatchGroup& g) { return g.plan->host.d == 3 && g.mode == EC_SCHED_TERMS; }
+bool use_terms(const BatchGroup& g) {
+  return g.mode == EC_SCHED_TERMS && (g.plan->host.d == 3 || !is_large2d(g.plan->host));
+}
 bool fp32_tables(int precision) { return precision != EC_FP64; }
 
 size_t group_ws_bytes(const BatchGroup& g, int precision) {
@@ -664,9 +684,11 @@ int ec_batch_create(const ec_plan* const* plans, const int64_t* counts, int n_gr
       // groups of other sizes take the pipelined schedule (term groups
       // spread one cell over many workgroups); each falls back to two-pass
       // where absent
-      bg.mode = counts[g] <= terms_default_max_cells(plans[g]->host.N, precision)
-                    ? EC_SCHED_TERMS
-                    : (counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_PIPELINE);
+      const int64_t tmax = plans[g]->host.d == 2
+                               ? kTerms2dMaxCells
+                               : terms_default_max_cells(plans[g]->host.N, precision);
+      bg.mode = counts[g] <= tmax ? EC_SCHED_TERMS
+                                  : (counts[g] >= 32 ? EC_SCHED_FUSED : EC_SCHED_PIPELINE);
       default_schedule(bg, precision);
       const HostTables& T = plans[g]->host;
       const double hd = std::pow(2.0 * T.L / T.N, T.d);
@@ -752,12 +774,10 @@ int ec_batch_set_schedule(ec_batch* b, int group, int mode, int cells_per_pass, 
       g = saved;
       return rc;
     };
-    if (mode == EC_SCHED_TERMS &&
-        (g.plan->host.d != 3 ||
-         !terms_supported(g.plan->host.N, b->precision,
-                          terms_default_split(g.plan->host.N, b->precision))))
+    if (mode == EC_SCHED_TERMS && !terms_ok(g.plan->host, b->precision))
       return fail(EC_ERR_UNSUPPORTED,
-                  "the term-parallel schedule needs 3D cells of N = 16, 24 or 32 in FP64 or FP32");
+                  "the term-parallel schedule needs 3D cells of N = 16, 24 or 32 or 2D cells of "
+                  "N <= 32, in FP64 or FP32");
     if (mode == EC_SCHED_LINES && !lines_supported(g.plan->host, b->precision))
       return fail(EC_ERR_UNSUPPORTED, "the lines schedule needs 3D cells of N = 64 or 128 in FP64");
     if (mode != EC_SCHED_LINES && is_large3d_only(g.plan->host))
@@ -961,6 +981,12 @@ int ec_autotune(ec_batch* b, const double* f, double* Q, const char* cache_path,
               for (auto& x : cand) dup |= (x.mode == sc.mode && x.chunk == sc.chunk && x.G == sc.G);
               if (!dup) cand.push_back(sc);
             }
+      }
+      if (T.d == 2 && count < 256 && terms_ok(T, b->precision)) {
+        BatchGroup probe = g;
+        probe.mode = EC_SCHED_TERMS;
+        default_schedule(probe, b->precision);
+        cand.push_back(Sched{EC_SCHED_TERMS, probe.chunk, 1});
       }
       if (T.d == 3 && count < 256 &&
           terms_supported(T.N, b->precision, terms_default_split(T.N, b->precision))) {

@@ -678,10 +678,13 @@ static hipError_t launch_terms_t(const ChunkArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_terms_lds<R, N, P>), grid, dim3(fused_threads<N, P>()), 0, st,
                        (const cx<R>*)W, (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0,
                        a.ncells, (double*)a.Z);
-  const int64_t pts = (int64_t)a.ncells * N * N * N;
+  return launch_terms_reduce(a, N * N * N, st);
+}
+
+hipError_t launch_terms_reduce(const ChunkArgs& a, int n, hipStream_t st) {
+  const int64_t pts = (int64_t)a.ncells * n;
   hipLaunchKernelGGL(k_terms_reduce, dim3((unsigned)((pts + 255) / 256)), dim3(256), 0, st,
-                     (const double*)a.Z, a.J, N * N * N, a.f, a.off, a.cell0, a.ncells, a.Q,
-                     a.dt);
+                     (const double*)a.Z, a.J, n, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
   if (a.ev) (void)hipEventRecord(a.ev[3], st);
   return hipGetLastError();
 }
@@ -693,6 +696,7 @@ bool terms_supported(int N, int precision, int split) {
 
 hipError_t launch_terms(const ChunkArgs& a, int split, hipStream_t st) {
   if (a.ncells <= 0) return hipSuccess;
+  if (a.d == 2) return launch_terms_2d(a, st);
   if (a.d != 3 || !terms_supported(a.N, a.precision, split) || !a.Z) return hipErrorInvalidValue;
   if (a.precision == 0) {
     if (a.N == 16) return split == 1 ? launch_terms_t<double, 16, 1>(a, st)

@@ -31,6 +31,17 @@ struct ChunkArgs {
 
 hipError_t launch_chunk(const ChunkArgs& a, hipStream_t s);
 
+// Q = sum of the term partials a.Z ([ncells][J][n] doubles) per point in the
+// fused kernel's order (the loss term's -F l first, then the terms); Euler
+// update when a.dt != 0.  Records a.ev[3] after it when a.ev is set.
+hipError_t launch_terms_reduce(const ChunkArgs& a, int n, hipStream_t s);
+
+// 2D term-parallel schedule (N = 8, 12, 16, 24, 32; FP64 or FP32): the
+// forward transform into a.W, one block per (cell, term) writing that term's
+// products to a.Z (ncells x J x N^2 doubles), then launch_terms_reduce.
+bool terms_2d_supported(int N);
+hipError_t launch_terms_2d(const ChunkArgs& a, hipStream_t s);
+
 // k_fwd only (3D, N in 16, 24, 32, 64): W[cell][x][k2][k1] = 2D transform of
 // every x slab; half (N = 16, 24, 32): only k2 < N/2, W[cell][x][k2 < N/2][k1].
 // Records a.ev[0] before it when a.ev is set.

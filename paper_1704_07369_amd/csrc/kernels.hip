@@ -221,6 +221,82 @@ __global__ __launch_bounds__(slabs_per_block<N>() * N) void k_slab(
   }
 }
 
+// ---------------------------------------------------------------------------
+// 2D term-parallel form for small batches: one block of N threads per (cell,
+// term) runs that term's inverse 2D transform (the slab pass of one term) and
+// writes its products, or for the loss term -F l, to part[cell][term][n];
+// k_terms_reduce sums them per point (loss first, then the terms in order).
+// A single cell then takes about one term's latency instead of J terms'.
+// ---------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__(N) void k_terms_2d(const cx<R>* __restrict__ W,
+                                                const cx<R>* __restrict__ G, int J,
+                                                const double* f,
+                                                const int64_t* __restrict__ off, int64_t cell0,
+                                                int ncells, double* __restrict__ part) {
+  constexpr int P = N * N;
+  __shared__ cx<R> lds[N][N + 1];
+  const int cc = blockIdx.x, j = blockIdx.y, i = threadIdx.x;
+  if (cc >= ncells) return;             // whole block
+  const cx<R>* Wc = W + (int64_t)cc * P;
+  const cx<R>* Gj = G + (int64_t)j * P;
+  cx<R> v[N];
+#pragma unroll
+  for (int k2 = 0; k2 < N; ++k2) v[k2] = cmul(Gj[k2 * N + i], Wc[k2 * N + i]);
+  fft_line<N, +1>(v);                   // along z: (k1 = i, z)
+#pragma unroll
+  for (int z = 0; z < N; ++z) lds[i][z] = v[z];
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) v[k1] = lds[k1][i];
+  fft_line<N, +1>(v);                   // along y: c_j(y, z = i)
+  double* pc = part + ((int64_t)cc * J + j) * P;
+  if (j == J - 1) {
+    const double* fc = f + off[cell0 + cc];
+#pragma unroll
+    for (int y = 0; y < N; ++y) pc[y * N + i] = -fc[y * N + i] * (double)v[y].x;
+  } else {
+#pragma unroll
+    for (int y = 0; y < N; ++y) pc[y * N + i] = (double)v[y].x * (double)v[y].y;
+  }
+}
+
+template <typename R, int N>
+static hipError_t launch_terms_2d_t(const ChunkArgs& a, hipStream_t st) {
+  constexpr int SPB = slabs_per_block<N>();
+  const int slab_blocks = (int)((a.ncells + SPB - 1) / SPB);
+  cx<R>* W = (cx<R>*)a.W;
+  if (a.ev) (void)hipEventRecord(a.ev[0], st);
+  hipLaunchKernelGGL((k_fwd<R, 1, N>), dim3(slab_blocks), dim3(SPB * N), 0, st, a.f, a.off,
+                     a.cell0, a.ncells, W);
+  if (a.ev) (void)hipEventRecord(a.ev[1], st);
+  if (a.ev) (void)hipEventRecord(a.ev[2], st);
+  hipLaunchKernelGGL((k_terms_2d<R, N>), dim3((unsigned)a.ncells, (unsigned)a.J), dim3(N), 0, st,
+                     (const cx<R>*)W, (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0, a.ncells,
+                     (double*)a.Z);
+  return launch_terms_reduce(a, N * N, st);
+}
+
+bool terms_2d_supported(int N) { return N == 8 || N == 12 || N == 16 || N == 24 || N == 32; }
+
+hipError_t launch_terms_2d(const ChunkArgs& a, hipStream_t st) {
+  if (a.ncells <= 0) return hipSuccess;
+  if (a.d != 2 || !terms_2d_supported(a.N) || !a.Z || a.precision == 2) return hipErrorInvalidValue;
+#define EFM_CASE2(NN)                                                               \
+  case NN:                                                                          \
+    return a.precision == 0 ? launch_terms_2d_t<double, NN>(a, st) : launch_terms_2d_t<float, NN>(a, st);
+  switch (a.N) {
+    EFM_CASE2(8)
+    EFM_CASE2(12)
+    EFM_CASE2(16)
+    EFM_CASE2(24)
+    EFM_CASE2(32)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef EFM_CASE2
+}
+
 template <typename R, int N0, int N>
 static hipError_t launch_chunk_t(const ChunkArgs& a, hipStream_t st) {
   constexpr int SPB = slabs_per_block<N>();

@@ -262,3 +262,48 @@ def test_step_graph_matches_oracle_euler():
     # a second call replays the cached graph from the new state
     b.step(f, dt, 1, mon)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("N,M,ncell,prec", [(32, 16, 1, 0), (32, 16, 5, 0), (16, 8, 3, 0),
+                                            (32, 16, 3, 1), (24, 8, 2, 0)])
+def test_2d_term_parallel(N, M, ncell, prec):
+    """Small 2D batches default to the term-parallel schedule (one block per
+    (cell, term), partial products summed in the fixed order loss-first):
+    the full grid against the oracle's double sum, against the two-pass
+    schedule on the same cells, and three forward-Euler steps of the captured
+    graph against the two-pass schedule's."""
+    import torch
+    say(f"case 2D term-parallel N={N} M={M} cells={ncell} precision={prec}")
+    L = 8.0
+    p = E.Plan(N, 2, L, M, R=R)
+    cells = mixtures(2, N, L, ncell, 4400 + N)
+    if ncell > 1:
+        cells[1] = synth.bkw_datum(2, N, L)
+    outs, steps = {}, {}
+    for mode in (E.EC_SCHED_TERMS, E.EC_SCHED_TWO_PASS):
+        b = E.Batch([p], [ncell], prec)
+        if mode == E.EC_SCHED_TWO_PASS:
+            b.set_schedule(0, mode, 0, 0)
+        say(f"  schedule {b.get_schedule(0)}")
+        assert b.get_schedule(0)[0] == mode
+        f = to_dev(E.pack(b, cells))
+        Q = torch.full_like(f, float("nan"))
+        b.collide(f, Q)
+        b.step(f, 0.01, 3)
+        torch.cuda.synchronize()
+        outs[mode] = E.unpack(b, Q.cpu().numpy())
+        steps[mode] = E.unpack(b, f.cpu().numpy())
+        b.close()
+    op = oplan(N, 2, L, M)
+    for c in range(ncell):
+        qt, q2 = outs[E.EC_SCHED_TERMS][c], outs[E.EC_SCHED_TWO_PASS][c]
+        ref = efm.collide_modes(op, cells[c])
+        err = rel_err(qt, ref.Q, ref.Qplus)
+        tol = bound_full(prec, N, 2, ref)
+        d2 = np.abs(qt - q2).max() / np.abs(ref.Qplus).max()
+        ds = np.abs(steps[E.EC_SCHED_TERMS][c] - steps[E.EC_SCHED_TWO_PASS][c]).max()
+        say(f"  cell {c}: vs oracle {err:.2e} (bound {tol:.1e}), vs two-pass {d2:.1e}, "
+            f"3 steps vs two-pass {ds:.1e}")
+        assert err <= tol
+        assert d2 <= (1e-14 if prec == 0 else 1e-6)
+        assert ds <= (1e-14 if prec == 0 else 1e-6) * np.abs(steps[E.EC_SCHED_TWO_PASS][c]).max()
