@@ -97,7 +97,8 @@ def test_small_batch_defaults_of_other_sizes():
     crossover (FP64 / FP32: 16^3 192 / 192 cells, 24^3 64 / 80, 32^3 48 / 40),
     fused above it (x split 4 for 32^3 launches of up to CUs / 4 cells, 2 for
     24^3 launches where 2 workgroups per cell fill one round and 3 do not),
-    two-pass at 64^3 and for 2D grids (whose groups always run two-pass)."""
+    two-pass at 64^3; 2D grids of N <= 32 term-parallel up to 1024 cells (the
+    2D form: one block per cell and term), two-pass above."""
     say("case small-batch defaults of other sizes")
     T, F = E.EC_SCHED_TERMS, E.EC_SCHED_FUSED
     for N, d, prec, count, want in [
@@ -105,7 +106,8 @@ def test_small_batch_defaults_of_other_sizes():
             (16, 3, 1, 192, T), (16, 3, 1, 193, F), (24, 3, 0, 64, T), (24, 3, 0, 65, F),
             (24, 3, 1, 80, T), (24, 3, 1, 81, F), (32, 3, 0, 48, T), (32, 3, 0, 49, F),
             (32, 3, 1, 40, T), (32, 3, 1, 41, F),
-            (64, 3, 0, 2, E.EC_SCHED_TWO_PASS), (32, 2, 0, 2, E.EC_SCHED_TWO_PASS)]:
+            (64, 3, 0, 2, E.EC_SCHED_TWO_PASS), (32, 2, 0, 2, T), (32, 2, 1, 1024, T),
+            (32, 2, 0, 1025, E.EC_SCHED_TWO_PASS)]:
         p = E.Plan(N, d, L, 8, R=R)
         b = E.Batch([p], [count], prec)
         say(f"  N={N} d={d} precision={prec} cells={count}: schedule {b.get_schedule(0)}")
