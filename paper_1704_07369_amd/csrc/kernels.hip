@@ -15,6 +15,8 @@
 //           c_j(x, y, z); gain += Re c_j Im c_j in FP64 (j < J-1), loss
 //           l = Re c_{J-1}; then Q = gain - F l (or F + dt Q, in place).
 //           In 2D the x pass is empty and k_slab reads gamma_j W directly.
+//   At N0 = N = 64 the x and slab passes are k_pencil64 and k_slab64: four
+//   threads per 64-point line, 16 values each, radix-4 exchanges in LDS.
 //
 // Every access is coalesced: consecutive threads touch consecutive k1 (or z).
 // Transforms are unnormalised; N^-d, the quadrature weights and the filter
@@ -103,63 +105,197 @@ __global__ __launch_bounds__(PENCIL_BS) void k_pencil(
   }
 }
 
-// The same x pass for FP64 pencils of N0 = 64, two threads per pencil (a
-// 64-point line of FP64 complex values does not fit in a thread's registers
-// next to the transform's temporaries).  One radix-2 step by decimation in
-// frequency splits every 64-point DFT into two 32-point ones:
-//   X(2m)   = DFT32[v(k) + v(k + 32)](m),
-//   X(2m+1) = DFT32[(v(k) - v(k + 32)) w^k](m),   w = exp(+-2 pi i / 64);
-// thread h of the pair transforms the sequence h and owns the outputs 2m + h.
-constexpr int PAIR_PENCILS = PENCIL_BS / 2;
+// ---------------------------------------------------------------------------
+// 64^3 passes: every 64-point line split over four threads
+// ---------------------------------------------------------------------------
+// A line of 64 complex values fills a thread's registers (FP64) and leaves
+// one wave per SIMD.  At N = 64 both passes give each thread 16 values of a
+// line: with k = 4 m + q and x = 16 a + b (decimation in time) or k = 16 a +
+// b and x = 4 c + r (decimation in frequency) the 64-point DFT is a 16-point
+// DFT in registers, the twiddle exp(SIGN 2 pi i q b / 64) and a 4-point DFT
+// over the four threads of the line, which meet in LDS.  Blocks of 256
+// threads (four waves), two or more blocks per CU.
+constexpr int L64_BS = 256;
 
-// the radix-2 step for one k: thread h keeps v(k) + v(k + 32) (h = 0) or
-// (v(k) - v(k + 32)) w^k (h = 1)
+struct Tw64Pairs {
+  double v[128];
+};
+constexpr Tw64Pairs make_tw64() {
+  Tw64Pairs t{};
+  for (int j = 0; j < 64; ++j) {
+    t.v[2 * j] = Tw<64>::c[j];
+    t.v[2 * j + 1] = Tw<64>::s[j];
+  }
+  return t;
+}
+// exp(2 pi i j / 64) as (cos, sin) pairs, for exponents known at run time
+__constant__ Tw64Pairs kTw64 = make_tw64();
+
 template <int SIGN, typename R>
-__device__ __forceinline__ cx<R> dif2(cx<R> lo, cx<R> hi, int h, int k) {
-  return h ? twiddle<64, SIGN>(csub(lo, hi), k) : cadd(lo, hi);
+__device__ __forceinline__ cx<R> root64(int j) {
+  return {(R)kTw64.v[2 * j], (R)(SIGN > 0 ? kTw64.v[2 * j + 1] : -kTw64.v[2 * j + 1])};
 }
 
-template <typename R, int N>
-__global__ __launch_bounds__(PENCIL_BS) void k_pencil_pair64(
-    const cx<R>* __restrict__ W, const cx<R>* __restrict__ G, int J, int ncells,
-    cx<R>* __restrict__ Z) {
-  constexpr int N0 = 64;
-  constexpr int P = N * N;
-  __shared__ cx<R> fh[N0][PAIR_PENCILS];
-  const int h = threadIdx.x & 1, lp = threadIdx.x >> 1;
-  const int64_t gid = (int64_t)blockIdx.x * PAIR_PENCILS + lp;
-  const bool active = gid < (int64_t)ncells * P;
-  const int cc = active ? (int)(gid / P) : 0;
-  const int p = active ? (int)(gid % P) : 0;
-  cx<R> u[32];
+// x pass at N0 = N = 64: one block per 64 pencils p (64 blocks per cell; the
+// blocks of one pencil range share an XCD, so its table slice is reused from
+// L2 by the cells in flight).  Thread (w, lane) takes pencil p = 64 (block %
+// 64) + lane.  Forward: it loads x = 4 m + w, m < 16 (decimation in time) and
+// keeps Fh(16 a + 4 w + i), a, i < 4, in registers for every term.  Per term:
+// u = gamma_j Fh, the 4-point DFT over a, the twiddle exp(2 pi i b r / 64),
+// LDS, and the 16-point DFT over b of residue r = w: Z_j(x = 4 c + w, p).
+template <typename R>
+__global__ __launch_bounds__(L64_BS) void k_pencil64(const cx<R>* __restrict__ W,
+                                                     const cx<R>* __restrict__ G, int J,
+                                                     cx<R>* __restrict__ Z) {
+  constexpr int N = 64, P = N * N;
+  __shared__ cx<R> lds[4 * 16 * 64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cc = blockIdx.x >> 6;
+  const int p = ((blockIdx.x & 63) << 6) + lane;
+  cx<R> fh[16];                             // Fh(16 a + 4 w + i) at [4 i + a]
   {
-    const cx<R>* Wc = W + (int64_t)cc * N0 * P + p;
+    const cx<R>* Wc = W + (int64_t)cc * N * P + p;
+    cx<R> v[16];
 #pragma unroll
-    for (int k = 0; k < 32; ++k)
-      u[k] = dif2<-1>(Wc[(int64_t)k * P], Wc[(int64_t)(k + 32) * P], h, k);
+    for (int m = 0; m < 16; ++m) v[m] = Wc[(int64_t)(4 * m + w) * P];
+    fft_line<16, -1>(v);                    // over m, residue q = w
+#pragma unroll
+    for (int b = 1; b < 16; ++b) v[b] = cmul(v[b], root64<-1, R>(w * b));
+#pragma unroll
+    for (int b = 0; b < 16; ++b) lds[(w * 16 + b) * 64 + lane] = v[b];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      cx<R> t[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t[q] = lds[(q * 16 + 4 * w + i) * 64 + lane];
+      butterfly<4, -1>(t);                  // over q: Fh(16 a + b) at t[a]
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fh[4 * i + a] = t[a];
+    }
+    __syncthreads();                        // the exchange buffer is free again
   }
-  fft_line<32, -1>(u);                      // along x: Fh(2m + h, p), unnormalised
+  cx<R> g[16];
+  auto load_g = [&](int j) {
+    const cx<R>* Gj = G + (int64_t)j * N * P + p;
 #pragma unroll
-  for (int m = 0; m < 32; ++m) fh[2 * m + h][lp] = u[m];
-  __syncthreads();                          // both halves of every pencil are in LDS
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) g[4 * i + a] = Gj[(int64_t)(16 * a + 4 * w + i) * P];
+  };
+  load_g(0);
   for (int j = 0; j < J; ++j) {
-    const cx<R>* Gj = G + ((int64_t)j * N0 * P) + p;
-    // groups of 8 k: a group's 16 table loads are in flight together, the
-    // next group's stay behind it (all 64 at once would not fit next to u)
+    cx<R> u[16];
 #pragma unroll
-    for (int k0 = 0; k0 < 32; k0 += 8) {
+    for (int k = 0; k < 16; ++k) u[k] = cmul(g[k], fh[k]);
+    if (j + 1 < J) load_g(j + 1);           // in flight during this term
 #pragma unroll
-      for (int k = k0; k < k0 + 8; ++k)
-        u[k] = dif2<+1>(cmul(Gj[(int64_t)k * P], fh[k][lp]),
-                        cmul(Gj[(int64_t)(k + 32) * P], fh[k + 32][lp]), h, k);
-      __builtin_amdgcn_sched_barrier(0);
+    for (int i = 0; i < 4; ++i) {
+      cx<R> t[4] = {u[4 * i], u[4 * i + 1], u[4 * i + 2], u[4 * i + 3]};
+      butterfly<4, +1>(t);                  // over a: residue r at t[r]
+      const int b = 4 * w + i;
+      lds[b * 64 + lane] = t[0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) lds[(r * 16 + b) * 64 + lane] = cmul(t[r], root64<+1, R>(b * r));
     }
-    fft_line<32, +1>(u);
-    if (active) {
-      cx<R>* Zj = Z + ((int64_t)cc * J + j) * N0 * P + p;
+    __syncthreads();
+    cx<R> v[16];
 #pragma unroll
-      for (int m = 0; m < 32; ++m) Zj[(int64_t)(2 * m + h) * P] = u[m];
+    for (int b = 0; b < 16; ++b) v[b] = lds[(w * 16 + b) * 64 + lane];
+    fft_line<16, +1>(v);                    // over b: x = 4 c + w at v[c]
+    cx<R>* Zj = Z + ((int64_t)cc * J + j) * N * P + p;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Zj[(int64_t)(4 * c + w) * P] = v[c];
+    __syncthreads();                        // every read of this term is done
+  }
+}
+
+// slab pass at N0 = N = 64: one block per (cell, x) slab Z_j[x][k2][k1].
+// z (from k2, decimation in time: k2 = 4 m + q, z = 16 az + b) and y (from
+// k1, decimation in frequency: k1 = 16 a + by, y = 4 c + r) run as three
+// 16-point register stages with two LDS exchanges per term:
+//   1. thread (q = w, k1 = lane): the 16-point DFT over m, twiddle (q b);
+//   2. thread (b = 4 w + lane / 16, by = lane % 16): the 4 x 4 DFT over (q, a)
+//      -> (az, r), twiddle (by r);
+//   3. thread (r = w, z = lane): the 16-point DFT over by: c_j(4 c + r, z).
+// The FP64 gain of the points (y = 4 c + w, z = lane) stays in registers.
+template <typename R>
+__global__ __launch_bounds__(L64_BS) void k_slab64(const cx<R>* __restrict__ Z, int J,
+                                                   const double* f,
+                                                   const int64_t* __restrict__ off,
+                                                   int64_t cell0, double* Q, double dt) {
+  constexpr int N = 64, P = N * N, LD = 65;   // LD: padded rows of the second exchange
+  __shared__ cx<R> lds[4 * 16 * LD];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cc = blockIdx.x >> 6, x = blockIdx.x & 63;
+  const int b2 = 4 * w + (lane >> 4), by = lane & 15;
+  cx<R> tw2[3];
+#pragma unroll
+  for (int r = 1; r < 4; ++r) tw2[r - 1] = root64<+1, R>(by * r);
+  double acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+  cx<R> nxt[16], v[16];
+  auto load_z = [&](int j) {
+    const cx<R>* Zs = Z + (((int64_t)cc * J + j) * N + x) * P + lane;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) nxt[m] = Zs[(4 * m + w) * N];
+  };
+  load_z(0);
+  for (int j = 0; j < J; ++j) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = nxt[m];
+    if (j + 1 < J) load_z(j + 1);           // in flight during this term
+    fft_line<16, +1>(v);                    // over m: residue q = w, index b
+#pragma unroll
+    for (int b = 1; b < 16; ++b) v[b] = cmul(v[b], root64<+1, R>(w * b));
+    __syncthreads();                        // the previous term's last reads are done
+#pragma unroll
+    for (int b = 0; b < 16; ++b) lds[(w * 16 + b) * 64 + lane] = v[b];
+    __syncthreads();
+    cx<R> u[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) u[q][a] = lds[(q * 16 + b2) * 64 + 16 * a + by];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      cx<R> t[4] = {u[0][a], u[1][a], u[2][a], u[3][a]};
+      butterfly<4, +1>(t);                  // over q: z = 16 az + b2 at t[az]
+#pragma unroll
+      for (int az = 0; az < 4; ++az) u[az][a] = t[az];
     }
+#pragma unroll
+    for (int az = 0; az < 4; ++az) {
+      cx<R> t[4] = {u[az][0], u[az][1], u[az][2], u[az][3]};
+      butterfly<4, +1>(t);                  // over a: residue r at t[r]
+      u[az][0] = t[0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) u[az][r] = cmul(t[r], tw2[r - 1]);
+    }
+    __syncthreads();                        // every read of the first exchange is done
+#pragma unroll
+    for (int az = 0; az < 4; ++az)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) lds[(r * 16 + by) * LD + 16 * az + b2] = u[az][r];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = lds[(w * 16 + k) * LD + lane];
+    fft_line<16, +1>(v);                    // over by: c_j(y = 4 c + w, z = lane) at v[c]
+    if (j + 1 < J) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc[c] += (double)v[c].x * (double)v[c].y;
+    }
+  }
+  const int64_t base = off[cell0 + cc] + (int64_t)x * P;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int64_t i = base + (4 * c + w) * N + lane;
+    const double fv = f[i];
+    const double q = acc[c] - fv * (double)v[c].x;
+    Q[i] = (dt == 0.0) ? q : fv + dt * q;
   }
 }
 
@@ -313,11 +449,9 @@ static hipError_t launch_chunk_t(const ChunkArgs& a, hipStream_t st) {
     if (a.precision == 2) {
       hipError_t e = launch_pencil_bf16(W, G, a.J, a.ncells, Z, N, st);
       if (e != hipSuccess) return e;
-    } else if constexpr (N0 == 64 && sizeof(R) == 8) {
-      const int64_t pencils = (int64_t)a.ncells * N * N;
-      const int pblocks = (int)((pencils + PAIR_PENCILS - 1) / PAIR_PENCILS);
-      hipLaunchKernelGGL((k_pencil_pair64<R, N>), dim3(pblocks), dim3(PENCIL_BS), 0, st,
-                         W, G, a.J, a.ncells, Z);
+    } else if constexpr (N0 == 64) {
+      hipLaunchKernelGGL((k_pencil64<R>), dim3((unsigned)a.ncells * 64), dim3(L64_BS), 0, st, W,
+                         G, a.J, Z);
     } else {
       const int64_t pencils = (int64_t)a.ncells * N * N;
       const int pblocks = (int)((pencils + PENCIL_BS - 1) / PENCIL_BS);
@@ -325,8 +459,13 @@ static hipError_t launch_chunk_t(const ChunkArgs& a, hipStream_t st) {
                          W, G, a.J, a.ncells, Z);
     }
     if (a.ev) (void)hipEventRecord(a.ev[2], st);
-    hipLaunchKernelGGL((k_slab<R, N0, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
-                       Z, G, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
+    if constexpr (N0 == 64) {
+      hipLaunchKernelGGL((k_slab64<R>), dim3((unsigned)a.ncells * 64), dim3(L64_BS), 0, st, Z,
+                         a.J, a.f, a.off, a.cell0, a.Q, a.dt);
+    } else {
+      hipLaunchKernelGGL((k_slab<R, N0, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
+                         Z, G, a.J, a.f, a.off, a.cell0, a.ncells, a.Q, a.dt);
+    }
   } else {
     if (a.ev) (void)hipEventRecord(a.ev[2], st);
     hipLaunchKernelGGL((k_slab<R, 1, N>), dim3(slab_blocks), dim3(SPB * N), 0, st,
