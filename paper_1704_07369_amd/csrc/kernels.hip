@@ -131,15 +131,39 @@ constexpr Tw64Pairs make_tw64() {
 // exp(2 pi i j / 64) as (cos, sin) pairs, for exponents known at run time
 __constant__ Tw64Pairs kTw64 = make_tw64();
 
+// a store that streams past L2 (non-temporal), for outputs read only by a
+// later kernel
+template <typename R>
+__device__ __forceinline__ void store_stream(cx<R>* p, cx<R> v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
 template <int SIGN, typename R>
 __device__ __forceinline__ cx<R> root64(int j) {
   return {(R)kTw64.v[2 * j], (R)(SIGN > 0 ? kTw64.v[2 * j + 1] : -kTw64.v[2 * j + 1])};
 }
 
-// x pass at N0 = N = 64: one block per 64 pencils p (64 blocks per cell; the
-// blocks of one pencil range share an XCD, so its table slice is reused from
-// L2 by the cells in flight).  Thread (w, lane) takes pencil p = 64 (block %
-// 64) + lane.  Forward: it loads x = 4 m + w, m < 16 (decimation in time) and
+// Pencil row k2 of block b of the x pass at N = 64 (64 blocks per cell, one
+// row each).  Blocks b, b + 8, ... run on one XCD; the rows k2 and 64 - k2
+// are placed on the same XCD, so the cells in flight there read one table
+// row for both (gamma is even: gamma(-k) = gamma(k)).  XCD 0 takes rows 0,
+// 32 and the pairs 1..3; XCD x > 0 the pairs 4 (x - 1) + 4 .. 4 (x - 1) + 7.
+__device__ __forceinline__ int pencil_row64(int b) {
+  const int x = b & 7, r = (b >> 3) & 7;
+  if (x == 0) {
+    if (r < 2) return 32 * r;
+    const int m = ((r - 2) >> 1) + 1;
+    return (r & 1) ? 64 - m : m;
+  }
+  const int m = 4 * (x - 1) + 4 + (r >> 1);
+  return (r & 1) ? 64 - m : m;
+}
+
+// x pass at N0 = N = 64: one block per pencil row k2 = pencil_row64(block)
+// of a cell; thread (w, lane) takes pencil p = (k2, k1 = lane).  Rows k2 >
+// 32 read the table of the mirrored pencil (-kx, 64 - k2, -k1), so a term's
+// table is read for 33 rows of 64.  Forward: it loads x = 4 m + w, m < 16 (decimation in time) and
 // keeps Fh(16 a + 4 w + i), a, i < 4, in registers for every term.  Per term:
 // u = gamma_j Fh, the 4-point DFT over a, the twiddle exp(2 pi i b r / 64),
 // LDS, and the 16-point DFT over b of residue r = w: Z_j(x = 4 c + w, p).
@@ -152,7 +176,11 @@ __global__ __launch_bounds__(L64_BS) void k_pencil64(const cx<R>* __restrict__ W
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cc = blockIdx.x >> 6;
-  const int p = ((blockIdx.x & 63) << 6) + lane;
+  const int k2 = pencil_row64(blockIdx.x);
+  const int p = (k2 << 6) + lane;
+  const bool mir = k2 > 32;
+  // the table's pencil: this one, or (64 - k2, -k1) read at -kx
+  const int pg = mir ? ((64 - k2) << 6) + ((64 - lane) & 63) : p;
   cx<R> fh[16];                             // Fh(16 a + 4 w + i) at [4 i + a]
   {
     const cx<R>* Wc = W + (int64_t)cc * N * P + p;
@@ -178,11 +206,14 @@ __global__ __launch_bounds__(L64_BS) void k_pencil64(const cx<R>* __restrict__ W
   }
   cx<R> g[16];
   auto load_g = [&](int j) {
-    const cx<R>* Gj = G + (int64_t)j * N * P + p;
+    const cx<R>* Gj = G + (int64_t)j * N * P + pg;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int a = 0; a < 4; ++a) g[4 * i + a] = Gj[(int64_t)(16 * a + 4 * w + i) * P];
+      for (int a = 0; a < 4; ++a) {
+        const int kx = 16 * a + 4 * w + i;
+        g[4 * i + a] = Gj[(int64_t)(mir ? (64 - kx) & 63 : kx) * P];
+      }
   };
   load_g(0);
   for (int j = 0; j < J; ++j) {
@@ -206,7 +237,7 @@ __global__ __launch_bounds__(L64_BS) void k_pencil64(const cx<R>* __restrict__ W
     fft_line<16, +1>(v);                    // over b: x = 4 c + w at v[c]
     cx<R>* Zj = Z + ((int64_t)cc * J + j) * N * P + p;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) Zj[(int64_t)(4 * c + w) * P] = v[c];
+    for (int c = 0; c < 16; ++c) store_stream(Zj + (int64_t)(4 * c + w) * P, v[c]);
     __syncthreads();                        // every read of this term is done
   }
 }
