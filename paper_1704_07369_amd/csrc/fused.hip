@@ -97,6 +97,26 @@ __device__ __forceinline__ void accum_roots(const cx<R> (&g)[P], const cx<R> (&f
   }
 }
 
+// Raw buffer loads for the gather: the thread's byte offset sits in one
+// register for the whole kernel and each load's constant plane offset in a
+// scalar register, so no per-load address arithmetic reaches the vector ALU
+// (64-bit address forms cost about three vector instructions per load).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+template <typename R>
+__device__ __forceinline__ cx<R> buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  cx<R> o;
+  if constexpr (sizeof(R) == 8) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    __builtin_memcpy(&o, &v, sizeof(o));
+  } else {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    __builtin_memcpy(&o, &v, sizeof(o));
+  }
+  return o;
+}
+
 // one plane pair of G_s: the entry at (a, kk, bq) and its mirror
 template <typename R, int N, int P, int S>
 __device__ __forceinline__ void gather_store(const cx<R> (&g)[P], const cx<R> (&fv)[P], int kk,
@@ -117,10 +137,14 @@ __device__ __forceinline__ void gather_term(const cx<R>* __restrict__ Gt,
                                             const cx<R> (&fh)[C > 0 ? C : 1][P], int a, int bq,
                                             int am, int bm, cx<R> tw, cx<R>* vol) {
   constexpr int NP = N / P, LD = N + 1;
+  constexpr unsigned E = sizeof(cx<R>), n = N * N * N;
   // planes per group: a group's loads are in flight together
   constexpr int GP = 4;
   static_assert((N / 2) % GP == 0 && C % GP == 0, "half-space planes come in whole groups");
   const cx<R> twc = {tw.x, -tw.y};
+  // table entry ((a + NP j) N + k2) N + bq, spectrum ((a + NP j) N/2 + k2) N + bq
+  const __amdgpu_buffer_rsrc_t gt = buf_rsrc(Gt, n * E), fr = buf_rsrc(Fc, n / 2 * E);
+  const unsigned gvo = (unsigned)(a * N * N + bq) * E, fvo = (unsigned)(a * (N / 2) * N + bq) * E;
   // planes k2 < C: Fh from registers (compile-time indices), table from L2
 #pragma unroll
   for (int k2 = 0; k2 < C; k2 += GP) {
@@ -128,7 +152,8 @@ __device__ __forceinline__ void gather_term(const cx<R>* __restrict__ Gt,
 #pragma unroll
     for (int u = 0; u < GP; ++u) {
 #pragma unroll
-      for (int j = 0; j < P; ++j) gl[u][j] = Gt[((a + NP * j) * N + k2 + u) * N + bq];
+      for (int j = 0; j < P; ++j)
+        gl[u][j] = buf_load<R>(gt, gvo, (unsigned)((NP * j * N + k2 + u) * N) * E);
     }
 #pragma unroll
     for (int u = 0; u < GP; ++u)
@@ -143,8 +168,8 @@ __device__ __forceinline__ void gather_term(const cx<R>* __restrict__ Gt,
     for (int u = 0; u < GP; ++u) {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        gl[u][j] = Gt[((a + NP * j) * N + k2 + u) * N + bq];
-        fl[u][j] = Fc[((a + NP * j) * (N / 2) + k2 + u) * N + bq];   // half-space layout
+        gl[u][j] = buf_load<R>(gt, gvo, (unsigned)((NP * j * N + k2 + u) * N) * E);
+        fl[u][j] = buf_load<R>(fr, fvo, (unsigned)((NP * j * (N / 2) + k2 + u) * N) * E);
       }
     }
 #pragma unroll
@@ -336,17 +361,21 @@ constexpr int fh_regs() { return sizeof(R) == 4 && P == 2 ? N / 2 : 0; }
 // flight at a time: issuing the next group's loads before combining this one
 // measured 3.5 % slower in FP64 and no faster in FP32 -- the gather is bound
 // by the bytes delivered into the CU, not by the round trip.
+// one group of GP planes: table entries (a + NP j, k2 + u, bq) of the term
+// (resource gt, thread offset gvo = col * sizeof(cx)) and spectrum entries of
+// the half-space layout (resource fr, offset fvo = fcol * sizeof(cx))
 template <typename R, int N, int P, int GP>
-__device__ __forceinline__ void gather_load(const cx<R>* __restrict__ Gt,
-                                            const cx<R>* __restrict__ Fc, int col, int fcol,
-                                            int k2, cx<R> (&gl)[GP][P], cx<R> (&fl)[GP][P]) {
+__device__ __forceinline__ void gather_load(__amdgpu_buffer_rsrc_t gt, __amdgpu_buffer_rsrc_t fr,
+                                            unsigned gvo, unsigned fvo, int k2,
+                                            cx<R> (&gl)[GP][P], cx<R> (&fl)[GP][P]) {
   constexpr int NP = N / P;
+  constexpr unsigned E = sizeof(cx<R>);
 #pragma unroll
   for (int u = 0; u < GP; ++u) {
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      gl[u][j] = Gt[col + (NP * j * N + k2 + u) * N];
-      fl[u][j] = Fc[fcol + (NP * j * (N / 2) + k2 + u) * N];
+      gl[u][j] = buf_load<R>(gt, gvo, (unsigned)((NP * j * N + k2 + u) * N) * E);
+      fl[u][j] = buf_load<R>(fr, fvo, (unsigned)((NP * j * (N / 2) + k2 + u) * N) * E);
     }
   }
 }
@@ -360,7 +389,10 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
   constexpr int GP = 2;                 // planes per group of loads (4 spill in FP64)
   constexpr int NG = N / 2 / GP;
   constexpr bool FH = fh_regs<R, N, P>() > 0;
+  constexpr unsigned E = sizeof(cx<R>), n = N * N * N;
   const cx<R> twc = {tw.x, -tw.y};
+  const __amdgpu_buffer_rsrc_t gt = buf_rsrc(Gt, n * E), fr = buf_rsrc(Fc, n / 2 * E);
+  const unsigned gvo = (unsigned)col * E, fvo = (unsigned)fcol * E;
   cx<R> gl[GP][P], fl[GP][P];
 #pragma unroll
   for (int g = 0; g < NG; ++g) {
@@ -368,9 +400,10 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
 #pragma unroll
       for (int u = 0; u < GP; ++u)
 #pragma unroll
-        for (int j = 0; j < P; ++j) gl[u][j] = Gt[col + ((N / P) * j * N + g * GP + u) * N];
+        for (int j = 0; j < P; ++j)
+          gl[u][j] = buf_load<R>(gt, gvo, (unsigned)(((N / P) * j * N + g * GP + u) * N) * E);
     } else {
-      gather_load<R, N, P, GP>(Gt, Fc, col, fcol, g * GP, gl, fl);
+      gather_load<R, N, P, GP>(gt, fr, gvo, fvo, g * GP, gl, fl);
     }
     __builtin_amdgcn_sched_barrier(0);  // this group's loads go out before its math
 #pragma unroll
@@ -421,14 +454,12 @@ __device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt
                                              double (&acc)[P][N / P]) {
   constexpr int NP = N / P, T = NP * N, LD = col_ld<N>();
   const int th = threadIdx.x;
-  // offset by an opaque zero, the per-element addresses are formed here
-  // instead of being hoisted out of the term loop (64 of them would stay live
-  // across every term)
+  // offset by an opaque zero, the addresses of F are formed here instead of
+  // being hoisted out of the term loop
   const int z0 = opaque_zero();
   const double* fp = fc + z0;
   cx<R> v[N];
-  gather_col_s<R, N, P>(s, Gt, Fc, a * N * N + bq + z0, a * N * N / 2 + bq + z0, partner4, tw,
-                        fh, v);
+  gather_col_s<R, N, P>(s, Gt, Fc, a * N * N + bq, a * N * N / 2 + bq, partner4, tw, fh, v);
   fft_line<N, +1>(v);                   // along z: (k', k1 = bq, z)
   R* pl = buf + a * N * LD;             // this half-wave's plane
   __syncthreads();                      // every wave is done reading the previous term
