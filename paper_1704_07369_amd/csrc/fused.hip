@@ -380,7 +380,7 @@ __device__ __forceinline__ void gather_load(__amdgpu_buffer_rsrc_t gt, __amdgpu_
   }
 }
 
-template <typename R, int N, int P, int S>
+template <typename R, int N, int P, int S, int DEPTH>
 __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
                                            const cx<R>* __restrict__ Fc, int col, int fcol,
                                            int partner4, cx<R> tw,
@@ -393,25 +393,33 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
   const cx<R> twc = {tw.x, -tw.y};
   const __amdgpu_buffer_rsrc_t gt = buf_rsrc(Gt, n * E), fr = buf_rsrc(Fc, n / 2 * E);
   const unsigned gvo = (unsigned)col * E, fvo = (unsigned)fcol * E;
-  cx<R> gl[GP][P], fl[GP][P];
-#pragma unroll
-  for (int g = 0; g < NG; ++g) {
+  // DEPTH groups of loads in flight (ring of DEPTH buffers)
+  cx<R> gl[DEPTH][GP][P], fl[DEPTH][GP][P];
+  auto load = [&](int g) {
+    const int b = g % DEPTH;
     if constexpr (FH) {
 #pragma unroll
       for (int u = 0; u < GP; ++u)
 #pragma unroll
         for (int j = 0; j < P; ++j)
-          gl[u][j] = buf_load<R>(gt, gvo, (unsigned)(((N / P) * j * N + g * GP + u) * N) * E);
+          gl[b][u][j] = buf_load<R>(gt, gvo, (unsigned)(((N / P) * j * N + g * GP + u) * N) * E);
     } else {
-      gather_load<R, N, P, GP>(gt, fr, gvo, fvo, g * GP, gl, fl);
+      gather_load<R, N, P, GP>(gt, fr, gvo, fvo, g * GP, gl[b], fl[b]);
     }
+  };
+#pragma unroll
+  for (int g = 0; g < DEPTH - 1; ++g) load(g);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    if (g + DEPTH - 1 < NG) load(g + DEPTH - 1);
     __builtin_amdgcn_sched_barrier(0);  // this group's loads go out before its math
+    const int b = g % DEPTH;
 #pragma unroll
     for (int u = 0; u < GP; ++u) {
       const int kk = g * GP + u;
       cx<R> SA = {(R)0, (R)0}, SB = {(R)0, (R)0};
-      if constexpr (FH) accum_roots<P, S>(gl[u], fh[kk], SA, SB);
-      else accum_roots<P, S>(gl[u], fl[u], SA, SB);
+      if constexpr (FH) accum_roots<P, S>(gl[b][u], fh[kk], SA, SB);
+      else accum_roots<P, S>(gl[b][u], fl[b][u], SA, SB);
       const cx<R> zp = {SA.x - SB.y, SA.y + SB.x}, zm = {SA.x + SB.y, SB.x - SA.y};
       // s = 0: the twiddle is exp(0) = 1
       v[kk] = S == 0 ? zp : cmul(tw, zp);
@@ -422,15 +430,15 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
   v[N / 2] = {(R)0, (R)0};
 }
 
-template <typename R, int N, int P, int S = 0>
+template <typename R, int N, int P, int DEPTH, int S = 0>
 __device__ __forceinline__ void gather_col_s(int s, const cx<R>* __restrict__ Gt,
                                              const cx<R>* __restrict__ Fc, int col, int fcol,
                                              int partner4, cx<R> tw,
                                              const cx<R> (&fh)[fh_regs<R, N, P>() ? N / 2 : 1][P],
                                              cx<R> (&v)[N]) {
-  if (s == S) gather_col<R, N, P, S>(Gt, Fc, col, fcol, partner4, tw, fh, v);
+  if (s == S) gather_col<R, N, P, S, DEPTH>(Gt, Fc, col, fcol, partner4, tw, fh, v);
   else if constexpr (S + 1 < P)
-    gather_col_s<R, N, P, S + 1>(s, Gt, Fc, col, fcol, partner4, tw, fh, v);
+    gather_col_s<R, N, P, DEPTH, S + 1>(s, Gt, Fc, col, fcol, partner4, tw, fh, v);
 }
 
 // The thread's spectrum inputs of the planes kept in registers (fh_regs)
@@ -445,7 +453,7 @@ __device__ __forceinline__ void load_fh(const cx<R>* __restrict__ Fc, int fcol,
   }
 }
 
-template <typename R, int N, int P, bool LOSS>
+template <typename R, int N, int P, bool LOSS, int DEPTH = 1>
 __device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt,
                                              const cx<R>* __restrict__ Fc, int a, int bq,
                                              int partner4, cx<R> tw,
@@ -459,7 +467,8 @@ __device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt
   const int z0 = opaque_zero();
   const double* fp = fc + z0;
   cx<R> v[N];
-  gather_col_s<R, N, P>(s, Gt, Fc, a * N * N + bq, a * N * N / 2 + bq, partner4, tw, fh, v);
+  gather_col_s<R, N, P, DEPTH>(s, Gt, Fc, a * N * N + bq, a * N * N / 2 + bq, partner4, tw, fh,
+                               v);
   fft_line<N, +1>(v);                   // along z: (k', k1 = bq, z)
   R* pl = buf + a * N * LD;             // this half-wave's plane
   __syncthreads();                      // every wave is done reading the previous term
@@ -564,6 +573,13 @@ void k_fused_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
   }
 }
 
+// Load groups of the gather in flight in the term-parallel kernel: with one
+// workgroup per (cell, term, residue class) the load latency is exposed (one
+// wave per SIMD), so the next group is issued before the current one is
+// combined.  The fused kernel keeps one group: there two waves per SIMD and
+// the gather's bandwidth bound leave nothing to hide.
+constexpr int TERMS_DEPTH = 2;
+
 // Term-parallel form of the column kernel for small batches: one workgroup
 // per (cell, term, x residue s) runs that single term (the same run_term_col)
 // and writes its products, or for the loss term -F l, to part[cell][term][n];
@@ -595,15 +611,15 @@ void k_terms_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
   cx<R> fh[fh_regs<R, N, P>() ? N / 2 : 1][P];
   load_fh<R, N, P>(Fc, a * N * N / 2 + bq, fh);
   if (term == J - 1) {
-    run_term_col<R, N, P, true>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4, tw, fh, buf,
-                                fc, acc);
+    run_term_col<R, N, P, true, TERMS_DEPTH>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4,
+                                             tw, fh, buf, fc, acc);
   } else {
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
       for (int q = 0; q < NP; ++q) acc[p][q] = 0.0;
-    run_term_col<R, N, P, false>(s, G + (int64_t)term * n, Fc, a, bq, partner4, tw, fh, buf, fc,
-                                 acc);
+    run_term_col<R, N, P, false, TERMS_DEPTH>(s, G + (int64_t)term * n, Fc, a, bq, partner4,
+                                              tw, fh, buf, fc, acc);
   }
   double* pc = part + ((int64_t)cc * J + term) * n;
 #pragma unroll
