@@ -652,6 +652,52 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
   }
 }
 
+// The per-step monitors of a captured step graph alone: mass h^d sum F and
+// the H-functional h^d sum_{F > 0} F ln F of every cell (the same quantities
+// as k_monitors' step_mon output, without the other ten sums and their
+// barrier-per-level reduction; wave sums by lane exchange, then one LDS
+// round over the four waves).
+__global__ __launch_bounds__(MON_BS) void k_step_monitors(
+    const double* __restrict__ f, const int64_t* __restrict__ off, const int* __restrict__ cell_n,
+    const double* __restrict__ cell_hd, int64_t cell0, const int* step, double* step_mon,
+    int64_t step_stride, const int* step_cap) {
+  constexpr int NW = MON_BS / 64;
+  __shared__ double red[2][NW];
+  const int64_t c = cell0 + blockIdx.x;
+  const double* fc = f + off[c];
+  const int n = cell_n[c];
+  double m = 0.0, e = 0.0;
+#pragma unroll 4
+  for (int r = threadIdx.x; r < n; r += MON_BS) {
+    const double fv = fc[r];
+    m += fv;
+    if (fv > 0.0) e += fv * log(fv);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m += __shfl_xor(m, o);
+    e += __shfl_xor(e, o);
+  }
+  const int w = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = m;
+    red[1][w] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && *step >= 0 && *step < step_cap[0]) {
+    double mm = 0.0, ee = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      mm += red[0][k];
+      ee += red[1][k];
+    }
+    const double hd = cell_hd[c];
+    double* o = step_mon + ((int64_t)(*step) * step_stride + blockIdx.x) * 2;
+    o[0] = hd * mm;
+    o[1] = hd * ee;
+  }
+}
+
 hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
                            const int* cell_n, const double* cell_hd, const int* cell_geo,
                            const double* cell_L, int64_t cell0, int64_t ncells, double* full,
@@ -659,6 +705,11 @@ hipError_t launch_monitors(const double* f, const double* Q, const int64_t* off,
                            double* step_mon, int64_t step_stride, const int* step_cap,
                            hipStream_t s) {
   if (ncells <= 0) return hipSuccess;
+  if (!Q && !full && !entprod && !n_nonpos && step_mon) {
+    hipLaunchKernelGGL(k_step_monitors, dim3((unsigned)ncells), dim3(MON_BS), 0, s, f, off,
+                       cell_n, cell_hd, cell0, step, step_mon, step_stride, step_cap);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_monitors, dim3((unsigned)ncells), dim3(MON_BS), 0, s, f, Q, off,
                      cell_n, cell_hd, cell_geo, cell_L, cell0, full, entprod, n_nonpos, step,
                      step_mon, step_stride, step_cap);
