@@ -160,3 +160,30 @@ def test_sweep_plan_full_grid_sparse_spectrum():
             tol = bounds.bound(prec, N, 3, np.linalg.norm(qm) / np.linalg.norm(qp))
             say(f"  precision {prec} cell {c}: rel err {err:.3e} (bound {tol:.3e})")
             assert err <= tol
+
+
+def test_64_two_pass_euler_step_in_place():
+    """The 64^3 slab pass's in-place forward-Euler update (F + dt Q written
+    over F by the pass that computes Q) over a full pass of 23 cells and a
+    tail pass of 2, FP64 and FP32: equal to F + dt Q from a separate collide
+    of the same cells up to the rounding of the final update."""
+    import torch
+    say("case 64^3 two-pass Euler step in place, 25 cells in passes of 23")
+    p = E.Plan(64, 3, L, 2, kind=E.EC_KERNEL_VHS, R=R, gamma=0.5, n_radial=2)
+    cells = [synth.sample_mixture(synth.mixture_two_gaussians(9700 + i, 3), 64, L)
+             for i in range(25)]
+    dt = 0.01
+    for prec in (0, 1):
+        b = E.Batch([p], [len(cells)], prec)
+        b.set_schedule(0, E.EC_SCHED_TWO_PASS, 23, 0)
+        assert tuple(b.get_schedule(0))[:2] == (E.EC_SCHED_TWO_PASS, 23)
+        f = to_dev(E.pack(b, cells))
+        Q = torch.zeros_like(f)
+        b.collide(f, Q)
+        want = f + dt * Q
+        b.step(f, dt, 1)
+        torch.cuda.synchronize()
+        err = ((f - want).abs().max() / want.abs().max()).item()
+        say(f"  precision {prec}: max |step - (F + dt Q)| / max F = {err:.3e}")
+        assert err <= 1e-14
+        b.close()
