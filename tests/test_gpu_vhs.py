@@ -187,3 +187,38 @@ def test_64_two_pass_euler_step_in_place():
         say(f"  precision {prec}: max |step - (F + dt Q)| / max F = {err:.3e}")
         assert err <= 1e-14
         b.close()
+
+
+def test_64_degenerate_cells():
+    """Degenerate cells through the 64^3 passes (VHS gamma = 0.5, M' = 4, FP64
+    and FP32): F = 0 gives Q = 0 exactly; a single-point spike stays finite;
+    a mixture with a zeroed block matches the oracle on sampled points, half of
+    them inside the block, where Q = Q+ >= 0 (the loss F l vanishes there;
+    Theorem 1)."""
+    say("case 64^3 degenerate cells")
+    N = 64
+    p, op = plans(N, 2, 0.5, 2)
+    zero = np.zeros((N, N, N))
+    spike = np.zeros((N, N, N))
+    spike[N // 2, N // 2 + 3, N // 2 - 5] = 1.0
+    holey = synth.sample_mixture(synth.mixture_two_gaussians(9800, 3), N, L)
+    holey[24:36, 28:40, 20:44] = 0.0
+    rng = np.random.default_rng(98)
+    hole = np.ravel_multi_index(np.nonzero(holey == 0.0), holey.shape)
+    idx = np.unique(np.concatenate([rng.choice(hole, 16, replace=False),
+                                    np.argsort(holey.ravel())[-8:],
+                                    rng.choice(N ** 3, 8, replace=False)]))
+    q, qp, qm, _ = efm.collide_points(op, holey, idx)
+    inside = holey.ravel()[idx] == 0.0
+    assert inside.sum() >= 16 and np.abs(qm[inside]).max() == 0.0
+    for prec in (0, 1):
+        out = run(p, [zero, holey, spike], prec)
+        assert np.all(out[0] == 0.0)
+        assert np.all(np.isfinite(out[2]))
+        err = np.abs(out[1].ravel()[idx] - q).max() / np.abs(qp).max()
+        tol = bounds.bound(prec, N, 3, np.abs(qm).max() / np.abs(qp).max())
+        low = out[1].ravel()[idx][inside].min() / np.abs(qp).max()
+        say(f"  precision {prec}: max rel err {err:.3e} (bound {tol:.3e}), min Q in the hole "
+            f"{low:.3e} of max Q+")
+        assert err <= tol
+        assert low >= -tol
