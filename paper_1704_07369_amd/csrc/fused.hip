@@ -25,6 +25,11 @@
 
 #include "fft.h"
 
+// gather load groups the FP32 column kernel prefetches (col_prefetch)
+#ifndef EFM_COL_PREFETCH
+#define EFM_COL_PREFETCH 5
+#endif
+
 namespace efm {
 
 // exp(2 pi i m / N) for a runtime m in [0, N): a select over the exact table
@@ -345,6 +350,16 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Gather load groups of the next term issued during a term's x pass (see
+// prefetch_table): FP32 at split 2 only, where the spectrum lives in
+// registers and 36 registers are left (5 of the 8 groups: 254 registers, no
+// spill; 6 spill).  1024 cells of 32^3, FP32 launch of 512 cells: 1.039 ms
+// with none, 0.998 / 0.973 / 0.955 ms with 2 / 3 / 4 groups, 5 another 1.8 %
+// faster than 4.  None where the column and the FP64 accumulators fill the
+// register file.
+template <typename R, int N, int P>
+constexpr int col_prefetch();
+
 // Planes of the thread's spectrum inputs that the column kernel keeps in
 // registers for every term: all N/2 of them in FP32 at split 2 (64 more
 // registers, 219 in all; the gather then reads only the term table: 1024
@@ -352,6 +367,9 @@ __device__ __forceinline__ void wave_sync() {
 // to the FP64 column).
 template <typename R, int N, int P>
 constexpr int fh_regs() { return sizeof(R) == 4 && P == 2 ? N / 2 : 0; }
+
+template <typename R, int N, int P>
+constexpr int col_prefetch() { return fh_regs<R, N, P>() > 0 ? EFM_COL_PREFETCH : 0; }
 
 // Gather of one term into the thread's z column v[k2] (plane a, column bq;
 // col = a N^2 + bq indexes its first table entry, fcol = a N^2 / 2 + bq its
@@ -380,15 +398,42 @@ __device__ __forceinline__ void gather_load(__amdgpu_buffer_rsrc_t gt, __amdgpu_
   }
 }
 
-template <typename R, int N, int P, int S, int DEPTH>
+// planes per group of gather loads in the column kernels (4 spill in FP64)
+constexpr int COL_GP = 2;
+
+// Table loads of the first KP groups of a term's gather (spectrum held in
+// registers, fh_regs > 0), issued before the term starts: the column kernel
+// sends them out for the next term while it runs this term's x pass, when the
+// column registers are free and the load path idle.
+template <typename R, int N, int P, int KP>
+__device__ __forceinline__ void prefetch_table(const cx<R>* __restrict__ Gt, int col,
+                                               cx<R> (&pre)[KP > 0 ? KP : 1][COL_GP][P]) {
+  if constexpr (KP > 0) {
+    constexpr unsigned E = sizeof(cx<R>), n = N * N * N;
+    const __amdgpu_buffer_rsrc_t gt = buf_rsrc(Gt, n * E);
+    const unsigned gvo = (unsigned)col * E;
+#pragma unroll
+    for (int g = 0; g < KP; ++g)
+#pragma unroll
+      for (int u = 0; u < COL_GP; ++u)
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+          pre[g][u][j] =
+              buf_load<R>(gt, gvo, (unsigned)(((N / P) * j * N + g * COL_GP + u) * N) * E);
+  }
+}
+
+template <typename R, int N, int P, int S, int DEPTH, int KP>
 __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
                                            const cx<R>* __restrict__ Fc, int col, int fcol,
                                            int partner4, cx<R> tw,
                                            const cx<R> (&fh)[fh_regs<R, N, P>() ? N / 2 : 1][P],
+                                           const cx<R> (&pre)[KP > 0 ? KP : 1][COL_GP][P],
                                            cx<R> (&v)[N]) {
-  constexpr int GP = 2;                 // planes per group of loads (4 spill in FP64)
+  constexpr int GP = COL_GP;
   constexpr int NG = N / 2 / GP;
   constexpr bool FH = fh_regs<R, N, P>() > 0;
+  static_assert(KP == 0 || (FH && DEPTH == 1 && KP < NG), "prefetch: table-only gathers");
   constexpr unsigned E = sizeof(cx<R>), n = N * N * N;
   const cx<R> twc = {tw.x, -tw.y};
   const __amdgpu_buffer_rsrc_t gt = buf_rsrc(Gt, n * E), fr = buf_rsrc(Fc, n / 2 * E);
@@ -397,7 +442,12 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
   cx<R> gl[DEPTH][GP][P], fl[DEPTH][GP][P];
   auto load = [&](int g) {
     const int b = g % DEPTH;
-    if constexpr (FH) {
+    if (g < KP) {
+#pragma unroll
+      for (int u = 0; u < GP; ++u)
+#pragma unroll
+        for (int j = 0; j < P; ++j) gl[b][u][j] = pre[g < KP ? g : 0][u][j];
+    } else if constexpr (FH) {
 #pragma unroll
       for (int u = 0; u < GP; ++u)
 #pragma unroll
@@ -430,15 +480,16 @@ __device__ __forceinline__ void gather_col(const cx<R>* __restrict__ Gt,
   v[N / 2] = {(R)0, (R)0};
 }
 
-template <typename R, int N, int P, int DEPTH, int S = 0>
+template <typename R, int N, int P, int DEPTH, int KP, int S = 0>
 __device__ __forceinline__ void gather_col_s(int s, const cx<R>* __restrict__ Gt,
                                              const cx<R>* __restrict__ Fc, int col, int fcol,
                                              int partner4, cx<R> tw,
                                              const cx<R> (&fh)[fh_regs<R, N, P>() ? N / 2 : 1][P],
+                                             const cx<R> (&pre)[KP > 0 ? KP : 1][COL_GP][P],
                                              cx<R> (&v)[N]) {
-  if (s == S) gather_col<R, N, P, S, DEPTH>(Gt, Fc, col, fcol, partner4, tw, fh, v);
+  if (s == S) gather_col<R, N, P, S, DEPTH, KP>(Gt, Fc, col, fcol, partner4, tw, fh, pre, v);
   else if constexpr (S + 1 < P)
-    gather_col_s<R, N, P, DEPTH, S + 1>(s, Gt, Fc, col, fcol, partner4, tw, fh, v);
+    gather_col_s<R, N, P, DEPTH, KP, S + 1>(s, Gt, Fc, col, fcol, partner4, tw, fh, pre, v);
 }
 
 // The thread's spectrum inputs of the planes kept in registers (fh_regs)
@@ -453,13 +504,15 @@ __device__ __forceinline__ void load_fh(const cx<R>* __restrict__ Fc, int fcol,
   }
 }
 
-template <typename R, int N, int P, bool LOSS, int DEPTH = 1>
+template <typename R, int N, int P, bool LOSS, int DEPTH = 1, int KP = 0>
 __device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt,
                                              const cx<R>* __restrict__ Fc, int a, int bq,
                                              int partner4, cx<R> tw,
                                              const cx<R> (&fh)[fh_regs<R, N, P>() ? N / 2 : 1][P],
                                              R* buf, const double* __restrict__ fc,
-                                             double (&acc)[P][N / P]) {
+                                             double (&acc)[P][N / P],
+                                             cx<R> (&pre)[KP > 0 ? KP : 1][COL_GP][P],
+                                             const cx<R>* __restrict__ Gnext) {
   constexpr int NP = N / P, T = NP * N, LD = col_ld<N>();
   const int th = threadIdx.x;
   // offset by an opaque zero, the addresses of F are formed here instead of
@@ -467,8 +520,8 @@ __device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt
   const int z0 = opaque_zero();
   const double* fp = fc + z0;
   cx<R> v[N];
-  gather_col_s<R, N, P, DEPTH>(s, Gt, Fc, a * N * N + bq, a * N * N / 2 + bq, partner4, tw, fh,
-                               v);
+  gather_col_s<R, N, P, DEPTH, KP>(s, Gt, Fc, a * N * N + bq, a * N * N / 2 + bq, partner4, tw,
+                                   fh, pre, v);
   fft_line<N, +1>(v);                   // along z: (k', k1 = bq, z)
   R* pl = buf + a * N * LD;             // this half-wave's plane
   __syncthreads();                      // every wave is done reading the previous term
@@ -490,6 +543,11 @@ __device__ __forceinline__ void run_term_col(int s, const cx<R>* __restrict__ Gt
   // y -> x exchange across waves
 #pragma unroll
   for (int y = 0; y < N; ++y) pl[y * LD + bq] = v[y].x;
+  // unconditional (the caller passes a valid table after the last term too):
+  // a branch here would split the block and change which products the
+  // compiler contracts into FMAs, and FP32 results would no longer equal the
+  // term-parallel kernel's bit for bit
+  prefetch_table<R, N, P, KP>(Gnext, a * N * N + bq, pre);
   __syncthreads();
   cx<R> u[P][NP];
 #pragma unroll
@@ -550,11 +608,17 @@ void k_fused_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
   double acc[P][NP];
   cx<R> fh[fh_regs<R, N, P>() ? N / 2 : 1][P];
   load_fh<R, N, P>(Fc, a * N * N / 2 + bq, fh);
-  run_term_col<R, N, P, true>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4, tw, fh, buf, fc,
-                              acc);
+  constexpr int KP = col_prefetch<R, N, P>();
+  cx<R> pre[KP > 0 ? KP : 1][COL_GP][P];
+  prefetch_table<R, N, P, KP>(G + (int64_t)(J - 1) * n, a * N * N + bq, pre);
+  // the next term's table (after the last term: the first table again, a
+  // valid address whose loads are not used)
+  run_term_col<R, N, P, true, 1, KP>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4, tw, fh,
+                                     buf, fc, acc, pre, G);
   for (int term = 0; term < J - 1; ++term)
-    run_term_col<R, N, P, false>(s, G + (int64_t)term * n, Fc, a, bq, partner4, tw, fh, buf,
-                                 fc, acc);
+    run_term_col<R, N, P, false, 1, KP>(s, G + (int64_t)term * n, Fc, a, bq, partner4, tw, fh,
+                                        buf, fc, acc, pre,
+                                        G + (int64_t)(term + 1 < J - 1 ? term + 1 : 0) * n);
   // fresh copies again, so that the output addresses are not shared with
   // (and kept live from) the loss term's reads of F
   const int z0 = opaque_zero();
@@ -610,16 +674,17 @@ void k_terms_col(const cx<R>* __restrict__ Fh, const cx<R>* __restrict__ G, int 
   double acc[P][NP];
   cx<R> fh[fh_regs<R, N, P>() ? N / 2 : 1][P];
   load_fh<R, N, P>(Fc, a * N * N / 2 + bq, fh);
+  cx<R> pre[1][COL_GP][P];                // no prefetch: one term per workgroup
   if (term == J - 1) {
     run_term_col<R, N, P, true, TERMS_DEPTH>(s, G + (int64_t)(J - 1) * n, Fc, a, bq, partner4,
-                                             tw, fh, buf, fc, acc);
+                                             tw, fh, buf, fc, acc, pre, nullptr);
   } else {
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
       for (int q = 0; q < NP; ++q) acc[p][q] = 0.0;
     run_term_col<R, N, P, false, TERMS_DEPTH>(s, G + (int64_t)term * n, Fc, a, bq, partner4,
-                                              tw, fh, buf, fc, acc);
+                                              tw, fh, buf, fc, acc, pre, nullptr);
   }
   double* pc = part + ((int64_t)cc * J + term) * n;
 #pragma unroll
