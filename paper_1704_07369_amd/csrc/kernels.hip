@@ -163,10 +163,11 @@ __device__ __forceinline__ int pencil_row64(int b) {
 // x pass at N0 = N = 64: one block per pencil row k2 = pencil_row64(block)
 // of a cell; thread (w, lane) takes pencil p = (k2, k1 = lane).  Rows k2 >
 // 32 read the table of the mirrored pencil (-kx, 64 - k2, -k1), so a term's
-// table is read for 33 rows of 64.  Forward: it loads x = 4 m + w, m < 16 (decimation in time) and
-// keeps Fh(16 a + 4 w + i), a, i < 4, in registers for every term.  Per term:
-// u = gamma_j Fh, the 4-point DFT over a, the twiddle exp(2 pi i b r / 64),
-// LDS, and the 16-point DFT over b of residue r = w: Z_j(x = 4 c + w, p).
+// table is read for 33 rows of 64.  Forward: the thread loads x = 4 m + w,
+// m < 16 (decimation in time), and keeps Fh(16 a + 4 w + i), a, i < 4, in
+// registers for every term.  Per term: u = gamma_j Fh, the 4-point DFT over
+// a, the twiddle exp(2 pi i b r / 64), LDS, and the 16-point DFT over b of
+// residue r = w: Z_j(x = 4 c + w, p), written with streaming stores.
 template <typename R>
 __global__ __launch_bounds__(L64_BS) void k_pencil64(const cx<R>* __restrict__ W,
                                                      const cx<R>* __restrict__ G, int J,
