@@ -161,30 +161,38 @@ __device__ __forceinline__ int pencil_row64(int b) {
 }
 
 // x pass at N0 = N = 64: one block per pencil row k2 = pencil_row64(block)
-// of a cell; thread (w, lane) takes pencil p = (k2, k1 = lane).  Rows k2 >
-// 32 read the table of the mirrored pencil (-kx, 64 - k2, -k1), so a term's
-// table is read for 33 rows of 64.  Forward: the thread loads x = 4 m + w,
-// m < 16 (decimation in time), and keeps Fh(16 a + 4 w + i), a, i < 4, in
-// registers for every term.  Per term: u = gamma_j Fh, the 4-point DFT over
-// a, the twiddle exp(2 pi i b r / 64), LDS, and the 16-point DFT over b of
-// residue r = w: Z_j(x = 4 c + w, p), written with streaming stores.
+// of C consecutive cells (C = 2 in FP32: one table load per term serves both;
+// the last block of an odd count holds one); thread (w, lane) takes pencil p
+// = (k2, k1 = lane).  Rows k2 > 32 read the table of the mirrored pencil
+// (-kx, 64 - k2, -k1), so a term's table is read for 33 rows of 64.
+// Forward: the thread loads x = 4 m + w, m < 16 (decimation in time), and
+// keeps Fh(16 a + 4 w + i), a, i < 4, of each cell in registers for every
+// term.  Per term: u = gamma_j Fh, the 4-point DFT over a, the twiddle
+// exp(2 pi i b r / 64), LDS, and the 16-point DFT over b of residue r = w:
+// Z_j(x = 4 c + w, p), written with streaming stores.
 template <typename R>
+constexpr int pencil64_cells() { return sizeof(R) == 4 ? 2 : 1; }
+
+template <typename R, int C>
 __global__ __launch_bounds__(L64_BS) void k_pencil64(const cx<R>* __restrict__ W,
                                                      const cx<R>* __restrict__ G, int J,
-                                                     cx<R>* __restrict__ Z) {
+                                                     int ncells, cx<R>* __restrict__ Z) {
   constexpr int N = 64, P = N * N;
-  __shared__ cx<R> lds[4 * 16 * 64];
+  __shared__ cx<R> lds[C][4 * 16 * 64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int cc = blockIdx.x >> 6;
+  const int c0 = (blockIdx.x >> 6) * C;
+  const int nc = C == 1 ? 1 : min(C, ncells - c0);   // cells of this block (1 .. C)
   const int k2 = pencil_row64(blockIdx.x);
   const int p = (k2 << 6) + lane;
   const bool mir = k2 > 32;
   // the table's pencil: this one, or (64 - k2, -k1) read at -kx
   const int pg = mir ? ((64 - k2) << 6) + ((64 - lane) & 63) : p;
-  cx<R> fh[16];                             // Fh(16 a + 4 w + i) at [4 i + a]
-  {
-    const cx<R>* Wc = W + (int64_t)cc * N * P + p;
+  cx<R> fh[C][16];                          // Fh(16 a + 4 w + i) at [c][4 i + a]
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    // a missing cell of the last block repeats the block's first (not stored)
+    const cx<R>* Wc = W + (int64_t)(c0 + (C == 1 || c < nc ? c : 0)) * N * P + p;
     cx<R> v[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = Wc[(int64_t)(4 * m + w) * P];
@@ -192,19 +200,22 @@ __global__ __launch_bounds__(L64_BS) void k_pencil64(const cx<R>* __restrict__ W
 #pragma unroll
     for (int b = 1; b < 16; ++b) v[b] = cmul(v[b], root64<-1, R>(w * b));
 #pragma unroll
-    for (int b = 0; b < 16; ++b) lds[(w * 16 + b) * 64 + lane] = v[b];
-    __syncthreads();
+    for (int b = 0; b < 16; ++b) lds[c][(w * 16 + b) * 64 + lane] = v[b];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       cx<R> t[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) t[q] = lds[(q * 16 + 4 * w + i) * 64 + lane];
+      for (int q = 0; q < 4; ++q) t[q] = lds[c][(q * 16 + 4 * w + i) * 64 + lane];
       butterfly<4, -1>(t);                  // over q: Fh(16 a + b) at t[a]
 #pragma unroll
-      for (int a = 0; a < 4; ++a) fh[4 * i + a] = t[a];
+      for (int a = 0; a < 4; ++a) fh[c][4 * i + a] = t[a];
     }
-    __syncthreads();                        // the exchange buffer is free again
   }
+  __syncthreads();                          // the exchange buffers are free again
   cx<R> g[16];
   auto load_g = [&](int j) {
     const cx<R>* Gj = G + (int64_t)j * N * P + pg;
@@ -218,27 +229,36 @@ __global__ __launch_bounds__(L64_BS) void k_pencil64(const cx<R>* __restrict__ W
   };
   load_g(0);
   for (int j = 0; j < J; ++j) {
-    cx<R> u[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) u[k] = cmul(g[k], fh[k]);
-    if (j + 1 < J) load_g(j + 1);           // in flight during this term
+    for (int c = 0; c < C; ++c) {
+      cx<R> u[16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      cx<R> t[4] = {u[4 * i], u[4 * i + 1], u[4 * i + 2], u[4 * i + 3]};
-      butterfly<4, +1>(t);                  // over a: residue r at t[r]
-      const int b = 4 * w + i;
-      lds[b * 64 + lane] = t[0];
+      for (int k = 0; k < 16; ++k) u[k] = cmul(g[k], fh[c][k]);
+      if (c == C - 1 && j + 1 < J) load_g(j + 1);   // in flight during this term
 #pragma unroll
-      for (int r = 1; r < 4; ++r) lds[(r * 16 + b) * 64 + lane] = cmul(t[r], root64<+1, R>(b * r));
+      for (int i = 0; i < 4; ++i) {
+        cx<R> t[4] = {u[4 * i], u[4 * i + 1], u[4 * i + 2], u[4 * i + 3]};
+        butterfly<4, +1>(t);                // over a: residue r at t[r]
+        const int b = 4 * w + i;
+        lds[c][b * 64 + lane] = t[0];
+#pragma unroll
+        for (int r = 1; r < 4; ++r)
+          lds[c][(r * 16 + b) * 64 + lane] = cmul(t[r], root64<+1, R>(b * r));
+      }
     }
     __syncthreads();
-    cx<R> v[16];
 #pragma unroll
-    for (int b = 0; b < 16; ++b) v[b] = lds[(w * 16 + b) * 64 + lane];
-    fft_line<16, +1>(v);                    // over b: x = 4 c + w at v[c]
-    cx<R>* Zj = Z + ((int64_t)cc * J + j) * N * P + p;
+    for (int c = 0; c < C; ++c) {
+      cx<R> v[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) store_stream(Zj + (int64_t)(4 * c + w) * P, v[c]);
+      for (int b = 0; b < 16; ++b) v[b] = lds[c][(w * 16 + b) * 64 + lane];
+      fft_line<16, +1>(v);                  // over b: x = 4 c' + w at v[c']
+      if (C == 1 || c < nc) {                // (no branch for one cell per block)
+        cx<R>* Zj = Z + ((int64_t)(c0 + c) * J + j) * N * P + p;
+#pragma unroll
+        for (int x4 = 0; x4 < 16; ++x4) store_stream(Zj + (int64_t)(4 * x4 + w) * P, v[x4]);
+      }
+    }
     __syncthreads();                        // every read of this term is done
   }
 }
@@ -482,8 +502,9 @@ static hipError_t launch_chunk_t(const ChunkArgs& a, hipStream_t st) {
       hipError_t e = launch_pencil_bf16(W, G, a.J, a.ncells, Z, N, st);
       if (e != hipSuccess) return e;
     } else if constexpr (N0 == 64) {
-      hipLaunchKernelGGL((k_pencil64<R>), dim3((unsigned)a.ncells * 64), dim3(L64_BS), 0, st, W,
-                         G, a.J, Z);
+      constexpr int CPB = pencil64_cells<R>();
+      hipLaunchKernelGGL((k_pencil64<R, CPB>), dim3((unsigned)((a.ncells + CPB - 1) / CPB) * 64),
+                         dim3(L64_BS), 0, st, W, G, a.J, a.ncells, Z);
     } else {
       const int64_t pencils = (int64_t)a.ncells * N * N;
       const int pblocks = (int)((pencils + PENCIL_BS - 1) / PENCIL_BS);
