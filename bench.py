@@ -212,6 +212,21 @@ def _read_counter_csv(d):
     return out
 
 
+def _reap_group(pgid, what):
+    """End whatever is left of a finished child's own session (the profiler
+    can leave a helper behind when it exits), so that the bench leaves no
+    process running."""
+    try:
+        os.killpg(pgid, 0)
+    except (ProcessLookupError, PermissionError):
+        return
+    log(f"bench: {what} run left processes in its group; ending them")
+    try:
+        os.killpg(pgid, signal.SIGKILL)
+    except ProcessLookupError:
+        pass
+
+
 def measure_traffic(args):
     """HBM bytes per launch of the dominant kernels, 2 counter runs of the
     child; None where rocprofv3 is missing or a run fails."""
@@ -235,6 +250,7 @@ def measure_traffic(args):
                 p.wait()
                 shutil.rmtree(d, ignore_errors=True)
                 return None, f"{ctr} counter run timed out"
+            _reap_group(p.pid, ctr)
         vals[ctr] = _read_counter_csv(d)
         shutil.rmtree(d, ignore_errors=True)
         # rocprofv3 can end with a signal after the program finished and the

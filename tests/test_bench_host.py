@@ -2,11 +2,13 @@
 measurement rows against the values the scope table states for it, the split
 of that count over the kernels, the matrix-core flops of the split-BF16 x
 pass, the roofline arithmetic, the parsing of rocprofv3 counter files, and
-the refusal of more than one GPU."""
+the refusal of more than one GPU, and the end of what a counter run leaves
+behind."""
 import csv
 import os
 import subprocess
 import sys
+import time
 
 import pytest
 
@@ -84,3 +86,25 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr and p.stdout == ""
+
+
+def test_counter_run_leftovers_are_ended():
+    # a child whose session keeps a process after the child itself exits (as
+    # a profiler's helper can): the reap after the wait leaves none running
+    p = subprocess.Popen(["sh", "-c", "sleep 60 & echo $!"], stdout=subprocess.PIPE, text=True,
+                         start_new_session=True)
+    left = int(p.stdout.readline())
+    p.wait()
+    os.kill(left, 0)                        # still there after the child ended
+    bench._reap_group(p.pid, "test")
+    deadline = time.time() + 5
+    while True:
+        try:
+            with open(f"/proc/{left}/stat") as fh:
+                if fh.read().rsplit(")", 1)[1].split()[0] == "Z":
+                    break                   # ended, not yet reaped by init
+        except FileNotFoundError:
+            break                           # ended and reaped
+        assert time.time() < deadline, "the leftover process still runs"
+        time.sleep(0.01)
+    bench._reap_group(p.pid, "test")        # nothing left: a no-op
