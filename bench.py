@@ -44,7 +44,7 @@ PEAK_BF16_MFMA = 2500.0   # TFLOP/s, MI355X dense BF16 matrix cores
 COPY_MIB = 256            # ec_copy size of the byte-counter calibration
 FULL_GRID_CELLS = [0, 127, 128, 255, 256, 511, 512, 1023]   # pass and round boundaries
 N, D, L, M, R = 32, 3, 8.0, 32, 6.0
-KNAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe", "k_fwdx", "k_fused"]
+KNAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe", "reserved", "k_fused"]
 
 
 def log(msg):
@@ -66,11 +66,13 @@ def flops_8d(n_side: int, d: int, terms: int) -> float:
 
 def kernel_flops(n_side: int, d: int, terms: int) -> list:
     """The same work split over the kernels that do it, indexed like the
-    profile slots (k_fwd, k_pencil, k_slab, k_pipe, k_fwdx, k_fused): the
-    forward transform's y, z passes (2/3) and x pass (1/3); the two-pass x
-    pass (forward x, the inverse x passes, the multiplies) and slab pass
-    (inverse y, z passes, products, loss); the pipelined and fused kernels do
-    everything after the forward transform (fused) or all of it (pipelined)."""
+    profile slots (k_fwd, k_pencil, k_slab, k_pipe, reserved, k_fused): in 3D
+    the two-pass schedule's slab transform does the forward transform's y, z
+    passes (2/3), its x pass (forward x, the inverse x passes, the
+    multiplies) and slab pass (inverse y, z passes, products, loss) the rest;
+    the fused schedules' forward kernel (slot 0 there) does the whole forward
+    transform, their fused kernel everything after it; the pipelined kernel
+    does all of it."""
     n = n_side ** d
     H = n_side ** (d - 1) * (n_side // 2 + 1)
     lg = math.log2(n)
@@ -78,14 +80,14 @@ def kernel_flops(n_side: int, d: int, terms: int) -> list:
     inv = (2 * terms + 1) * 2.5 * n * lg
     total = flops_8d(n_side, d, terms)
     if d == 3:
-        k_fwd, k_fwdx = fwd * 2 / 3, fwd / 3
+        k_fwd = fwd * 2 / 3
         k_pencil = fwd / 3 + inv / 3 + terms * 4 * H + 2 * H
         k_slab = inv * 2 / 3 + terms * 3 * n + 2 * n
     else:
-        k_fwd, k_fwdx = fwd, 0.0
+        k_fwd = fwd
         k_pencil = 0.0
         k_slab = total - fwd
-    return [k_fwd, k_pencil, k_slab, total, k_fwdx, total - fwd]
+    return [k_fwd, k_pencil, k_slab, total, 0.0, total - fwd]
 
 
 def bf16_gemm_flops(n_side: int, d: int, terms: int) -> float:

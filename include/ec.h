@@ -366,11 +366,13 @@ int ec_step_ssprk3(ec_batch* batch, double* f, double dt, int n_steps, double* m
  * Profiling of ec_collide (tracing).  While enabled, ec_collide records HIP
  * events on its stream around its kernels.  ec_profile_read waits for them and
  * returns, per group g of the batch and kernel k (EC_PROF_KERNELS per group:
- * 0 forward slab transform, 1 x-pencil pass, 2 slab pass of the two-pass
- * schedule, 3 the pipelined kernel, 4 forward x transform and 5 fused kernel
- * of the fused schedule), ms[6g + k] = summed duration and launches[6g + k] =
- * number of launches, and cells[g] = cells processed; then it forgets the
- * records.  Host arrays of 6 * n_groups (cells: n_groups).
+ * 0 forward transform (the slab transform of the two-pass schedule, the
+ * whole 3D transform of the fused and term-parallel schedules), 1 x-pencil
+ * pass, 2 slab pass of the two-pass schedule, 3 the pipelined kernel, 4
+ * reserved (always 0), 5 fused or term-parallel kernels), ms[6g + k] = summed
+ * duration and launches[6g + k] = number of launches, and cells[g] = cells
+ * processed; then it forgets the records.  Host arrays of 6 * n_groups
+ * (cells: n_groups).
  */
 #define EC_PROF_KERNELS 6
 int ec_profile(ec_batch* batch, int enable);

@@ -24,7 +24,7 @@ EC_NMON = 11
 EC_SCHED_PIPELINE, EC_SCHED_TWO_PASS, EC_SCHED_FUSED, EC_SCHED_LINES, EC_SCHED_TERMS = 0, 1, 2, 3, 4
 EC_PROF_KERNELS = 6
 EC_TUNE_REMEASURE = 1
-PROF_KERNEL_NAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe", "k_fwdx", "k_fused"]
+PROF_KERNEL_NAMES = ["k_fwd", "k_pencil", "k_slab", "k_pipe", "reserved", "k_fused"]
 MON_NAMES = ["mass", "sumQ", "entropy_prod", "eta", "minF", "eps_pos", "sumabsQ",
              "momQ_x", "momQ_y", "momQ_z", "energyQ"]
 

@@ -1099,10 +1099,12 @@ int ec_profile_read(ec_batch* b, double* ms, int64_t* launches, int64_t* cells) 
           launches[EC_PROF_KERNELS * r.group + k] += 1;
         }
       } else if (r.kind == 2) {
-        const int slot[3] = {0, 4, 5};   // k_fwd, k_fwdx, k_fused
-        for (int k = 0; k < 3; ++k) {
+        // the forward transform (events 0 -> 1) and the fused or term kernels
+        // (2 -> 3); 1 -> 2 is empty
+        const int slot[2] = {0, 5}, from[2] = {0, 2}, to[2] = {1, 3};
+        for (int k = 0; k < 2; ++k) {
           float t = 0.f;
-          HIPCHK(hipEventElapsedTime(&t, r.ev[k], r.ev[k + 1]));
+          HIPCHK(hipEventElapsedTime(&t, r.ev[from[k]], r.ev[to[k]]));
           ms[EC_PROF_KERNELS * r.group + slot[k]] += t;
           launches[EC_PROF_KERNELS * r.group + slot[k]] += 1;
         }

@@ -13,9 +13,10 @@ namespace efm {
 int fused_default_split(int N, int precision);
 bool fused_supported(int N, int precision, int split);
 
-// k_fwd (2D transform of every x slab into a.W), k_fwdx (x transform in place:
-// a.W then holds the unnormalised 3D spectrum), k_fused.  Events a.ev, when
-// set: before k_fwd, after k_fwd, after k_fwdx, after k_fused.
+// The unnormalised 3D spectrum of every cell into a.W, half-space layout
+// W[cell][kx][k2 < N/2][k1] (k_fwd3, or for small batches k_fwd and the
+// in-place x pass k_fwdx), then k_fused.  Events a.ev, when set: before the
+// forward transform, after it (twice), after k_fused.
 hipError_t launch_fused(const ChunkArgs& a, int split, hipStream_t st);
 
 // Term-parallel variant for small batches (3D, N = 16, 24, 32, FP64 or FP32,

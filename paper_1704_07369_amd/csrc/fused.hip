@@ -62,6 +62,130 @@ __global__ __launch_bounds__(64) void k_fwdx(cx<R>* __restrict__ W, int ncells) 
   for (int k = 0; k < N; ++k) Wc[(int64_t)k * P2] = v[k];
 }
 
+// The whole forward transform of one cell per workgroup (N = 16, 24, 32;
+// N^2/2 threads), into the half-space layout W[cell][kx][k2 < N/2][k1]:
+//  1. the cell is read in halves through LDS, so that consecutive lanes load
+//     consecutive values; thread (xl, y), xl < N/2, then transforms the real
+//     z lines of (xl, y) and (xl + N/2, y) as one complex line C = DFT(a + i b)
+//     and separates the two half spectra, A(k) = (C(k) + conj C(-k)) / 2 and
+//     B(k) = (C(k) - conj C(-k)) / 2i for k2 < N/2;
+//  2. through LDS (real parts, then imaginary parts) thread (x, k2) collects
+//     its y line and transforms it;
+//  3. through LDS thread (k2, k1) collects its x line, transforms it and
+//     stores the pencil (consecutive threads, consecutive k1).
+// F is read once and W written once, half the device-memory bytes of a slab
+// pass followed by an in-place x pass.  Rows of N + 1 elements keep the
+// lanes of every LDS access on distinct banks.
+template <typename R, int N>
+__global__ __launch_bounds__(N * N / 2) void k_fwd3(const double* __restrict__ f,
+                                                    const int64_t* __restrict__ off,
+                                                    int64_t cell0, cx<R>* __restrict__ W) {
+  constexpr int H = N / 2, LD = N + 1, S = H * LD, T = N * N / 2;
+  __shared__ R lds[N * S];
+  const int t = threadIdx.x;
+  const int64_t cc = blockIdx.x;
+  const int xl = t / N, y = t % N;          // stage 1
+  const int x = t / H, k2 = t % H;          // stage 2
+  cx<R> A[H], B[H];
+  {
+    // each half x < N/2, x >= N/2 of the cell (N^3/2 values, N per thread)
+    // read with consecutive lanes on consecutive values, then its z lines
+    // taken from LDS (line xl N + y of the half = row t)
+    const double* fc = f + off[cell0 + cc];
+    cx<R> v[N];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h) __syncthreads();
+#pragma unroll
+      for (int i = 0; i < N; ++i)             // value t + i N^2/2 of the half: (row xl + i H, z = y)
+        lds[(xl + i * H) * LD + y] = (R)fc[(int64_t)h * H * N * N + t + i * T];
+      __syncthreads();
+#pragma unroll
+      for (int z = 0; z < N; ++z) {
+        if (h == 0) v[z].x = lds[t * LD + z];
+        else v[z].y = lds[t * LD + z];
+      }
+    }
+    __syncthreads();                        // the rows are read before the exchanges
+    fft_line<N, -1>(v);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const cx<R> p = v[k], m = v[(N - k) % N];
+      A[k] = {(R)0.5 * (p.x + m.x), (R)0.5 * (p.y - m.y)};
+      B[k] = {(R)0.5 * (p.y + m.y), (R)0.5 * (m.x - p.x)};
+    }
+  }
+  cx<R> u[N];
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    lds[(xl * H + k) * LD + y] = A[k].x;
+    lds[((xl + H) * H + k) * LD + y] = B[k].x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i].x = lds[t * LD + i];   // t * LD = (x H + k2) LD
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    lds[(xl * H + k) * LD + y] = A[k].y;
+    lds[((xl + H) * H + k) * LD + y] = B[k].y;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i].y = lds[t * LD + i];
+  fft_line<N, -1>(u);                       // (x, k1, k2)
+  cx<R> w[N];
+  const int q2 = t / N, q1 = t % N;         // stage 3
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) lds[x * S + k2 * LD + k1] = u[k1].x;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i].x = lds[i * S + q2 * LD + q1];
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) lds[x * S + k2 * LD + k1] = u[k1].y;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i].y = lds[i * S + q2 * LD + q1];
+  fft_line<N, -1>(w);
+  cx<R>* Wc = W + cc * N * H * N + t;       // t = k2 N + k1
+#pragma unroll
+  for (int kx = 0; kx < N; ++kx) Wc[(int64_t)kx * H * N] = w[kx];
+}
+
+// forward transform of the fused schedules: the spectrum in the half-space
+// layout.  k_fwd3 for batches that give every CU a cell; smaller batches
+// (one workgroup per cell would leave most CUs idle and the cell's load
+// latency exposed) take the slab pass and the in-place x pass, spread over
+// N^2/2 and N^2/128 blocks per cell.  Events 0 and 1 bracket the forward
+// transform, event 2 follows at once (no 3D schedule has a separate x pass).
+// (the smallest batch for k_fwd3, measured on MI355X: at N = 32 the two
+// kernels take 14 against 23 us for 32 cells, 24 against 21 us for 64; at
+// N = 24 14 against 15 us for 64 cells, 16 against 15 for 96; at N = 16
+// k_fwd3 is faster from one cell on)
+template <int N>
+constexpr int fwd3_min_cells() { return N == 16 ? 1 : (N == 24 ? 96 : 64); }
+
+template <typename R, int N>
+static hipError_t launch_fwd_half(const ChunkArgs& a, hipStream_t st) {
+  if (a.ev) (void)hipEventRecord(a.ev[0], st);
+  if (a.ncells >= fwd3_min_cells<N>()) {
+    hipLaunchKernelGGL((k_fwd3<R, N>), dim3((unsigned)a.ncells), dim3(N * N / 2), 0, st, a.f,
+                       a.off, a.cell0, (cx<R>*)a.W);
+  } else {
+    hipError_t e = launch_fwd_half_slabs(a, st);
+    if (e != hipSuccess) return e;
+    constexpr int KZ = N / 2;
+    const int64_t pencils = (int64_t)a.ncells * KZ * N;
+    hipLaunchKernelGGL((k_fwdx<R, N, KZ>), dim3((unsigned)((pencils + 63) / 64)), dim3(64), 0,
+                       st, (cx<R>*)a.W, a.ncells);
+  }
+  if (a.ev) (void)hipEventRecord(a.ev[1], st);
+  if (a.ev) (void)hipEventRecord(a.ev[2], st);
+  return hipGetLastError();
+}
+
 // Planes k2 < C of this thread's Fh inputs kept in registers across terms
 // (measured on MI355X, 1024 cells: more planes spill or cost occupancy)
 template <int N, int P, int B>
@@ -772,15 +896,9 @@ __global__ __launch_bounds__(256) void k_terms_reduce(const double* __restrict__
 
 template <typename R, int N, int P>
 static hipError_t launch_terms_t(const ChunkArgs& a, hipStream_t st) {
-  constexpr int KZ = N / 2;
   cx<R>* W = (cx<R>*)a.W;
-  hipError_t e = launch_fwd(a, st, true);
+  hipError_t e = launch_fwd_half<R, N>(a, st);
   if (e != hipSuccess) return e;
-  if (a.ev) (void)hipEventRecord(a.ev[1], st);
-  const int64_t pencils = (int64_t)a.ncells * KZ * N;
-  hipLaunchKernelGGL((k_fwdx<R, N, KZ>), dim3((unsigned)((pencils + 63) / 64)), dim3(64), 0, st,
-                     W, a.ncells);
-  if (a.ev) (void)hipEventRecord(a.ev[2], st);
   const dim3 grid((unsigned)((a.ncells + 7) / 8 * 8 * P), (unsigned)a.J);
   if constexpr (N == 32)
     hipLaunchKernelGGL((k_terms_col<R, N, P>), grid, dim3(fused_threads<N, P>()), 0, st,
@@ -824,19 +942,13 @@ hipError_t launch_terms(const ChunkArgs& a, int split, hipStream_t st) {
   return split == 2 ? launch_terms_t<float, 32, 2>(a, st) : launch_terms_t<float, 32, 4>(a, st);
 }
 
-// k_fwd, k_fwdx, then the fused kernel (COL: the column form)
+// the forward transform, then the fused kernel (COL: the column form); both
+// forms read only the half space k2 < N/2 of the spectrum
 template <typename R, int N, int P, bool COL>
 static hipError_t launch_fused_t(const ChunkArgs& a, hipStream_t st) {
   cx<R>* W = (cx<R>*)a.W;
-  // both forms read only the half space k2 < N/2 of the spectrum
-  constexpr int KZ = N / 2;
-  hipError_t e = launch_fwd(a, st, true);
+  hipError_t e = launch_fwd_half<R, N>(a, st);
   if (e != hipSuccess) return e;
-  if (a.ev) (void)hipEventRecord(a.ev[1], st);
-  const int64_t pencils = (int64_t)a.ncells * KZ * N;
-  hipLaunchKernelGGL((k_fwdx<R, N, KZ>), dim3((unsigned)((pencils + 63) / 64)), dim3(64), 0, st,
-                     W, a.ncells);
-  if (a.ev) (void)hipEventRecord(a.ev[2], st);
   const dim3 grid((unsigned)((a.ncells + 7) / 8 * 8 * P)), block(fused_threads<N, P>());
   if constexpr (COL)
     hipLaunchKernelGGL((k_fused_col<R, N, P>), grid, block, 0, st, (const cx<R>*)W,

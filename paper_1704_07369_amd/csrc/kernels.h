@@ -42,10 +42,9 @@ hipError_t launch_terms_reduce(const ChunkArgs& a, int n, hipStream_t s);
 bool terms_2d_supported(int N);
 hipError_t launch_terms_2d(const ChunkArgs& a, hipStream_t s);
 
-// k_fwd only (3D, N in 16, 24, 32, 64): W[cell][x][k2][k1] = 2D transform of
-// every x slab; half (N = 16, 24, 32): only k2 < N/2, W[cell][x][k2 < N/2][k1].
-// Records a.ev[0] before it when a.ev is set.
-hipError_t launch_fwd(const ChunkArgs& a, hipStream_t s, bool half = false);
+// k_fwd alone (3D, N = 16, 24, 32) into the half-space layout
+// W[cell][x][k2 < N/2][k1]: the 2D transform of every x slab.  No events.
+hipError_t launch_fwd_half_slabs(const ChunkArgs& a, hipStream_t s);
 
 // Per-cell reductions (fixed order, deterministic).  Any output may be null.
 //   full:    [cell][EC_NMON]

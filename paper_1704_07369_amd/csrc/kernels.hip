@@ -547,31 +547,28 @@ static hipError_t launch_chunk_r(const ChunkArgs& a, hipStream_t st) {
 #undef EFM_CASE
 }
 
-template <typename R, int N, int KZ>
-static hipError_t launch_fwd_t(const ChunkArgs& a, hipStream_t st) {
+template <typename R, int N>
+static hipError_t launch_fwd_slabs_t(const ChunkArgs& a, hipStream_t st) {
   constexpr int SPB = slabs_per_block<N>();
-  const int64_t slabs = (int64_t)a.ncells * N;
-  const int slab_blocks = (int)((slabs + SPB - 1) / SPB);
-  if (a.ev) (void)hipEventRecord(a.ev[0], st);
-  hipLaunchKernelGGL((k_fwd<R, N, N, KZ>), dim3(slab_blocks), dim3(SPB * N), 0, st, a.f, a.off,
-                     a.cell0, a.ncells, (cx<R>*)a.W);
+  const int slab_blocks = (int)(((int64_t)a.ncells * N + SPB - 1) / SPB);
+  hipLaunchKernelGGL((k_fwd<R, N, N, N / 2>), dim3(slab_blocks), dim3(SPB * N), 0, st, a.f,
+                     a.off, a.cell0, a.ncells, (cx<R>*)a.W);
   return hipGetLastError();
 }
 
 template <typename R>
-static hipError_t launch_fwd_r(const ChunkArgs& a, bool half, hipStream_t st) {
+static hipError_t launch_fwd_slabs_r(const ChunkArgs& a, hipStream_t st) {
   switch (a.N) {
-    case 16: return half ? launch_fwd_t<R, 16, 8>(a, st) : launch_fwd_t<R, 16, 16>(a, st);
-    case 24: return half ? launch_fwd_t<R, 24, 12>(a, st) : launch_fwd_t<R, 24, 24>(a, st);
-    case 32: return half ? launch_fwd_t<R, 32, 16>(a, st) : launch_fwd_t<R, 32, 32>(a, st);
-    case 64: return launch_fwd_t<R, 64, 64>(a, st);
+    case 16: return launch_fwd_slabs_t<R, 16>(a, st);
+    case 24: return launch_fwd_slabs_t<R, 24>(a, st);
+    case 32: return launch_fwd_slabs_t<R, 32>(a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_fwd(const ChunkArgs& a, hipStream_t st, bool half) {
-  if (a.d != 3 || (half && a.N != 16 && a.N != 24 && a.N != 32)) return hipErrorInvalidValue;
-  return a.precision != 0 ? launch_fwd_r<float>(a, half, st) : launch_fwd_r<double>(a, half, st);
+hipError_t launch_fwd_half_slabs(const ChunkArgs& a, hipStream_t st) {
+  if (a.d != 3) return hipErrorInvalidValue;
+  return a.precision != 0 ? launch_fwd_slabs_r<float>(a, st) : launch_fwd_slabs_r<double>(a, st);
 }
 
 hipError_t launch_chunk(const ChunkArgs& a, hipStream_t st) {

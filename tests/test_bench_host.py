@@ -5,6 +5,7 @@ pass, the roofline arithmetic, the parsing of rocprofv3 counter files, and
 the refusal of more than one GPU, and the end of what a counter run leaves
 behind."""
 import csv
+import math
 import os
 import subprocess
 import sys
@@ -31,13 +32,14 @@ def test_flops_per_evaluation_match_the_stated_figures():
                                             (32, 2, 32)])
 def test_kernel_split_covers_the_evaluation(n_side, d, terms):
     total = bench.flops_8d(n_side, d, terms)
-    k_fwd, k_pencil, k_slab, k_pipe, k_fwdx, k_fused = bench.kernel_flops(n_side, d, terms)
-    assert k_pipe == total
+    k_fwd, k_pencil, k_slab, k_pipe, reserved, k_fused = bench.kernel_flops(n_side, d, terms)
+    assert k_pipe == total and reserved == 0.0
     # each schedule's kernels do the whole evaluation once: two-pass k_fwd
-    # (y, z), k_pencil (forward x, multiplies, inverse x), k_slab; fused k_fwd,
-    # k_fwdx (forward x) and the fused kernel
+    # (y, z), k_pencil (forward x, multiplies, inverse x), k_slab; fused: the
+    # whole forward transform (2.5 n log2 n) and the fused kernel
     assert k_fwd + k_pencil + k_slab == pytest.approx(total, rel=1e-12)
-    assert k_fwd + k_fwdx + k_fused == pytest.approx(total, rel=1e-12)
+    n = n_side ** d
+    assert 2.5 * n * math.log2(n) + k_fused == pytest.approx(total, rel=1e-12)
     if (n_side, d) == (32, 3):
         assert k_fused == pytest.approx(85.35e6, rel=1e-4)
 
@@ -50,8 +52,8 @@ def test_bf16_matrix_flops():
 
 def test_roofline_arithmetic():
     flops = bench.kernel_flops(32, 3, 32)
-    ms = [1.0, 0.0, 0.0, 0.0, 2.0, 60.0]          # the fused slot dominates
-    launches = [20, 0, 0, 0, 20, 20]
+    ms = [2.7, 0.0, 0.0, 0.0, 0.0, 60.0]          # the fused slot dominates
+    launches = [20, 0, 0, 0, 0, 20]
     prof = (ms, launches, 1024 * 20)
     r = bench.roofline(prof, flops, bench.PEAK_FP64, traffic=123)
     assert r["kernel"] == "k_fused" and r["launches"] == 20

@@ -107,3 +107,35 @@ def test_fused_step_in_place(N):
         outs.append((f.cpu().numpy(), mon.cpu().numpy()))
     assert np.abs(outs[0][0] - outs[1][0]).max() <= 1e-13 * np.abs(outs[1][0]).max()
     assert np.allclose(outs[0][1], outs[1][1], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("N,prec", [(24, 0), (24, 1), (32, 0), (32, 1)])
+def test_forward_kernel_paths(N, prec):
+    """The fused schedule's forward transform takes one workgroup per cell
+    (k_fwd3) from 96 cells at 24^3 and 64 at 32^3, the slab pass and the
+    in-place x pass below that.  The same cells in a batch of 128 and in a
+    batch of 3 (fused, default split): both against the oracle on sampled
+    points (first and last cell of the large batch), and FP64 against each
+    other on the full grid to 1e-13 (the two forward paths round differently)."""
+    say(f"case forward paths N={N} precision={prec}")
+    big = [synth.sample_mixture(synth.mixture_anisotropic(7500 + i, 3), N, L) for i in range(128)]
+    split = {24: 3, 32: 2}[N]                 # the default splits
+    a = run(N, big, prec, E.EC_SCHED_FUSED, 0, split)
+    b = run(N, big[:3], prec, E.EC_SCHED_FUSED, 0, split)
+    op = oplan(N)
+    rng = np.random.default_rng(75 + N)
+    for out, c in ((a, 0), (a, 127), (b, 0), (b, 2)):
+        assert np.all(np.isfinite(out[c]))
+        idx = np.unique(np.concatenate([np.argsort(big[c].ravel())[-12:],
+                                        rng.choice(N ** 3, 28, replace=False)]))
+        q, qp, qm, _ = efm.collide_points(op, big[c], idx)
+        err = np.abs(out[c].ravel()[idx] - q).max() / np.abs(qp).max()
+        tol = bound_pts(prec, N, 3, qp, qm)
+        say(f"  {'k_fwd3' if out is a else 'slab + x pass'} cell {c}: rel err {err:.3e} "
+            f"(bound {tol:.2e})")
+        assert err <= tol
+    if prec == 0:
+        for c in range(3):
+            d = np.linalg.norm(a[c] - b[c]) / np.linalg.norm(b[c])
+            say(f"  cell {c}: |batch of 128 - batch of 3| / |Q| = {d:.3e}")
+            assert d <= 1e-13
