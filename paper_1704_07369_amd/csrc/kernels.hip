@@ -686,8 +686,21 @@ __global__ __launch_bounds__(MON_BS) void k_step_monitors(
   const double* fc = f + off[c];
   const int n = cell_n[c];
   double m = 0.0, e = 0.0;
-#pragma unroll 4
-  for (int r = threadIdx.x; r < n; r += MON_BS) {
+  // eight loads in flight per thread before their logarithms (the values
+  // are added in the order of a plain strided loop)
+  constexpr int U = 8;
+  int r = threadIdx.x;
+  for (; r + (U - 1) * MON_BS < n; r += U * MON_BS) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = fc[r + u * MON_BS];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      m += v[u];
+      if (v[u] > 0.0) e += v[u] * log(v[u]);
+    }
+  }
+  for (; r < n; r += MON_BS) {
     const double fv = fc[r];
     m += fv;
     if (fv > 0.0) e += fv * log(fv);
