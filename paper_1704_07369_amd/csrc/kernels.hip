@@ -24,6 +24,7 @@
 #include "kernels.h"
 
 #include "fft.h"
+#include "logpos.h"
 #include "mfma.h"
 
 namespace efm {
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(MON_BS) void k_monitors(
     a[0] += fv;
     a[1] += qv;
     if (fv > 0.0) {
-      const double lf = log(fv);
+      const double lf = log_pos(fv);
       a[2] += qv * lf;
       a[3] += fv * lf;
     } else {
@@ -697,13 +698,13 @@ __global__ __launch_bounds__(MON_BS) void k_step_monitors(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       m += v[u];
-      if (v[u] > 0.0) e += v[u] * log(v[u]);
+      if (v[u] > 0.0) e += v[u] * log_pos(v[u]);
     }
   }
   for (; r < n; r += MON_BS) {
     const double fv = fc[r];
     m += fv;
-    if (fv > 0.0) e += fv * log(fv);
+    if (fv > 0.0) e += fv * log_pos(fv);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
