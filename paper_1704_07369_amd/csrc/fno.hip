@@ -249,6 +249,81 @@ __global__ __launch_bounds__(256) void k_fno_mix2(const cx<float>* __restrict__ 
   }
 }
 
+// The same mixing on the matrix cores (C = 16).  Per mode m and chunk of 64
+// cells, Y = scale X W with X, Y 64 x 16 complex and W 16 x 16 complex
+// (forward W(c, j) = R[m][c][j], adjoint W(c, j) = conj R[m][j][c]), as the
+// real product [Xr Xi] [[Wr, Wi], [-Wi, Wr]] = [Yr Yi] of K = 32: four cell
+// tiles x two output halves x eight K steps of v_mfma_f32_16x16x4_f32, FP32
+// products and sums as on the vector ALU.  Operand layout of 16x16x4 (lane l,
+// r = l % 16, q = l / 16): A[r][q], B[q][r], D[4 q + v][r] (v < 4).  One wave
+// per (mode, cell chunk).  K step k (< 4: real parts, then imaginary parts)
+// takes channel 4 q + k % 4 in the slot of lane group q, so lane (r, q) loads
+// the four contiguous channels 4 q .. 4 q + 3 of X[b0 + 16 t + r][m] (32
+// bytes, t < 4; cells beyond B read as zero and store nothing) and
+// W(4 q + k, r), k < 4.
+constexpr int MIX_MFMA_CELLS = 64;
+
+__global__ __launch_bounds__(256) void k_fno_mix_mfma16(const cx<float>* __restrict__ R,
+                                                        const cx<float>* __restrict__ X, int B,
+                                                        int NM, int adjoint, float scale,
+                                                        cx<float>* __restrict__ Y) {
+  constexpr int C = 16, CT = MIX_MFMA_CELLS / 16;
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nchunk = (B + MIX_MFMA_CELLS - 1) / MIX_MFMA_CELLS;
+  if (wid >= (int64_t)NM * nchunk) return;  // uniform per wave
+  const int m = (int)(wid % NM);
+  const int b0 = (int)(wid / NM) * MIX_MFMA_CELLS;
+  const int r = lane & 15, q = lane >> 4;
+  const cx<float>* Rm = R + (int64_t)m * C * C;
+  cx<float> w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = 4 * q + k;
+    const cx<float> t = adjoint ? Rm[r * C + c] : Rm[c * C + r];
+    w[k] = {t.x, adjoint ? -t.y : t.y};
+  }
+  cx<float> x[CT][4];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+    const int b = b0 + 16 * t + r;
+    // two 16-byte loads: X is a device allocation of its own and a lane's
+    // channels start at a multiple of 32 bytes
+    const float4* xp = reinterpret_cast<const float4*>(X + ((int64_t)b * NM + m) * C + 4 * q);
+    const float4 lo = b < B ? xp[0] : float4{0.f, 0.f, 0.f, 0.f};
+    const float4 hi = b < B ? xp[1] : float4{0.f, 0.f, 0.f, 0.f};
+    x[t][0] = {lo.x, lo.y};
+    x[t][1] = {lo.z, lo.w};
+    x[t][2] = {hi.x, hi.y};
+    x[t][3] = {hi.z, hi.w};
+  }
+  v4f acc[CT][2];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      acc[t][h] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        // A = [Xr Xi]; B rows k < 4: [Wr | Wi], rows k >= 4: [-Wi | Wr]
+        const float a = k < 4 ? x[t][k].x : x[t][k - 4].y;
+        const cx<float> wk = w[k & 3];
+        const float bv = k < 4 ? (h == 0 ? wk.x : wk.y) : (h == 0 ? -wk.y : wk.x);
+        acc[t][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[t][h], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + 16 * t + 4 * q + v;
+      if (b < B) Y[((int64_t)b * NM + m) * C + r] = {scale * acc[t][0][v], scale * acc[t][1][v]};
+    }
+  }
+}
+
 // dR[m][i][o] = scale sum_b G[b][m][o] conj(U[b][m][i]); one thread per (m, o),
 // summing every input channel i over the cells in order
 template <int C>
@@ -699,6 +774,21 @@ static unsigned mix_blocks(int B, int NM) {
   return (unsigned)((nt + 255) / 256);
 }
 
+// mode mixing (forward, or the adjoint with conj R transposed): on the matrix
+// cores at C = 16, on the vector ALU otherwise
+template <int C>
+static void launch_mix(const cx<float>* R, const cx<float>* X, int B, int NM, int adjoint,
+                       float scale, cx<float>* Y, hipStream_t st) {
+  if constexpr (C == 16) {
+    const int64_t waves = (int64_t)((B + MIX_MFMA_CELLS - 1) / MIX_MFMA_CELLS) * NM;
+    hipLaunchKernelGGL(k_fno_mix_mfma16, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, R,
+                       X, B, NM, adjoint, scale, Y);
+  } else {
+    hipLaunchKernelGGL((k_fno_mix2<C>), dim3(mix_blocks<C>(B, NM)), dim3(256), 0, st, R, X, B,
+                       NM, adjoint, scale, Y);
+  }
+}
+
 template <int N, int K, int C>
 struct FnoOps {
   using D = FnoDims<N, K>;
@@ -763,8 +853,7 @@ static hipError_t fno_forward_t(const FnoArgs& a, hipStream_t st) {
     hipError_t e = l == 0 ? O::fwd_transform(a.u[l], B * C, a.T, a.Uh[l], st, li)
                           : O::fwd_x_pass(a.T, B * C, a.Uh[l], st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fno_mix2<C>), dim3(mix_blocks<C>(B, D::NM)), dim3(256), 0, st, a.R[l],
-                       a.Uh[l], B, D::NM, 0, 1.f / (float)n, a.V);
+    launch_mix<C>(a.R[l], a.Uh[l], B, D::NM, 0, 1.f / (float)n, a.V, st);
     e = O::inv_x_pass(a.V, B * C, a.T, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fno_inv_slab_pointwise<N, K, C>), dim3(N, (unsigned)B), dim3(C * N), 0,
@@ -824,8 +913,7 @@ static hipError_t fno_backward_t(const FnoArgs& args, hipStream_t st) {
     const int64_t nmc = (int64_t)D::NM * C;
     hipLaunchKernelGGL((k_fno_dR<C>), dim3((unsigned)((nmc + 255) / 256)), dim3(256), 0, st, a.V,
                        a.Uh[l], B, D::NM, 1.f / (float)n, a.gR[l]);
-    hipLaunchKernelGGL((k_fno_mix2<C>), dim3(mix_blocks<C>(B, D::NM)), dim3(256), 0, st, a.R[l],
-                       a.V, B, D::NM, 1, 1.f / (float)n, a.V2);
+    launch_mix<C>(a.R[l], a.V, B, D::NM, 1, 1.f / (float)n, a.V2, st);
     // du_in = pointwise part + Re IDFT(scatter(Gu))
     e = O::inv_transform(a.V2, B * C, a.T, a.du2, 1, st);
     if (e != hipSuccess) return e;
