@@ -139,3 +139,20 @@ def test_forward_kernel_paths(N, prec):
             d = np.linalg.norm(a[c] - b[c]) / np.linalg.norm(b[c])
             say(f"  cell {c}: |batch of 128 - batch of 3| / |Q| = {d:.3e}")
             assert d <= 1e-13
+
+
+@pytest.mark.parametrize("N,nmin", [(24, 96), (32, 64)])
+def test_forward_kernel_threshold(N, nmin):
+    """Batches of nmin - 1 and nmin cells fall on either side of the switch
+    between the two-kernel forward transform and k_fwd3: their common cells
+    agree on the full grid to 1e-13 (FP64, fused, default split)."""
+    say(f"case forward threshold N={N}: {nmin - 1} and {nmin} cells")
+    cells = [synth.sample_mixture(synth.mixture_anisotropic(7600 + i, 3), N, L) for i in range(nmin)]
+    split = {24: 3, 32: 2}[N]
+    a = run(N, cells[:nmin - 1], 0, E.EC_SCHED_FUSED, 0, split)
+    b = run(N, cells, 0, E.EC_SCHED_FUSED, 0, split)
+    for c in (0, nmin // 2, nmin - 2):
+        d = np.linalg.norm(a[c] - b[c]) / np.linalg.norm(b[c])
+        say(f"  cell {c}: |{nmin - 1} cells - {nmin} cells| / |Q| = {d:.3e}")
+        assert np.all(np.isfinite(b[c])) and d <= 1e-13
+    assert np.all(np.isfinite(b[nmin - 1]))

@@ -77,6 +77,29 @@ def test_forward_and_gradients_match_reference(N, K, C, L, B, nfd):
     assert err < 2e-3
 
 
+def test_forward_over_several_mixing_chunks():
+    """The mode mixing at 16 channels runs on the matrix cores with one wave
+    per mode and 64 cells: a batch of 67 cells (one full chunk and a ragged
+    one of 3) at the production size (32^3, 12 modes, 16 channels, one layer)
+    against the FP64 reference network, every cell within the forward bound."""
+    import torch
+    N, K, C, L, B = 32, 12, 16, 1, 67
+    say(f"case surrogate forward N={N} K={K} C={C} L={L} B={B}")
+    sur = Surrogate(N, K, C, L, seed=9, max_batch=B)
+    p = _perturbed_params(sur, 13)
+    sur.set_params(p)
+    x, _ = _inputs(N, B, 8)
+    xd = to_dev(x)
+    y = torch.zeros_like(xd)
+    sur.forward(xd, y, B)
+    torch.cuda.synchronize()
+    yref = fno.forward(p.astype(np.float64), x.astype(np.float64), N, K, C, L)
+    err = np.abs(y.cpu().numpy() - yref).max(axis=1) / np.abs(yref).max(axis=1)
+    say(f"  per-cell forward rel err: max {err.max():.3e} (cells 0, 63, 64, 66: "
+        f"{err[0]:.2e} {err[63]:.2e} {err[64]:.2e} {err[66]:.2e})")
+    assert err.max() < 1e-5
+
+
 def test_screen_fallback_matches_exact_operator():
     """A corrupted network (NaN weights) fails the screen on every cell, and
     the fallback returns the exact operator's Q."""
