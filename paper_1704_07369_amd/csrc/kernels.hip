@@ -450,11 +450,118 @@ __global__ __launch_bounds__(N) void k_terms_2d(const cx<R>* __restrict__ W,
   }
 }
 
+// One 2D cell per block for small batches: J groups of N threads, group t runs
+// term t (t = J - 1: the loss).  Each group transforms the cell itself (the
+// forward transform is a small part of the work, and the spectrum never
+// leaves the CU): thread i takes column z = i of F, the y pass, a transpose
+// in the group's LDS slice and the z pass, which leave it the spectrum column
+// k1 = i that its term needs; then the product with the term's table (loads
+// in groups of 8, so that they are not all in flight next to the line), the
+// inverse z pass, a transpose, the inverse y pass and Re c Im c (the loss:
+// -F Re c) into the slice.  The block sums the slices per point, the loss
+// first and the terms in order (the order of k_terms_reduce), and writes Q or
+// F + dt Q.  LDS: J slices of N (N + 1) doubles (transposes in real and
+// imaginary halves, in R; products in FP64), at most cell2d_jmax slices.
+template <int N>
+constexpr int cell2d_jmax() {
+  return 1024 / N < 163840 / (N * (N + 1) * 8) ? 1024 / N : 163840 / (N * (N + 1) * 8);
+}
+
+// Smallest batch on which the 2D term-parallel schedule runs k_cell_2d, per
+// precision and N (measured on MI355X, M' = 16, 1 to 1024 cells): FP64 at
+// N = 32 never (a line takes more registers than 17 groups of 32 threads
+// leave: 24.8 against 14.8 us for one cell), FP64 at N = 24 from 128 cells
+// (17.0 against 20.9 us; 14.9 against 13.3 us for one cell), everything else
+// from one cell (N = 16 FP64 7.8 against 12.4 us, N = 32 FP32 13.3 against
+// 14.2 us for one cell and 56.6 against 91.8 us for 1024; 0: never).
+template <typename R, int N>
+constexpr int cell2d_min_cells() {
+  return sizeof(R) == 8 && N == 32 ? 0 : (sizeof(R) == 8 && N == 24 ? 128 : 1);
+}
+
+template <typename R, int N>
+__global__ __launch_bounds__(cell2d_jmax<N>() * N) void k_cell_2d(
+    const cx<R>* __restrict__ G, int J, const double* f, const int64_t* __restrict__ off,
+    int64_t cell0, double* Q, double dt) {
+  constexpr int JM = cell2d_jmax<N>(), LD = N + 1, S = N * LD, KB = N < 8 ? N : 8;
+  __shared__ double lds[JM * S];
+  const int g = threadIdx.x / N, i = threadIdx.x % N;
+  const int64_t base = off[cell0 + blockIdx.x];
+  const double* fc = f + base;
+  double* sl = lds + g * S;                 // this group's slice
+  R* rs = reinterpret_cast<R*>(sl);
+  cx<R> v[N];
+#pragma unroll
+  for (int y = 0; y < N; ++y) v[y] = {(R)fc[y * N + i], (R)0};
+  fft_line<N, -1>(v);                       // (k1, z = i)
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) rs[k1 * LD + i] = v[k1].x;
+  __syncthreads();
+#pragma unroll
+  for (int z = 0; z < N; ++z) v[z].x = rs[i * LD + z];
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) rs[k1 * LD + i] = v[k1].y;
+  __syncthreads();
+#pragma unroll
+  for (int z = 0; z < N; ++z) v[z].y = rs[i * LD + z];
+  fft_line<N, -1>(v);                       // Fh(k1 = i, k2)
+  const cx<R>* Gt = G + (int64_t)g * N * N;
+#pragma unroll
+  for (int k0 = 0; k0 < N; k0 += KB) {
+    cx<R> gl[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) gl[k] = Gt[(k0 + k) * N + i];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) v[k0 + k] = cmul(gl[k], v[k0 + k]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  fft_line<N, +1>(v);                       // (k1 = i, z)
+  __syncthreads();
+#pragma unroll
+  for (int z = 0; z < N; ++z) rs[i * LD + z] = v[z].x;
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) v[k1].x = rs[k1 * LD + i];
+  __syncthreads();
+#pragma unroll
+  for (int z = 0; z < N; ++z) rs[i * LD + z] = v[z].y;
+  __syncthreads();
+#pragma unroll
+  for (int k1 = 0; k1 < N; ++k1) v[k1].y = rs[k1 * LD + i];
+  fft_line<N, +1>(v);                       // c(y, z = i)
+  __syncthreads();                          // every slice is free for the products
+  if (g == J - 1) {
+#pragma unroll
+    for (int y = 0; y < N; ++y) sl[y * N + i] = -fc[y * N + i] * (double)v[y].x;
+  } else {
+#pragma unroll
+    for (int y = 0; y < N; ++y) sl[y * N + i] = (double)v[y].x * (double)v[y].y;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < N * N; r += J * N) {
+    double q = lds[(J - 1) * S + r];
+    for (int t = 0; t < J - 1; ++t) q += lds[t * S + r];
+    Q[base + r] = dt == 0.0 ? q : fc[r] + dt * q;
+  }
+}
+
 template <typename R, int N>
 static hipError_t launch_terms_2d_t(const ChunkArgs& a, hipStream_t st) {
   constexpr int SPB = slabs_per_block<N>();
   const int slab_blocks = (int)((a.ncells + SPB - 1) / SPB);
   cx<R>* W = (cx<R>*)a.W;
+  if constexpr (cell2d_min_cells<R, N>() > 0) {
+    if (a.J <= cell2d_jmax<N>() && a.ncells >= cell2d_min_cells<R, N>()) {
+      // forward transform inside the kernel: events 0 .. 2 in a row
+      for (int k = 0; k < 3; ++k)
+        if (a.ev) (void)hipEventRecord(a.ev[k], st);
+      hipLaunchKernelGGL((k_cell_2d<R, N>), dim3((unsigned)a.ncells), dim3(a.J * N), 0, st,
+                         (const cx<R>*)a.gamma, a.J, a.f, a.off, a.cell0, a.Q, a.dt);
+      if (a.ev) (void)hipEventRecord(a.ev[3], st);
+      return hipGetLastError();
+    }
+  }
   if (a.ev) (void)hipEventRecord(a.ev[0], st);
   hipLaunchKernelGGL((k_fwd<R, 1, N>), dim3(slab_blocks), dim3(SPB * N), 0, st, a.f, a.off,
                      a.cell0, a.ncells, W);

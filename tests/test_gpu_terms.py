@@ -275,3 +275,59 @@ def test_terms_with_a_ragged_term_count(Nl, prec):
         err = np.abs(qt.ravel()[idx] - q).max() / scale
         say(f"  cell {c}: vs fused {d_fused:.2e} of the gain, vs oracle {err:.2e}")
         assert np.all(np.isfinite(qt)) and d_fused <= 1e-14 and err <= bound_pts(prec, Nl, 3, qp, qm)
+
+
+def _collide_2d(N, cells, prec):
+    import torch
+    p = E.Plan(N, 2, 8.0, 16, R=6.0)
+    b = E.Batch([p], [len(cells)], prec)
+    b.set_schedule(0, E.EC_SCHED_TERMS, 0, 0)
+    f = to_dev(E.pack(b, cells))
+    Q = torch.full_like(f, float("nan"))
+    b.collide(f, Q)
+    torch.cuda.synchronize()
+    out = E.unpack(b, Q.cpu().numpy())
+    b.close()
+    return out
+
+
+@pytest.mark.parametrize("N,prec,ncell", [(8, 0, 3), (12, 0, 2), (16, 0, 3), (16, 1, 2),
+                                          (24, 1, 2), (32, 1, 2)])
+def test_2d_one_block_per_cell(N, prec, ncell):
+    """2D cells of the term-parallel schedule evaluated one block per cell
+    (k_cell_2d: 17 groups of N threads for M' = 16, each transforming the
+    cell and running one term, the products summed in LDS): every cell on the
+    full grid against the oracle's double sum, within the stated bound."""
+    from tests.gpu_util import bound_full, rel_err
+    say(f"case 2D one block per cell N={N} precision={prec} cells={ncell}")
+    cells = [synth.sample_mixture(synth.mixture_two_gaussians(8100 + N + c, 2), N, 8.0)
+             for c in range(ncell)]
+    out = _collide_2d(N, cells, prec)
+    op = efm.make_plan(N, 2, 8.0, 16, R=6.0)
+    for c in range(ncell):
+        ref = efm.collide_modes(op, cells[c])
+        err = rel_err(out[c], ref.Q, ref.Qplus)
+        tol = bound_full(prec, N, 2, ref)
+        say(f"  cell {c}: rel err {err:.3e} (bound {tol:.2e})")
+        assert np.all(np.isfinite(out[c])) and err <= tol
+
+
+def test_2d_one_block_switch_at_24():
+    """At 24^2 FP64 the one-block kernel runs from 128 cells (below, the slab
+    transform, the term kernel and the sum): batches of 127 and 128 cells
+    agree on their common cells to 1e-13, and the first cell of the larger
+    batch matches the oracle."""
+    from tests.gpu_util import rel_err
+    say("case 2D 24^2 FP64: 127 and 128 cells")
+    cells = [synth.sample_mixture(synth.mixture_two_gaussians(8200 + c, 2), 24, 8.0)
+             for c in range(128)]
+    a = _collide_2d(24, cells[:127], 0)
+    b = _collide_2d(24, cells, 0)
+    for c in (0, 63, 126):
+        d = np.linalg.norm(a[c] - b[c]) / np.linalg.norm(b[c])
+        say(f"  cell {c}: |127 cells - 128 cells| / |Q| = {d:.3e}")
+        assert d <= 1e-13
+    ref = efm.collide_modes(efm.make_plan(24, 2, 8.0, 16, R=6.0), cells[0])
+    err = rel_err(b[0], ref.Q, ref.Qplus)
+    say(f"  cell 0 of 128 vs the oracle: {err:.3e}")
+    assert np.all(np.isfinite(b[127])) and err <= 1e-12
