@@ -367,7 +367,8 @@ int ec_step_ssprk3(ec_batch* batch, double* f, double dt, int n_steps, double* m
  * events on its stream around its kernels.  ec_profile_read waits for them and
  * returns, per group g of the batch and kernel k (EC_PROF_KERNELS per group:
  * 0 forward transform (the slab transform of the two-pass schedule, the
- * whole 3D transform of the fused and term-parallel schedules), 1 x-pencil
+ * whole 3D transform of the fused and term-parallel schedules; 2D cells run
+ * as one block each include it in 5), 1 x-pencil
  * pass, 2 slab pass of the two-pass schedule, 3 the pipelined kernel, 4
  * reserved (always 0), 5 fused or term-parallel kernels), ms[6g + k] = summed
  * duration and launches[6g + k] = number of launches, and cells[g] = cells
