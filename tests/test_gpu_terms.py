@@ -291,8 +291,8 @@ def _collide_2d(N, cells, prec):
     return out
 
 
-@pytest.mark.parametrize("N,prec,ncell", [(8, 0, 3), (12, 0, 2), (16, 0, 3), (16, 1, 2),
-                                          (24, 1, 2), (32, 1, 2)])
+@pytest.mark.parametrize("N,prec,ncell", [(8, 0, 3), (8, 1, 2), (12, 0, 2), (12, 1, 2),
+                                          (16, 0, 3), (16, 1, 2), (24, 1, 2), (32, 1, 2)])
 def test_2d_one_block_per_cell(N, prec, ncell):
     """2D cells of the term-parallel schedule evaluated one block per cell
     (k_cell_2d: 17 groups of N threads for M' = 16, each transforming the
