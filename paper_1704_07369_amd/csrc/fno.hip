@@ -371,10 +371,97 @@ __global__ __launch_bounds__(256) void k_fno_lift(const float* __restrict__ Fin,
   for (int c = 0; c < C; ++c) u0[(b * C + c) * n + r] = Wl[c] * f + bl[c];
 }
 
+// The pointwise layer of one slab on the matrix cores (C = 16): per chunk of
+// 64 points of the slab, pre = W in as four 16 x 16 x 16 products of four
+// v_mfma_f32_16x16x4_f32 each (operand layout as in the mode mixing: lane l,
+// r = l % 16, q = l / 16 supplies A[r][q] and B[q][r] and holds D[4 q + v][r]).
+// K step j takes input channel 4 q + j in the slot of lane group q, and tile t
+// holds the points c0 + 4 r + t in its columns, so lane (r, q) loads the four
+// contiguous points c0 + 4 r .. c0 + 4 r + 3 of channels 4 q + j and ends
+// with output channels 4 q + v of the same four points, stored the same way.
+// Then h = pre + bias + s (s: the spectral branch in rl), uo = GELU(h) or h;
+// the projection sum_c Wp[c] uo[c] + bp adds the four lane groups' partial
+// sums across lanes.  keep: uo replaces s in rl for the next forward slab pass.
+template <int N>
+__device__ __forceinline__ void pointwise_mfma16(
+    float (*rl)[N][N + 1], int x, int64_t b, const float* __restrict__ u, const LiftIn& lift,
+    const float* __restrict__ W, const float* __restrict__ bias, int act, float* __restrict__ h,
+    float* __restrict__ uo, const float* __restrict__ Wp, const float* __restrict__ bp,
+    float* __restrict__ yout, bool keep) {
+  constexpr int C = 16, n = N * N * N, NW = C * N / 64;
+  static_assert(N % 8 == 0, "64-point chunks of whole 4-point row pieces");
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  float wa[4], bo[4], wp[4], wl[4], bl[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    wa[j] = W[r * C + 4 * q + j];
+    bo[j] = bias[4 * q + j];
+    wp[j] = yout ? Wp[4 * q + j] : 0.f;
+    wl[j] = lift.Fin ? lift.Wl[4 * q + j] : 0.f;
+    bl[j] = lift.Fin ? lift.bl[4 * q + j] : 0.f;
+  }
+  const float bp0 = yout ? bp[0] : 0.f;
+  for (int ch = wv; ch < N * N / 64; ch += NW) {   // uniform per wave
+    const int p = ch * 64 + 4 * r;                 // the lane's first point in the slab
+    const int yy = p / N, zz = p % N;              // its four points lie in row yy
+    const int64_t rg = (int64_t)x * N * N + p;
+    v4f in[4];
+    if (lift.Fin) {   // a caller's array: no alignment beyond 4 bytes assumed
+      const float* fp = lift.Fin + b * n + rg;
+      const float f0 = fp[0], f1 = fp[1], f2 = fp[2], f3 = fp[3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        in[j] = v4f{wl[j] * f0 + bl[j], wl[j] * f1 + bl[j], wl[j] * f2 + bl[j], wl[j] * f3 + bl[j]};
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        in[j] = *reinterpret_cast<const v4f*>(u + (b * C + 4 * q + j) * n + rg);
+    }
+    v4f acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[j], in[j][t], acc[t], 0, 0, 0);
+    }
+    v4f py = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int o = 4 * q + v;
+      v4f hv, ov;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        hv[t] = acc[t][v] + bo[v] + rl[o][yy][zz + t];
+        ov[t] = act ? gelu(hv[t]) : hv[t];
+      }
+      const int64_t go = (b * C + o) * n + rg;
+      if (h) *reinterpret_cast<v4f*>(h + go) = hv;
+      if (uo) *reinterpret_cast<v4f*>(uo + go) = ov;
+      py += wp[v] * ov;
+      if (keep) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) rl[o][yy][zz + t] = ov[t];   // this lane's own entries
+      }
+    }
+    if (yout) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        py[t] += __shfl_xor(py[t], 16);
+        py[t] += __shfl_xor(py[t], 32);
+      }
+      if (q == 0) *reinterpret_cast<v4f*>(yout + b * n + rg) = py + bp0;
+    }
+  }
+}
+
 // Forward layer tail, fused: the inverse slab pass of the spectral branch for
 // the slab x of every channel of cell b (grid (x, b), C N threads), then
-// h = W u + bias + s, uo = GELU(h) (or h) at the slab's points, so that the
-// spectral branch s never goes through global memory.  h and uo are stored
+// h = W u + bias + s, uo = GELU(h) (or h) at the slab's points (C = 16: W u on
+// the matrix cores, pointwise_mfma16), so that the spectral branch s never
+// goes through global memory.  h and uo are stored
 // only when non-null; lift.Fin set: u is the lifted input formed here; yout
 // set (last layer): also the projection yout = sum_c Wp[c] uo[c] + bp; Tnext
 // set: also the next layer's forward slab pass of uo into Tnext.
@@ -417,31 +504,35 @@ __global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
 #pragma unroll
   for (int z = 0; z < N; ++z) rl[c][i][z] = v[z].x;
   __syncthreads();
-  for (int q = threadIdx.x; q < N * N; q += NT) {   // points (yy, zz) of the slab
-    const int yy = q / N, zz = q % N;
-    const int64_t r = (int64_t)x * N * N + q;
-    float in[C];
-    if (lift.Fin) {
-      const float fv = lift.Fin[b * n + r];
+  if constexpr (C == 16) {
+    pointwise_mfma16<N>(rl, x, b, u, lift, W, bias, act, h, uo, Wp, bp, yout, Tnext != nullptr);
+  } else {
+    for (int q = threadIdx.x; q < N * N; q += NT) {   // points (yy, zz) of the slab
+      const int yy = q / N, zz = q % N;
+      const int64_t r = (int64_t)x * N * N + q;
+      float in[C];
+      if (lift.Fin) {
+        const float fv = lift.Fin[b * n + r];
 #pragma unroll
-      for (int k = 0; k < C; ++k) in[k] = lift.Wl[k] * fv + lift.bl[k];
-    } else {
+        for (int k = 0; k < C; ++k) in[k] = lift.Wl[k] * fv + lift.bl[k];
+      } else {
 #pragma unroll
-      for (int k = 0; k < C; ++k) in[k] = u[(b * C + k) * n + r];
+        for (int k = 0; k < C; ++k) in[k] = u[(b * C + k) * n + r];
+      }
+      float py = yout ? bp[0] : 0.f;
+#pragma unroll
+      for (int o = 0; o < C; ++o) {
+        float acc = bias[o] + rl[o][yy][zz];
+#pragma unroll
+        for (int k = 0; k < C; ++k) acc += W[o * C + k] * in[k];
+        if (h) h[(b * C + o) * n + r] = acc;
+        const float out = act ? gelu(acc) : acc;
+        if (uo) uo[(b * C + o) * n + r] = out;
+        if (yout) py += Wp[o] * out;               // the projection sum_c Wp[c] u[c] + bp
+        if (Tnext) rl[o][yy][zz] = out;            // this thread's own entries of s
+      }
+      if (yout) yout[b * n + r] = py;
     }
-    float py = yout ? bp[0] : 0.f;
-#pragma unroll
-    for (int o = 0; o < C; ++o) {
-      float acc = bias[o] + rl[o][yy][zz];
-#pragma unroll
-      for (int k = 0; k < C; ++k) acc += W[o * C + k] * in[k];
-      if (h) h[(b * C + o) * n + r] = acc;
-      const float out = act ? gelu(acc) : acc;
-      if (uo) uo[(b * C + o) * n + r] = out;
-      if (yout) py += Wp[o] * out;               // the projection sum_c Wp[c] u[c] + bp
-      if (Tnext) rl[o][yy][zz] = out;            // this thread's own entries of s
-    }
-    if (yout) yout[b * n + r] = py;
   }
   if (!Tnext) return;
   // the next layer's forward slab pass of the slab x of every channel, from
