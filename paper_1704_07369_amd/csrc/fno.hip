@@ -159,6 +159,87 @@ __global__ __launch_bounds__(256) void k_fno_inv_x(const cx<float>* __restrict__
   for (int x = 0; x < N; ++x) Ts[(int64_t)x * D::PEN] = v[x];
 }
 
+// The spectral branch between the slab passes of inference, fused: for a
+// tile of TP = 128 / C kept (ky, kz) pencils of every channel of two cells
+// (grid (pencil tiles, cell pairs), 256 threads), the forward x transform
+// (kept kx only), the mode mixing Y[m][o] = scale sum_i R[m][i][o] X[m][i] of
+// those modes (the products and sums of k_fno_mix2, in the same order) and the
+// inverse x transform, in place in T, so the kept modes never go through
+// global memory.  Thread (o, pencil, kx parity) reads its C weights of a mode
+// once for both cells, with the next mode's weights in flight.
+template <int N, int K, int C>
+__global__ __launch_bounds__(256) void k_fno_xmix(cx<float>* T, int B,
+                                                  const cx<float>* __restrict__ R, float scale) {
+  using D = FnoDims<N, K>;
+  constexpr int TP = 128 / C, CB = 2, LC = C + 1, KH = D::KY / 2;
+  static_assert(C * TP * CB == 256, "one thread per x line");
+  __shared__ cx<float> X[CB][D::KY][TP][LC];
+  const int pen0 = blockIdx.x * TP;
+  const int np = min(TP, D::PEN - pen0);
+  const int b0 = blockIdx.y * CB;
+  const int nb = min(CB, B - b0);
+  // thread (cell, c, p): the x line of pencil pen0 + p, channel c
+  const int p = threadIdx.x % TP, c = (threadIdx.x / TP) % C, cl = threadIdx.x / (TP * C);
+  const bool line = p < np && cl < nb;
+  cx<float>* Ts = T + ((int64_t)(b0 + cl) * C + c) * N * D::PEN + pen0 + p;
+  if (line) {
+    cx<float> v[N];
+#pragma unroll
+    for (int x = 0; x < N; ++x) v[x] = Ts[(int64_t)x * D::PEN];
+    fft_line<N, -1>(v);
+#pragma unroll
+    for (int mx = 0; mx < D::KY; ++mx) X[cl][mx][p][c] = v[kidx<N, K>(mx)];
+  }
+  __syncthreads();
+  // thread (o, pm, par): output channel o of pencil pen0 + pm at kx = 2 h + par
+  const int o = threadIdx.x % C, pm = (threadIdx.x / C) % TP, par = threadIdx.x / (C * TP);
+  cx<float> y[KH][CB];
+  if (pm < np) {
+    const cx<float>* Rp = R + (int64_t)(par * D::PEN + pen0 + pm) * C * C + o;
+    constexpr int64_t STEP = (int64_t)2 * D::PEN * C * C;   // kx -> kx + 2
+    cx<float> wn[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) wn[k] = Rp[k * C];
+#pragma unroll
+    for (int h = 0; h < KH; ++h) {
+      const int mx = 2 * h + par;
+      cx<float> w[C];
+#pragma unroll
+      for (int k = 0; k < C; ++k) w[k] = wn[k];
+      if (h + 1 < KH) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) wn[k] = Rp[(h + 1) * STEP + k * C];
+      }
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        cx<float> acc = {0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < C; ++k) acc = cadd(acc, cmul(w[k], X[q][mx][pm][k]));
+        y[h][q] = {scale * acc.x, scale * acc.y};
+      }
+    }
+  }
+  __syncthreads();                               // every read of X is done
+  if (pm < np) {
+#pragma unroll
+    for (int h = 0; h < KH; ++h) {
+#pragma unroll
+      for (int q = 0; q < CB; ++q) X[q][2 * h + par][pm][o] = y[h][q];
+    }
+  }
+  __syncthreads();
+  if (line) {
+    cx<float> v[N];
+#pragma unroll
+    for (int x = 0; x < N; ++x) v[x] = {0.f, 0.f};
+#pragma unroll
+    for (int mx = 0; mx < D::KY; ++mx) v[kidx<N, K>(mx)] = X[cl][mx][p][c];
+    fft_line<N, +1>(v);
+#pragma unroll
+    for (int x = 0; x < N; ++x) Ts[(int64_t)x * D::PEN] = v[x];
+  }
+}
+
 // truncated inverse transform, slab pass: T[s][x][ky][kz] -> out[s][x][y][z] = Re(...)
 // (accumulate != 0: out += result); the real slabs are staged in LDS so that
 // the global stores are contiguous
@@ -893,6 +974,21 @@ struct FnoOps {
                        dim3(256), 0, st, T, Uh);
     return hipGetLastError();
   }
+  static hipError_t fwd_slab_pass(const float* u, int nsc, cx<float>* T, hipStream_t st,
+                                  LiftIn lift = LiftIn()) {
+    const int64_t nslab = (int64_t)nsc * N;
+    constexpr int SB = slabs_per_block<N>();
+    hipLaunchKernelGGL((k_fno_fwd_slab<N, K>), dim3((unsigned)((nslab + SB - 1) / SB)), dim3(256),
+                       0, st, u, T, nslab, lift, C);
+    return hipGetLastError();
+  }
+  // x transform, mode mixing and inverse x transform of B cells, in place in T
+  static hipError_t xmix(cx<float>* T, int B, const cx<float>* R, float scale, hipStream_t st) {
+    constexpr int TP = 128 / C;
+    hipLaunchKernelGGL((k_fno_xmix<N, K, C>), dim3((D::PEN + TP - 1) / TP, (unsigned)((B + 1) / 2)),
+                       dim3(256), 0, st, T, B, R, scale);
+    return hipGetLastError();
+  }
   static hipError_t fwd_x_pass(const cx<float>* T, int nsc, cx<float>* Uh, hipStream_t st) {
     constexpr int TP = pens_per_block<C>();
     hipLaunchKernelGGL((k_fno_fwd_x<N, K, C>), dim3((D::PEN + TP - 1) / TP, (unsigned)(nsc / C)),
@@ -940,12 +1036,21 @@ static hipError_t fno_forward_t(const FnoArgs& a, hipStream_t st) {
   for (int l = 0; l < a.L; ++l) {
     const LiftIn li = l == 0 ? lift : LiftIn();
     const bool last = l + 1 == a.L;
-    // the slab pass of layers l > 0 ran in the previous layer's last kernel
-    hipError_t e = l == 0 ? O::fwd_transform(a.u[l], B * C, a.T, a.Uh[l], st, li)
-                          : O::fwd_x_pass(a.T, B * C, a.Uh[l], st);
-    if (e != hipSuccess) return e;
-    launch_mix<C>(a.R[l], a.Uh[l], B, D::NM, 0, 1.f / (float)n, a.V, st);
-    e = O::inv_x_pass(a.V, B * C, a.T, st);
+    // the slab pass of layers l > 0 ran in the previous layer's last kernel.
+    // Training stores the kept modes Uh for the weight gradient: separate x
+    // passes and mixing on the matrix cores; inference runs them fused
+    hipError_t e = hipSuccess;
+    if (keep) {
+      e = l == 0 ? O::fwd_transform(a.u[l], B * C, a.T, a.Uh[l], st, li)
+                 : O::fwd_x_pass(a.T, B * C, a.Uh[l], st);
+      if (e != hipSuccess) return e;
+      launch_mix<C>(a.R[l], a.Uh[l], B, D::NM, 0, 1.f / (float)n, a.V, st);
+      e = O::inv_x_pass(a.V, B * C, a.T, st);
+    } else {
+      e = l == 0 ? O::fwd_slab_pass(a.u[l], B * C, a.T, st, li) : hipSuccess;
+      if (e != hipSuccess) return e;
+      e = O::xmix(a.T, B, a.R[l], 1.f / (float)n, st);
+    }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fno_inv_slab_pointwise<N, K, C>), dim3(N, (unsigned)B), dim3(C * N), 0,
                        st, a.T, a.u[l], li, a.W[l], a.bias[l], last ? 0 : 1,
