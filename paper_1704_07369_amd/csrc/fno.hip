@@ -163,8 +163,8 @@ __global__ __launch_bounds__(256) void k_fno_inv_x(const cx<float>* __restrict__
 // tile of TP = 128 / C kept (ky, kz) pencils of every channel of two cells
 // (grid (pencil tiles, cell pairs), 256 threads), the forward x transform
 // (kept kx only), the mode mixing Y[m][o] = scale sum_i R[m][i][o] X[m][i] of
-// those modes (the products and sums of k_fno_mix2, in the same order) and the
-// inverse x transform, in place in T, so the kept modes never go through
+// those modes (summed over i in order, each complex product added as four
+// fused multiply-adds) and the inverse x transform, in place in T, so the kept modes never go through
 // global memory.  Thread (o, pencil, kx parity) reads its C weights of a mode
 // once for both cells, with the next mode's weights in flight.
 template <int N, int K, int C>
@@ -214,7 +214,13 @@ __global__ __launch_bounds__(256) void k_fno_xmix(cx<float>* T, int B,
       for (int q = 0; q < CB; ++q) {
         cx<float> acc = {0.f, 0.f};
 #pragma unroll
-        for (int k = 0; k < C; ++k) acc = cadd(acc, cmul(w[k], X[q][mx][pm][k]));
+        for (int k = 0; k < C; ++k) {   // acc += w X as four fused multiply-adds
+          const cx<float> xv = X[q][mx][pm][k];
+          acc.x = fmaf(w[k].x, xv.x, acc.x);
+          acc.x = fmaf(-w[k].y, xv.y, acc.x);
+          acc.y = fmaf(w[k].x, xv.y, acc.y);
+          acc.y = fmaf(w[k].y, xv.x, acc.y);
+        }
         y[h][q] = {scale * acc.x, scale * acc.y};
       }
     }
