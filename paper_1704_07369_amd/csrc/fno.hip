@@ -40,6 +40,17 @@ __device__ __forceinline__ int kidx(int m) {   // index m in [0, 2K) -> FFT inde
   return m < K ? m : N - 2 * K + m;
 }
 
+// Offset of the truncated spectrum T of (cell b, channel c, slab x, kept
+// (ky, kz) pencil e): channel-first [b][c][x][pen] (training, whose x passes
+// take a tile of pencils of one channel), or channel-last [b][x][pen][c]
+// (inference at C = 16, whose spectral kernel takes one pencil of every
+// channel of 16 cells)
+template <int N, int K, int C, bool CL>
+__device__ __forceinline__ int64_t tofs(int64_t b, int c, int x, int e) {
+  constexpr int PEN = FnoDims<N, K>::PEN;
+  return CL ? ((b * N + x) * PEN + e) * C + c : ((b * C + c) * N + x) * PEN + e;
+}
+
 // ---------------------------------------------------------------------------
 // Transform passes.  Slab passes take SB = 256 / N slabs per 256-thread block
 // (one thread per line, LDS transposes inside each slab); x passes take one
@@ -159,90 +170,82 @@ __global__ __launch_bounds__(256) void k_fno_inv_x(const cx<float>* __restrict__
   for (int x = 0; x < N; ++x) Ts[(int64_t)x * D::PEN] = v[x];
 }
 
-// The spectral branch between the slab passes of inference, fused: for a
-// tile of TP = 128 / C kept (ky, kz) pencils of every channel of two cells
-// (grid (pencil tiles, cell pairs), 256 threads), the forward x transform
-// (kept kx only), the mode mixing Y[m][o] = scale sum_i R[m][i][o] X[m][i] of
-// those modes (summed over i in order, each complex product added as four
-// fused multiply-adds) and the inverse x transform, in place in T, so the kept modes never go through
-// global memory.  Thread (o, pencil, kx parity) reads its C weights of a mode
-// once for both cells, with the next mode's weights in flight.
-template <int N, int K, int C>
-__global__ __launch_bounds__(256) void k_fno_xmix(cx<float>* T, int B,
-                                                  const cx<float>* __restrict__ R, float scale) {
+// The spectral branch between the slab passes of inference at C = 16, fused,
+// on the channel-last T: one block per (kept (ky, kz) pencil, chunk of 16
+// cells), 256 threads.
+//  1. thread (cell r, channel c) transforms its x line forward (the 16
+//     channels of a cell are 128 contiguous bytes at each x) and keeps the
+//     kx of the kept modes, into LDS;
+//  2. wave w mixes the pencil's modes kx = w, w + 4, ... on the matrix cores:
+//     per mode Y = scale X W over the 16 cells as in k_fno_mix_mfma16 (the
+//     real product [Xr Xi] [[Wr, Wi], [-Wi, Wr]], 16 v_mfma_f32_16x16x4_f32;
+//     lane (r, q) takes channels 4 q .. 4 q + 3 of cell r from LDS and the
+//     weights W(4 q + k, r) = R[m][4 q + k][r], and ends with output channel
+//     r of cells 4 q .. 4 q + 3, which it writes over the mode's inputs);
+//  3. thread (cell, c) transforms the mixed line back and stores it in place.
+// The kept modes never go through global memory, and each weight is read once
+// per 16 cells.  Cells beyond B transform zeros and store nothing.
+template <int N, int K>
+__global__ __launch_bounds__(256) void k_fno_xmix16(cx<float>* T, int B,
+                                                    const cx<float>* __restrict__ R, float scale) {
   using D = FnoDims<N, K>;
-  constexpr int TP = 128 / C, CB = 2, LC = C + 1, KH = D::KY / 2;
-  static_assert(C * TP * CB == 256, "one thread per x line");
-  __shared__ cx<float> X[CB][D::KY][TP][LC];
-  const int pen0 = blockIdx.x * TP;
-  const int np = min(TP, D::PEN - pen0);
+  constexpr int C = 16, CB = 16, LC = C + 1;
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  __shared__ cx<float> X[D::KY][CB][LC];
+  const int pen = blockIdx.x;
   const int b0 = blockIdx.y * CB;
-  const int nb = min(CB, B - b0);
-  // thread (cell, c, p): the x line of pencil pen0 + p, channel c
-  const int p = threadIdx.x % TP, c = (threadIdx.x / TP) % C, cl = threadIdx.x / (TP * C);
-  const bool line = p < np && cl < nb;
-  cx<float>* Ts = T + ((int64_t)(b0 + cl) * C + c) * N * D::PEN + pen0 + p;
-  if (line) {
+  const int c = threadIdx.x % C, cl = threadIdx.x / C;
+  const bool live = b0 + cl < B;
+  cx<float>* Tl = T + tofs<N, K, C, true>(b0 + cl, c, 0, pen);   // + x PEN C
+  constexpr int64_t XS = (int64_t)D::PEN * C;
+  {
     cx<float> v[N];
 #pragma unroll
-    for (int x = 0; x < N; ++x) v[x] = Ts[(int64_t)x * D::PEN];
+    for (int x = 0; x < N; ++x) v[x] = live ? Tl[x * XS] : cx<float>{0.f, 0.f};
     fft_line<N, -1>(v);
 #pragma unroll
-    for (int mx = 0; mx < D::KY; ++mx) X[cl][mx][p][c] = v[kidx<N, K>(mx)];
+    for (int mx = 0; mx < D::KY; ++mx) X[mx][cl][c] = v[kidx<N, K>(mx)];
   }
   __syncthreads();
-  // thread (o, pm, par): output channel o of pencil pen0 + pm at kx = 2 h + par
-  const int o = threadIdx.x % C, pm = (threadIdx.x / C) % TP, par = threadIdx.x / (C * TP);
-  cx<float> y[KH][CB];
-  if (pm < np) {
-    const cx<float>* Rp = R + (int64_t)(par * D::PEN + pen0 + pm) * C * C + o;
-    constexpr int64_t STEP = (int64_t)2 * D::PEN * C * C;   // kx -> kx + 2
-    cx<float> wn[C];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  for (int mx = wv; mx < D::KY; mx += 4) {   // uniform per wave
+    const cx<float>* Rm = R + (int64_t)(mx * D::PEN + pen) * C * C;
+    cx<float> w[4], xv[4];
 #pragma unroll
-    for (int k = 0; k < C; ++k) wn[k] = Rp[k * C];
+    for (int k = 0; k < 4; ++k) {
+      w[k] = Rm[(4 * q + k) * C + r];
+      xv[k] = X[mx][r][4 * q + k];
+    }
+    v4f acc[2];
 #pragma unroll
-    for (int h = 0; h < KH; ++h) {
-      const int mx = 2 * h + par;
-      cx<float> w[C];
+    for (int hh = 0; hh < 2; ++hh) {
+      acc[hh] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int k = 0; k < C; ++k) w[k] = wn[k];
-      if (h + 1 < KH) {
-#pragma unroll
-        for (int k = 0; k < C; ++k) wn[k] = Rp[(h + 1) * STEP + k * C];
-      }
-#pragma unroll
-      for (int q = 0; q < CB; ++q) {
-        cx<float> acc = {0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < C; ++k) {   // acc += w X as four fused multiply-adds
-          const cx<float> xv = X[q][mx][pm][k];
-          acc.x = fmaf(w[k].x, xv.x, acc.x);
-          acc.x = fmaf(-w[k].y, xv.y, acc.x);
-          acc.y = fmaf(w[k].x, xv.y, acc.y);
-          acc.y = fmaf(w[k].y, xv.x, acc.y);
-        }
-        y[h][q] = {scale * acc.x, scale * acc.y};
+      for (int k = 0; k < 8; ++k) {
+        // A = [Xr Xi]; B rows k < 4: [Wr | Wi], rows k >= 4: [-Wi | Wr]
+        const float a = k < 4 ? xv[k].x : xv[k - 4].y;
+        const cx<float> wk = w[k & 3];
+        const float bv = k < 4 ? (hh == 0 ? wk.x : wk.y) : (hh == 0 ? -wk.y : wk.x);
+        acc[hh] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[hh], 0, 0, 0);
       }
     }
-  }
-  __syncthreads();                               // every read of X is done
-  if (pm < np) {
+    // this wave's reads of X[mx] precede its writes (one wave, in order)
 #pragma unroll
-    for (int h = 0; h < KH; ++h) {
-#pragma unroll
-      for (int q = 0; q < CB; ++q) X[q][2 * h + par][pm][o] = y[h][q];
-    }
+    for (int v = 0; v < 4; ++v) X[mx][4 * q + v][r] = {scale * acc[0][v], scale * acc[1][v]};
   }
   __syncthreads();
-  if (line) {
+  {
     cx<float> v[N];
 #pragma unroll
     for (int x = 0; x < N; ++x) v[x] = {0.f, 0.f};
 #pragma unroll
-    for (int mx = 0; mx < D::KY; ++mx) v[kidx<N, K>(mx)] = X[cl][mx][p][c];
+    for (int mx = 0; mx < D::KY; ++mx) v[kidx<N, K>(mx)] = X[mx][cl][c];
     fft_line<N, +1>(v);
+    if (live) {
 #pragma unroll
-    for (int x = 0; x < N; ++x) Ts[(int64_t)x * D::PEN] = v[x];
+      for (int x = 0; x < N; ++x) Tl[x * XS] = v[x];
+    }
   }
 }
 
@@ -552,7 +555,7 @@ __device__ __forceinline__ void pointwise_mfma16(
 // only when non-null; lift.Fin set: u is the lifted input formed here; yout
 // set (last layer): also the projection yout = sum_c Wp[c] uo[c] + bp; Tnext
 // set: also the next layer's forward slab pass of uo into Tnext.
-template <int N, int K, int C>
+template <int N, int K, int C, bool CL>
 __global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
     const cx<float>* T, const float* __restrict__ u, LiftIn lift,
     const float* __restrict__ W, const float* __restrict__ bias, int act, float* __restrict__ h,
@@ -560,24 +563,28 @@ __global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
     float* __restrict__ yout, cx<float>* Tnext) {   // T and Tnext may alias
   using D = FnoDims<N, K>;
   constexpr int NT = C * N, LN = N + 1, n = D::n;
-  constexpr int CBYTES = (int)sizeof(cx<float>) * C * N * (K + 1);
+  // spectrum [C][N][K + 1] with an odd channel stride, so that lanes of
+  // consecutive channels hit distinct banks
+  constexpr int CS = N * (K + 1) + 1;
+  constexpr int CBYTES = (int)sizeof(cx<float>) * C * CS;
   constexpr int RBYTES = (int)sizeof(float) * C * N * LN;
   __shared__ __align__(16) unsigned char raw[CBYTES > RBYTES ? CBYTES : RBYTES];
-  auto lds = reinterpret_cast<cx<float>(*)[N][K + 1]>(raw);   // [C][N][K + 1] spectrum
+  cx<float>* const sp = reinterpret_cast<cx<float>*>(raw);
+  auto lds = [sp](int c, int y, int col) -> cx<float>& { return sp[c * CS + y * (K + 1) + col]; };
   auto rl = reinterpret_cast<float(*)[N][LN]>(raw);            // [C][N][N + 1] branch s
   const int x = blockIdx.x;
   const int64_t b = blockIdx.y;
   for (int t = threadIdx.x; t < C * K; t += NT) {   // (channel, kz column) items
-    const int c = t / K, col = t % K;
-    const cx<float>* Ts = T + ((b * C + c) * N + x) * D::PEN;
+    // consecutive threads take consecutive entries of the layout
+    const int c = CL ? t % C : t / K, col = CL ? t / C : t % K;
     cx<float> v[N];
 #pragma unroll
     for (int y = 0; y < N; ++y) v[y] = {0.f, 0.f};
 #pragma unroll
-    for (int m = 0; m < D::KY; ++m) v[kidx<N, K>(m)] = Ts[m * K + col];
+    for (int m = 0; m < D::KY; ++m) v[kidx<N, K>(m)] = T[tofs<N, K, C, CL>(b, c, x, m * K + col)];
     fft_line<N, +1>(v);
 #pragma unroll
-    for (int y = 0; y < N; ++y) lds[c][y][col] = v[y];
+    for (int y = 0; y < N; ++y) lds(c, y, col) = v[y];
   }
   __syncthreads();
   const int c = threadIdx.x / N, i = threadIdx.x % N;   // thread (c, i): line y = i
@@ -585,7 +592,7 @@ __global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
 #pragma unroll
   for (int z = 0; z < N; ++z) v[z] = {0.f, 0.f};
 #pragma unroll
-  for (int kz = 0; kz < K; ++kz) v[kz] = lds[c][i][kz];
+  for (int kz = 0; kz < K; ++kz) v[kz] = lds(c, i, kz);
   fft_line<N, +1>(v);
   __syncthreads();                                // every read of the spectrum is done
 #pragma unroll
@@ -630,17 +637,49 @@ __global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
   fft_line<N, -1>(v);
   __syncthreads();                                // every read of the outputs is done
 #pragma unroll
-  for (int kz = 0; kz < K; ++kz) lds[c][i][kz] = v[kz];
+  for (int kz = 0; kz < K; ++kz) lds(c, i, kz) = v[kz];
   __syncthreads();
   for (int t = threadIdx.x; t < C * K; t += NT) {   // (channel, kz column) items
-    const int cc = t / K, col = t % K;
+    const int cc = CL ? t % C : t / K, col = CL ? t / C : t % K;
     cx<float> w[N];
 #pragma unroll
-    for (int y = 0; y < N; ++y) w[y] = lds[cc][y][col];
+    for (int y = 0; y < N; ++y) w[y] = lds(cc, y, col);
     fft_line<N, -1>(w);
-    cx<float>* Ts = Tnext + ((b * C + cc) * N + x) * D::PEN;
 #pragma unroll
-    for (int m = 0; m < D::KY; ++m) Ts[m * K + col] = w[kidx<N, K>(m)];
+    for (int m = 0; m < D::KY; ++m) Tnext[tofs<N, K, C, CL>(b, cc, x, m * K + col)] = w[kidx<N, K>(m)];
+  }
+}
+
+// Inference, layer 0 at C = 16: the forward slab pass of the lifted input
+// u0[c] = Wl[c] F~ + bl[c] of slab x of every channel of cell b (grid (x, b),
+// C N threads; thread (c, i): the z line y = i of channel c), into the
+// channel-last T
+template <int N, int K, int C>
+__global__ __launch_bounds__(C * N) void k_fno_lift_slab(LiftIn lift, cx<float>* __restrict__ T) {
+  using D = FnoDims<N, K>;
+  constexpr int NT = C * N;
+  constexpr int CS = N * (K + 1) + 1;   // odd channel stride, as in the layer kernel
+  __shared__ cx<float> lds[C * CS];
+  const int x = blockIdx.x;
+  const int64_t b = blockIdx.y;
+  const int c = threadIdx.x / N, i = threadIdx.x % N;
+  const float* fs = lift.Fin + b * D::n + ((int64_t)x * N + i) * N;
+  const float w = lift.Wl[c], c0 = lift.bl[c];
+  cx<float> v[N];
+#pragma unroll
+  for (int z = 0; z < N; ++z) v[z] = {w * fs[z] + c0, 0.f};
+  fft_line<N, -1>(v);
+#pragma unroll
+  for (int kz = 0; kz < K; ++kz) lds[c * CS + i * (K + 1) + kz] = v[kz];
+  __syncthreads();
+  for (int t = threadIdx.x; t < C * K; t += NT) {   // (channel, kz column) items
+    const int cc = t % C, col = t / C;
+    cx<float> u[N];
+#pragma unroll
+    for (int y = 0; y < N; ++y) u[y] = lds[cc * CS + y * (K + 1) + col];
+    fft_line<N, -1>(u);
+#pragma unroll
+    for (int m = 0; m < D::KY; ++m) T[tofs<N, K, C, true>(b, cc, x, m * K + col)] = u[kidx<N, K>(m)];
   }
 }
 
@@ -980,19 +1019,16 @@ struct FnoOps {
                        dim3(256), 0, st, T, Uh);
     return hipGetLastError();
   }
-  static hipError_t fwd_slab_pass(const float* u, int nsc, cx<float>* T, hipStream_t st,
-                                  LiftIn lift = LiftIn()) {
-    const int64_t nslab = (int64_t)nsc * N;
-    constexpr int SB = slabs_per_block<N>();
-    hipLaunchKernelGGL((k_fno_fwd_slab<N, K>), dim3((unsigned)((nslab + SB - 1) / SB)), dim3(256),
-                       0, st, u, T, nslab, lift, C);
+  // inference at C = 16 (channel-last T): the lifted input's forward slab
+  // pass, and the x transforms with the mode mixing, fused
+  static hipError_t lift_slab_cl(const LiftIn& lift, int B, cx<float>* T, hipStream_t st) {
+    hipLaunchKernelGGL((k_fno_lift_slab<N, K, C>), dim3(N, (unsigned)B), dim3(C * N), 0, st, lift,
+                       T);
     return hipGetLastError();
   }
-  // x transform, mode mixing and inverse x transform of B cells, in place in T
-  static hipError_t xmix(cx<float>* T, int B, const cx<float>* R, float scale, hipStream_t st) {
-    constexpr int TP = 128 / C;
-    hipLaunchKernelGGL((k_fno_xmix<N, K, C>), dim3((D::PEN + TP - 1) / TP, (unsigned)((B + 1) / 2)),
-                       dim3(256), 0, st, T, B, R, scale);
+  static hipError_t xmix_cl(cx<float>* T, int B, const cx<float>* R, float scale, hipStream_t st) {
+    hipLaunchKernelGGL((k_fno_xmix16<N, K>), dim3(D::PEN, (unsigned)((B + 15) / 16)), dim3(256), 0,
+                       st, T, B, R, scale);
     return hipGetLastError();
   }
   static hipError_t fwd_x_pass(const cx<float>* T, int nsc, cx<float>* Uh, hipStream_t st) {
@@ -1043,25 +1079,39 @@ static hipError_t fno_forward_t(const FnoArgs& a, hipStream_t st) {
     const LiftIn li = l == 0 ? lift : LiftIn();
     const bool last = l + 1 == a.L;
     // the slab pass of layers l > 0 ran in the previous layer's last kernel.
-    // Training stores the kept modes Uh for the weight gradient: separate x
-    // passes and mixing on the matrix cores; inference runs them fused
+    // Inference at C = 16 runs the x transforms and the mixing fused on the
+    // channel-last T; training, which stores the kept modes Uh for the weight
+    // gradient, and the other channel counts run them as separate kernels on
+    // the channel-first T
+    float* hl = keep ? a.h[l] : nullptr;
+    float* uo = keep || !last ? a.u[l + 1] : nullptr;
+    float* yo = last ? a.y : nullptr;
+    cx<float>* Tn = last ? nullptr : a.T;
     hipError_t e = hipSuccess;
-    if (keep) {
+    bool fused = false;
+    if constexpr (C == 16) {
+      if (!keep) {
+        e = l == 0 ? O::lift_slab_cl(li, B, a.T, st) : hipSuccess;
+        if (e != hipSuccess) return e;
+        e = O::xmix_cl(a.T, B, a.R[l], 1.f / (float)n, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_fno_inv_slab_pointwise<N, K, C, true>), dim3(N, (unsigned)B),
+                           dim3(C * N), 0, st, a.T, a.u[l], li, a.W[l], a.bias[l], last ? 0 : 1,
+                           hl, uo, a.Wp, a.bp, yo, Tn);
+        fused = true;
+      }
+    }
+    if (!fused) {
       e = l == 0 ? O::fwd_transform(a.u[l], B * C, a.T, a.Uh[l], st, li)
                  : O::fwd_x_pass(a.T, B * C, a.Uh[l], st);
       if (e != hipSuccess) return e;
       launch_mix<C>(a.R[l], a.Uh[l], B, D::NM, 0, 1.f / (float)n, a.V, st);
       e = O::inv_x_pass(a.V, B * C, a.T, st);
-    } else {
-      e = l == 0 ? O::fwd_slab_pass(a.u[l], B * C, a.T, st, li) : hipSuccess;
       if (e != hipSuccess) return e;
-      e = O::xmix(a.T, B, a.R[l], 1.f / (float)n, st);
+      hipLaunchKernelGGL((k_fno_inv_slab_pointwise<N, K, C, false>), dim3(N, (unsigned)B),
+                         dim3(C * N), 0, st, a.T, a.u[l], li, a.W[l], a.bias[l], last ? 0 : 1, hl,
+                         uo, a.Wp, a.bp, yo, Tn);
     }
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fno_inv_slab_pointwise<N, K, C>), dim3(N, (unsigned)B), dim3(C * N), 0,
-                       st, a.T, a.u[l], li, a.W[l], a.bias[l], last ? 0 : 1,
-                       keep ? a.h[l] : nullptr, keep || !last ? a.u[l + 1] : nullptr, a.Wp, a.bp,
-                       last ? a.y : nullptr, last ? nullptr : a.T);
   }
   return hipGetLastError();
 }
