@@ -774,6 +774,54 @@ __global__ __launch_bounds__(256) void k_fno_pointwise_bwd(const float* __restri
   }
 }
 
+// The same at C = 16 with du_in = W^T dh on the matrix cores: one wave per 64
+// points (grid B n / 256 blocks of four waves); lane (r, q) forms dh of
+// channels 4 q .. 4 q + 3 at the four contiguous points 4 r .. 4 r + 3 (16-byte
+// loads and stores), which are the B operand of four 16 x 16 x 16 products
+// (tile t: points 4 r + t; A = W^T, lane (r, q) supplying W[4 q + j][r] at K
+// step j), and ends with du_in of channels 4 q .. 4 q + 3 of the same points.
+__global__ __launch_bounds__(256) void k_fno_pointwise_bwd16(const float* __restrict__ duo,
+                                                             const float* __restrict__ h, int n,
+                                                             const float* __restrict__ W, int act,
+                                                             float* __restrict__ dh,
+                                                             float* __restrict__ dui) {
+  constexpr int C = 16;
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, q = lane >> 4;
+  const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64 + 4 * r;   // 64 | n
+  const int64_t b = p / n, rr = p % n;
+  float wa[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) wa[j] = W[(4 * q + j) * C + r];
+  v4f g[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t o = (b * C + 4 * q + j) * n + rr;
+    const v4f d = *reinterpret_cast<const v4f*>(duo + o);
+    if (act) {
+      const v4f hv = *reinterpret_cast<const v4f*>(h + o);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) g[j][t] = d[t] * gelu_d(hv[t]);
+    } else {
+      g[j] = d;
+    }
+    *reinterpret_cast<v4f*>(dh + o) = g[j];
+  }
+  v4f acc[4];   // tile t: acc[t][v] = du_in of channel 4 q + v at point 4 r + t
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[j], g[j][t], acc[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    *reinterpret_cast<v4f*>(dui + (b * C + 4 * q + v) * n + rr) =
+        v4f{acc[0][v], acc[1][v], acc[2][v], acc[3][v]};
+}
+
 // Partial sums for the dense parameter gradients (fixed order, deterministic):
 //   mode 0 (layer):  out[o*C+i] = sum dh[o] u[i], out[C*C + o] = sum dh[o]
 //   mode 1 (lift):   out[c] = sum du0[c] Fin, out[C + c] = sum du0[c]
@@ -878,6 +926,51 @@ __global__ __launch_bounds__(256) void k_fno_dense_partial(int mode, const float
   for (int k = 0; k < 2; ++k) {
     const int v = threadIdx.x + 256 * k;
     if (v < nvals) part[(int64_t)blockIdx.x * NV + v] = (float)acc[k];
+  }
+}
+
+// Mode 0 at C = 16 on the matrix cores: out[o][i] = sum dh[o] u[i] as 16 x 16
+// x 4 products over the block's points (operand layout as in the mode
+// mixing: lane (r, q) loads points 4 q .. 4 q + 3 of a 16-point group of row r
+// of dh and of u, one 16-byte load each, and K step s takes point 4 q + s;
+// wave w takes the groups w, w + 4, ...), FP32 sums over a wave's points and
+// FP64 over the block's four waves; out[C C + o] = sum dh[o] from the same
+// loads.  part[block][v] as k_fno_dense_partial.
+__global__ __launch_bounds__(256) void k_fno_dense_mfma16(const float* __restrict__ a,
+                                                          const float* __restrict__ g, int n,
+                                                          int npb, int64_t total,
+                                                          float* __restrict__ part) {
+  constexpr int C = 16, NV = C * C + C;
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  __shared__ float red[4][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const int64_t p0 = (int64_t)blockIdx.x * npb;
+  const int64_t p1 = min(p0 + (int64_t)npb, total);
+  const int ng = p1 > p0 ? (int)((p1 - p0) / 16) : 0;   // 16 divides npb and n
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+  float bs = 0.f;
+  for (int gi = wv; gi < ng; gi += 4) {   // uniform per wave
+    const int64_t pt = p0 + 16 * gi + 4 * q;
+    const int64_t b = pt / n, rr = pt % n;
+    const v4f gv = *reinterpret_cast<const v4f*>(g + (b * C + r) * n + rr);
+    const v4f av = *reinterpret_cast<const v4f*>(a + (b * C + r) * n + rr);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[k], av[k], acc, 0, 0, 0);
+    bs += (gv[0] + gv[1]) + (gv[2] + gv[3]);
+  }
+  // lane (r, q): acc[v] = out[4 q + v][r]; bs: row r over the lane's points
+  bs += __shfl_xor(bs, 16);
+  bs += __shfl_xor(bs, 32);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wv][(4 * q + v) * C + r] = acc[v];
+  if (q == 0) red[wv][C * C + r] = bs;
+  __syncthreads();
+  for (int v = threadIdx.x; v < NV; v += 256) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) sum += (double)red[w][v];
+    part[(int64_t)blockIdx.x * NV + v] = (float)sum;
   }
 }
 
@@ -1123,8 +1216,18 @@ static hipError_t dense_grad(int mode, const float* act, const float* g, int B, 
   // points per block: a whole number of tiles
   const int64_t per = (total + part_blocks - 1) / part_blocks;
   const int npb = (int)((per + DG_TILE - 1) / DG_TILE * DG_TILE);
-  hipLaunchKernelGGL((k_fno_dense_partial<C>), dim3(part_blocks), dim3(256), 0, st, mode, act, g,
-                     B, n, npb, part);
+  bool done = false;
+  if constexpr (C == 16) {
+    if (mode == 0) {   // the layers' weight gradients, on the matrix cores
+      hipLaunchKernelGGL(k_fno_dense_mfma16, dim3(part_blocks), dim3(256), 0, st, act, g, n, npb,
+                         total, part);
+      done = true;
+    }
+  }
+  if (!done) {
+    hipLaunchKernelGGL((k_fno_dense_partial<C>), dim3(part_blocks), dim3(256), 0, st, mode, act,
+                       g, B, n, npb, part);
+  }
   const int nvals = mode == 0 ? C * C + C : (mode == 1 ? 2 * C : C + 1);
   hipLaunchKernelGGL((k_fno_dense_final<C>), dim3(nvals), dim3(256), 0, st, part, part_blocks,
                      out);
@@ -1155,8 +1258,13 @@ static hipError_t fno_backward_t(const FnoArgs& args, hipStream_t st) {
   hipLaunchKernelGGL((k_fno_proj_bwd<C>), dim3(gb), dim3(256), 0, st, a.dy, B, n, a.Wp, a.du);
   for (int l = a.L - 1; l >= 0; --l) {
     // dh (into a.dh), pointwise part of du_in (into a.du2)
-    hipLaunchKernelGGL((k_fno_pointwise_bwd<C>), dim3(gb), dim3(256), 0, st, a.du, a.h[l], B, n,
-                       a.W[l], l + 1 < a.L ? 1 : 0, a.dh, a.du2);
+    if constexpr (C == 16) {
+      hipLaunchKernelGGL(k_fno_pointwise_bwd16, dim3((unsigned)(bn / 256)), dim3(256), 0, st, a.du,
+                         a.h[l], n, a.W[l], l + 1 < a.L ? 1 : 0, a.dh, a.du2);
+    } else {
+      hipLaunchKernelGGL((k_fno_pointwise_bwd<C>), dim3(gb), dim3(256), 0, st, a.du, a.h[l], B,
+                         n, a.W[l], l + 1 < a.L ? 1 : 0, a.dh, a.du2);
+    }
     e = dense_grad<C>(0, a.u[l], a.dh, B, n, a.part, a.part_blocks, a.gW[l], st);
     if (e != hipSuccess) return e;
     // spectral part: Gv = truncated DFT(dh); dR = sum_b Gv conj(Uh); Gu = conj(R)^T Gv
