@@ -18,7 +18,11 @@
 // truncated DFT of the output gradient.  Every truncated transform is a
 // pruned 3D FFT: forward = z lines of the slab (keep kz < K) -> y lines of the
 // kept kz (keep 2K ky) -> x lines of the 2K x K kept (ky, kz) pencils (keep
-// 2K kx); inverse = the same passes backwards with zero padding.
+// 2K kx); inverse = the same passes backwards with zero padding.  Inference at
+// C = 16 keeps the slab passes' output channel-last and runs the x lines and
+// the mode mixing as one kernel (k_fno_xmix16); training and the other channel
+// counts keep it channel-first, with separate x passes and mixing, since the
+// weight gradient needs the kept modes in device memory anyway.
 #include <hip/hip_runtime.h>
 
 #include "fft.h"
