@@ -655,35 +655,45 @@ __global__ __launch_bounds__(C * N) void k_fno_inv_slab_pointwise(
 }
 
 // Inference, layer 0 at C = 16: the forward slab pass of the lifted input
-// u0[c] = Wl[c] F~ + bl[c] of slab x of every channel of cell b (grid (x, b),
-// C N threads; thread (c, i): the z line y = i of channel c), into the
-// channel-last T
+// u0[c] = Wl[c] F~ + bl[c] of slab x of every channel of cell b, into the
+// channel-last T (grid (x, b), 256 threads).  The pass is linear, so it is
+// taken once, of F~ (wave 0: the z lines, then the y lines of the kept kz),
+// and each channel's spectrum is Wl[c] S + bl[c] N^2 at ky = kz = 0 (the
+// constant's unnormalised transform), written by every thread.
 template <int N, int K, int C>
-__global__ __launch_bounds__(C * N) void k_fno_lift_slab(LiftIn lift, cx<float>* __restrict__ T) {
+__global__ __launch_bounds__(256) void k_fno_lift_slab(LiftIn lift, cx<float>* __restrict__ T) {
   using D = FnoDims<N, K>;
-  constexpr int NT = C * N;
-  constexpr int CS = N * (K + 1) + 1;   // odd channel stride, as in the layer kernel
-  __shared__ cx<float> lds[C * CS];
+  static_assert(N <= 64 && K <= 64, "one wave transforms the slab");
+  __shared__ cx<float> lds[N][K + 1];
+  __shared__ cx<float> S[D::PEN];
   const int x = blockIdx.x;
   const int64_t b = blockIdx.y;
-  const int c = threadIdx.x / N, i = threadIdx.x % N;
-  const float* fs = lift.Fin + b * D::n + ((int64_t)x * N + i) * N;
-  const float w = lift.Wl[c], c0 = lift.bl[c];
-  cx<float> v[N];
+  const int t = threadIdx.x;
+  if (t < N) {   // z line y = t
+    const float* fs = lift.Fin + b * D::n + ((int64_t)x * N + t) * N;
+    cx<float> v[N];
 #pragma unroll
-  for (int z = 0; z < N; ++z) v[z] = {w * fs[z] + c0, 0.f};
-  fft_line<N, -1>(v);
+    for (int z = 0; z < N; ++z) v[z] = {fs[z], 0.f};
+    fft_line<N, -1>(v);
 #pragma unroll
-  for (int kz = 0; kz < K; ++kz) lds[c * CS + i * (K + 1) + kz] = v[kz];
+    for (int kz = 0; kz < K; ++kz) lds[t][kz] = v[kz];
+  }
   __syncthreads();
-  for (int t = threadIdx.x; t < C * K; t += NT) {   // (channel, kz column) items
-    const int cc = t % C, col = t / C;
-    cx<float> u[N];
+  if (t < K) {   // y line of kz = t
+    cx<float> v[N];
 #pragma unroll
-    for (int y = 0; y < N; ++y) u[y] = lds[cc * CS + y * (K + 1) + col];
-    fft_line<N, -1>(u);
+    for (int y = 0; y < N; ++y) v[y] = lds[y][t];
+    fft_line<N, -1>(v);
 #pragma unroll
-    for (int m = 0; m < D::KY; ++m) T[tofs<N, K, C, true>(b, cc, x, m * K + col)] = u[kidx<N, K>(m)];
+    for (int m = 0; m < D::KY; ++m) S[m * K + t] = v[kidx<N, K>(m)];
+  }
+  __syncthreads();
+  cx<float>* Ts = T + tofs<N, K, C, true>(b, 0, x, 0);   // PEN x C contiguous values
+  for (int e = t; e < D::PEN * C; e += 256) {
+    const int c = e % C, pen = e / C;
+    const cx<float> sv = S[pen];
+    const float w = lift.Wl[c];
+    Ts[e] = {fmaf(w, sv.x, pen == 0 ? lift.bl[c] * (float)(N * N) : 0.f), w * sv.y};
   }
 }
 
@@ -1119,8 +1129,7 @@ struct FnoOps {
   // inference at C = 16 (channel-last T): the lifted input's forward slab
   // pass, and the x transforms with the mode mixing, fused
   static hipError_t lift_slab_cl(const LiftIn& lift, int B, cx<float>* T, hipStream_t st) {
-    hipLaunchKernelGGL((k_fno_lift_slab<N, K, C>), dim3(N, (unsigned)B), dim3(C * N), 0, st, lift,
-                       T);
+    hipLaunchKernelGGL((k_fno_lift_slab<N, K, C>), dim3(N, (unsigned)B), dim3(256), 0, st, lift, T);
     return hipGetLastError();
   }
   static hipError_t xmix_cl(cx<float>* T, int B, const cx<float>* R, float scale, hipStream_t st) {
