@@ -213,13 +213,22 @@ __global__ __launch_bounds__(256) void k_fno_xmix16(cx<float>* T, int B,
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r = lane & 15, q = lane >> 4;
+  // this lane's weights of the wave's next mode are in flight during the current one
+  const cx<float>* Rl = R + (int64_t)pen * C * C + 4 * q * C + r;
+  constexpr int64_t KXS = (int64_t)D::PEN * C * C;   // kx -> kx + 1
+  cx<float> wn[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) wn[k] = Rl[wv * KXS + k * C];
   for (int mx = wv; mx < D::KY; mx += 4) {   // uniform per wave
-    const cx<float>* Rm = R + (int64_t)(mx * D::PEN + pen) * C * C;
     cx<float> w[4], xv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      w[k] = Rm[(4 * q + k) * C + r];
+      w[k] = wn[k];
       xv[k] = X[mx][r][4 * q + k];
+    }
+    if (mx + 4 < D::KY) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wn[k] = Rl[(mx + 4) * KXS + k * C];
     }
     v4f acc[2];
 #pragma unroll
