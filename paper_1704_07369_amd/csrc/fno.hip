@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_fno_xmix16(cx<float>* T, int B,
   const int b0 = blockIdx.y * CB;
   const int c = threadIdx.x % C, cl = threadIdx.x / C;
   const bool live = b0 + cl < B;
-  cx<float>* Tl = T + tofs<N, K, C, true>(b0 + cl, c, 0, pen);   // + x PEN C
+  cx<float>* Tl = T + tofs<N, K, C, true>(live ? b0 + cl : b0, c, 0, pen);   // + x PEN C
   constexpr int64_t XS = (int64_t)D::PEN * C;
   {
     cx<float> v[N];
@@ -1281,6 +1281,7 @@ static hipError_t fno_backward_t(const FnoArgs& args, hipStream_t st) {
   for (int l = a.L - 1; l >= 0; --l) {
     // dh (into a.dh), pointwise part of du_in (into a.du2)
     if constexpr (C == 16) {
+      static_assert(D::n % 256 == 0, "one wave per 64 points of a cell");
       hipLaunchKernelGGL(k_fno_pointwise_bwd16, dim3((unsigned)(bn / 256)), dim3(256), 0, st, a.du,
                          a.h[l], n, a.W[l], l + 1 < a.L ? 1 : 0, a.dh, a.du2);
     } else {
